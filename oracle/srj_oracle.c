@@ -1,0 +1,293 @@
+/*
+ * CPU oracle for the Scheduled Relaxation Jacobi (SRJ) hot path -- TEST INFRASTRUCTURE.
+ *
+ * Plain, slow, obviously correct loops.  Only the test-suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library; the product path never does.
+ * It shares no code with the HIP library.
+ *
+ * Discretisation (paper Sec. 3.1, Eq. 2nd-order_CD, written for the Poisson problem
+ * of Sec. 5.1 with the sign convention -lap(u) = f):
+ *   grid of n_i interior points per dimension, spacing h, ring of Dirichlet values;
+ *   b = (h*h) * f ;  weighted Jacobi step with weight w, c = w / (2d):
+ *     s  = (W + E) + (S + N)            [ + (D + U) in 3D ]
+ *     t  = (s + b) - (2d) * u           (t is the residual b - A u of the input state)
+ *     u' = u + c * t
+ *   The association above is fixed; the file is compiled with -ffp-contract=off so no
+ *   multiply-add is fused.
+ *
+ * Layout: row-major, x fastest.  2D: (ny+2) rows of (nx+2); 3D: (nz+2) planes of
+ * (ny+2) rows of (nx+2).  Index 0 and n+1 of every dimension is the Dirichlet ring.
+ */
+#include <stdint.h>
+#include <string.h>
+#include <math.h>
+
+#define I2(i, j) ((size_t)(i) * (size_t)(nx + 2) + (size_t)(j))
+#define I3(k, i, j) (((size_t)(k) * (size_t)(ny + 2) + (size_t)(i)) * (size_t)(nx + 2) + (size_t)(j))
+
+/* ---------------------------------------------------------------- FP64 sweeps */
+
+/* One weighted-Jacobi step, 2D 5-point (Eq. 2nd-order_CD).  out's ring is not touched. */
+void or_sweep2d(int64_t nx, int64_t ny, const double* u, const double* b, double c, double* out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 1; i <= ny; ++i) {
+        for (int64_t j = 1; j <= nx; ++j) {
+            double s = (u[I2(i, j - 1)] + u[I2(i, j + 1)]) + (u[I2(i - 1, j)] + u[I2(i + 1, j)]);
+            double t = (s + b[I2(i, j)]) - 4.0 * u[I2(i, j)];
+            out[I2(i, j)] = u[I2(i, j)] + c * t;
+        }
+    }
+}
+
+/* One weighted-Jacobi step, 3D 7-point (Eq. 2nd-order_CD extended to d = 3, Sec. 3.1). */
+void or_sweep3d(int64_t nx, int64_t ny, int64_t nz, const double* u, const double* b, double c,
+                double* out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 1; k <= nz; ++k) {
+        for (int64_t i = 1; i <= ny; ++i) {
+            for (int64_t j = 1; j <= nx; ++j) {
+                double s = ((u[I3(k, i, j - 1)] + u[I3(k, i, j + 1)]) +
+                            (u[I3(k, i - 1, j)] + u[I3(k, i + 1, j)])) +
+                           (u[I3(k - 1, i, j)] + u[I3(k + 1, i, j)]);
+                double t = (s + b[I3(k, i, j)]) - 6.0 * u[I3(k, i, j)];
+                out[I3(k, i, j)] = u[I3(k, i, j)] + c * t;
+            }
+        }
+    }
+}
+
+/* Plain Jacobi written from its own definition: u' = (sum of neighbours + b) / (2d).
+ * Kept separate from the weighted step so that "w = 1 is Jacobi" is a real check. */
+void or_jacobi2d(int64_t nx, int64_t ny, const double* u, const double* b, double* out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 1; i <= ny; ++i)
+        for (int64_t j = 1; j <= nx; ++j)
+            out[I2(i, j)] = (u[I2(i, j - 1)] + u[I2(i, j + 1)] + u[I2(i - 1, j)] + u[I2(i + 1, j)] +
+                             b[I2(i, j)]) / 4.0;
+}
+
+void or_jacobi3d(int64_t nx, int64_t ny, int64_t nz, const double* u, const double* b, double* out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 1; k <= nz; ++k)
+        for (int64_t i = 1; i <= ny; ++i)
+            for (int64_t j = 1; j <= nx; ++j)
+                out[I3(k, i, j)] = (u[I3(k, i, j - 1)] + u[I3(k, i, j + 1)] + u[I3(k, i - 1, j)] +
+                                    u[I3(k, i + 1, j)] + u[I3(k - 1, i, j)] + u[I3(k + 1, i, j)] +
+                                    b[I3(k, i, j)]) / 6.0;
+}
+
+/* Run `nsweeps` scheduled steps: step s uses c_seq[(k0 + s) mod M] (Sec. 2: the M-cycle
+ * repeated).  u holds the start state and receives the result; work is a second array of
+ * the same shape whose ring already equals u's ring. */
+void or_srj2d(int64_t nx, int64_t ny, double* u, const double* b, const double* c_seq, int64_t M,
+              int64_t k0, int64_t nsweeps, double* work)
+{
+    double* cur = u;
+    double* nxt = work;
+    for (int64_t s = 0; s < nsweeps; ++s) {
+        or_sweep2d(nx, ny, cur, b, c_seq[(k0 + s) % M], nxt);
+        double* t = cur; cur = nxt; nxt = t;
+    }
+    if (cur != u) memcpy(u, cur, sizeof(double) * (size_t)(nx + 2) * (size_t)(ny + 2));
+}
+
+void or_srj3d(int64_t nx, int64_t ny, int64_t nz, double* u, const double* b, const double* c_seq,
+              int64_t M, int64_t k0, int64_t nsweeps, double* work)
+{
+    double* cur = u;
+    double* nxt = work;
+    for (int64_t s = 0; s < nsweeps; ++s) {
+        or_sweep3d(nx, ny, nz, cur, b, c_seq[(k0 + s) % M], nxt);
+        double* t = cur; cur = nxt; nxt = t;
+    }
+    if (cur != u)
+        memcpy(u, cur, sizeof(double) * (size_t)(nx + 2) * (size_t)(ny + 2) * (size_t)(nz + 2));
+}
+
+/* ------------------------------------------------------------ residual norms */
+
+/* Compensated (Kahan) accumulation, row by row, then over rows in order. */
+typedef struct { double s, c; } kahan_t;
+static inline void kadd(kahan_t* k, double x)
+{
+    double y = x - k->c;
+    double t = k->s + y;
+    k->c = (t - k->s) - y;
+    k->s = t;
+}
+
+/* r = b - A u = (s + b) - 2d u on the interior.  out[0] = sum r^2, out[1] = max |r|. */
+void or_residual2d(int64_t nx, int64_t ny, const double* u, const double* b, double* out,
+                   double* rowsum, double* rowmax)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 1; i <= ny; ++i) {
+        kahan_t acc = {0.0, 0.0};
+        double m = 0.0;
+        for (int64_t j = 1; j <= nx; ++j) {
+            double s = (u[I2(i, j - 1)] + u[I2(i, j + 1)]) + (u[I2(i - 1, j)] + u[I2(i + 1, j)]);
+            double r = (s + b[I2(i, j)]) - 4.0 * u[I2(i, j)];
+            kadd(&acc, r * r);
+            double a = fabs(r);
+            if (a > m || a != a) m = a;
+        }
+        rowsum[i - 1] = acc.s;
+        rowmax[i - 1] = m;
+    }
+    kahan_t tot = {0.0, 0.0};
+    double m = 0.0;
+    for (int64_t i = 0; i < ny; ++i) {
+        kadd(&tot, rowsum[i]);
+        if (rowmax[i] > m || rowmax[i] != rowmax[i]) m = rowmax[i];
+    }
+    out[0] = tot.s;
+    out[1] = m;
+}
+
+void or_residual3d(int64_t nx, int64_t ny, int64_t nz, const double* u, const double* b, double* out,
+                   double* rowsum, double* rowmax)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 1; k <= nz; ++k) {
+        for (int64_t i = 1; i <= ny; ++i) {
+            kahan_t acc = {0.0, 0.0};
+            double m = 0.0;
+            for (int64_t j = 1; j <= nx; ++j) {
+                double s = ((u[I3(k, i, j - 1)] + u[I3(k, i, j + 1)]) +
+                            (u[I3(k, i - 1, j)] + u[I3(k, i + 1, j)])) +
+                           (u[I3(k - 1, i, j)] + u[I3(k + 1, i, j)]);
+                double r = (s + b[I3(k, i, j)]) - 6.0 * u[I3(k, i, j)];
+                kadd(&acc, r * r);
+                double a = fabs(r);
+                if (a > m || a != a) m = a;
+            }
+            rowsum[(k - 1) * ny + (i - 1)] = acc.s;
+            rowmax[(k - 1) * ny + (i - 1)] = m;
+        }
+    }
+    kahan_t tot = {0.0, 0.0};
+    double m = 0.0;
+    for (int64_t i = 0; i < ny * nz; ++i) {
+        kadd(&tot, rowsum[i]);
+        if (rowmax[i] > m || rowmax[i] != rowmax[i]) m = rowmax[i];
+    }
+    out[0] = tot.s;
+    out[1] = m;
+}
+
+/* r written out (interior; ring set to 0). */
+void or_residual_field2d(int64_t nx, int64_t ny, const double* u, const double* b, double* r)
+{
+    memset(r, 0, sizeof(double) * (size_t)(nx + 2) * (size_t)(ny + 2));
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 1; i <= ny; ++i)
+        for (int64_t j = 1; j <= nx; ++j) {
+            double s = (u[I2(i, j - 1)] + u[I2(i, j + 1)]) + (u[I2(i - 1, j)] + u[I2(i + 1, j)]);
+            r[I2(i, j)] = (s + b[I2(i, j)]) - 4.0 * u[I2(i, j)];
+        }
+}
+
+void or_residual_field3d(int64_t nx, int64_t ny, int64_t nz, const double* u, const double* b,
+                         double* r)
+{
+    memset(r, 0, sizeof(double) * (size_t)(nx + 2) * (size_t)(ny + 2) * (size_t)(nz + 2));
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 1; k <= nz; ++k)
+        for (int64_t i = 1; i <= ny; ++i)
+            for (int64_t j = 1; j <= nx; ++j) {
+                double s = ((u[I3(k, i, j - 1)] + u[I3(k, i, j + 1)]) +
+                            (u[I3(k, i - 1, j)] + u[I3(k, i + 1, j)])) +
+                           (u[I3(k - 1, i, j)] + u[I3(k + 1, i, j)]);
+                r[I3(k, i, j)] = (s + b[I3(k, i, j)]) - 6.0 * u[I3(k, i, j)];
+            }
+}
+
+/* ------------------------------------------------- reduced-precision sweeps */
+/* Same association, evaluated in binary32.  c32 is the binary32 rounding of c. */
+
+void or_sweep2d_f32(int64_t nx, int64_t ny, const float* u, const float* b, float c, float* out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 1; i <= ny; ++i)
+        for (int64_t j = 1; j <= nx; ++j) {
+            float s = (u[I2(i, j - 1)] + u[I2(i, j + 1)]) + (u[I2(i - 1, j)] + u[I2(i + 1, j)]);
+            float t = (s + b[I2(i, j)]) - 4.0f * u[I2(i, j)];
+            out[I2(i, j)] = u[I2(i, j)] + c * t;
+        }
+}
+
+void or_sweep3d_f32(int64_t nx, int64_t ny, int64_t nz, const float* u, const float* b, float c,
+                    float* out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 1; k <= nz; ++k)
+        for (int64_t i = 1; i <= ny; ++i)
+            for (int64_t j = 1; j <= nx; ++j) {
+                float s = ((u[I3(k, i, j - 1)] + u[I3(k, i, j + 1)]) +
+                           (u[I3(k, i - 1, j)] + u[I3(k, i + 1, j)])) +
+                          (u[I3(k - 1, i, j)] + u[I3(k + 1, i, j)]);
+                float t = (s + b[I3(k, i, j)]) - 6.0f * u[I3(k, i, j)];
+                out[I3(k, i, j)] = u[I3(k, i, j)] + c * t;
+            }
+}
+
+/* bfloat16 storage: the upper 16 bits of a binary32; widening is exact, narrowing rounds
+ * to nearest, ties to even (quiet NaN kept quiet). */
+static inline float bf_load(uint16_t h)
+{
+    uint32_t x = (uint32_t)h << 16;
+    float f;
+    memcpy(&f, &x, 4);
+    return f;
+}
+static inline uint16_t bf_store(float f)
+{
+    uint32_t x;
+    memcpy(&x, &f, 4);
+    if ((x & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((x >> 16) | 0x40u);
+    x += 0x7fffu + ((x >> 16) & 1u);
+    return (uint16_t)(x >> 16);
+}
+
+void or_f32_to_bf16(int64_t n, const float* in, uint16_t* out)
+{
+    for (int64_t i = 0; i < n; ++i) out[i] = bf_store(in[i]);
+}
+void or_bf16_to_f32(int64_t n, const uint16_t* in, float* out)
+{
+    for (int64_t i = 0; i < n; ++i) out[i] = bf_load(in[i]);
+}
+
+void or_sweep2d_bf16(int64_t nx, int64_t ny, const uint16_t* u, const uint16_t* b, float c,
+                     uint16_t* out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 1; i <= ny; ++i)
+        for (int64_t j = 1; j <= nx; ++j) {
+            float s = (bf_load(u[I2(i, j - 1)]) + bf_load(u[I2(i, j + 1)])) +
+                      (bf_load(u[I2(i - 1, j)]) + bf_load(u[I2(i + 1, j)]));
+            float uc = bf_load(u[I2(i, j)]);
+            float t = (s + bf_load(b[I2(i, j)])) - 4.0f * uc;
+            out[I2(i, j)] = bf_store(uc + c * t);
+        }
+}
+
+void or_sweep3d_bf16(int64_t nx, int64_t ny, int64_t nz, const uint16_t* u, const uint16_t* b,
+                     float c, uint16_t* out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 1; k <= nz; ++k)
+        for (int64_t i = 1; i <= ny; ++i)
+            for (int64_t j = 1; j <= nx; ++j) {
+                float s = ((bf_load(u[I3(k, i, j - 1)]) + bf_load(u[I3(k, i, j + 1)])) +
+                           (bf_load(u[I3(k, i - 1, j)]) + bf_load(u[I3(k, i + 1, j)]))) +
+                          (bf_load(u[I3(k - 1, i, j)]) + bf_load(u[I3(k + 1, i, j)]));
+                float uc = bf_load(u[I3(k, i, j)]);
+                float t = (s + bf_load(b[I3(k, i, j)])) - 6.0f * uc;
+                out[I3(k, i, j)] = bf_store(uc + c * t);
+            }
+}

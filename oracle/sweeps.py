@@ -1,0 +1,266 @@
+"""Weighted-Jacobi sweeps, SRJ cycles, residuals and the stopping rule -- oracle side.
+
+Test infrastructure only (see ``oracle/__init__``).  Arrays are numpy, C-contiguous,
+shape ``(n_y + 2, n_x + 2)`` in 2D or ``(n_z + 2, n_y + 2, n_x + 2)`` in 3D; index 0 and
+``n + 1`` of each axis is the Dirichlet ring.  Axis ``-1`` (x) is the fastest.
+
+Paper passages followed:
+* one step omega_i J -- Sec. 3.1, Eq. 2nd-order_CD (Poisson form, -lap u = f, b = h^2 f);
+* the M-cycle, weight i applied q_i times, cycles repeated -- Sec. 2;
+* the residual used to stop: r = b - A u with A = 2d I - (sum of neighbours) in units
+  of h^2; relres = ||r||_2 / ||b~||_2 with b~ the residual of the zero interior (source
+  plus boundary terms).  The paper's own stopping figure ||u^n - u^(n-1)||_inf
+  (Sec. 4.1, footnote on the tolerance) is reported beside it.
+"""
+import ctypes
+
+import numpy as np
+
+from ._clib import lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _dims(u):
+    if u.ndim == 2:
+        return (u.shape[1] - 2, u.shape[0] - 2)
+    if u.ndim == 3:
+        return (u.shape[2] - 2, u.shape[1] - 2, u.shape[0] - 2)
+    raise ValueError("2D or 3D arrays only")
+
+
+def _c64(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a
+
+
+def rhs(f, h):
+    """b = (h*h) * f on the interior, 0 on the ring (h*h is rounded once, then the product)."""
+    f = _c64(f)
+    hh = float(h) * float(h)
+    b = np.zeros_like(f)
+    inner = tuple(slice(1, -1) for _ in range(f.ndim))
+    b[inner] = hh * f[inner]
+    return b
+
+
+def sweep(u, b, c):
+    """One weighted-Jacobi step with coefficient c = omega / (2d)  (Eq. 2nd-order_CD)."""
+    u = _c64(u)
+    b = _c64(b)
+    out = u.copy()
+    L = lib()
+    d = _dims(u)
+    if u.ndim == 2:
+        L.or_sweep2d(d[0], d[1], _p(u), _p(b), float(c), _p(out))
+    else:
+        L.or_sweep3d(d[0], d[1], d[2], _p(u), _p(b), float(c), _p(out))
+    return out
+
+
+def jacobi(u, b):
+    """One plain Jacobi step from its own definition, u' = (sum of neighbours + b) / (2d)."""
+    u = _c64(u)
+    b = _c64(b)
+    out = u.copy()
+    L = lib()
+    d = _dims(u)
+    if u.ndim == 2:
+        L.or_jacobi2d(d[0], d[1], _p(u), _p(b), _p(out))
+    else:
+        L.or_jacobi3d(d[0], d[1], d[2], _p(u), _p(b), _p(out))
+    return out
+
+
+def coefficients(omega_sequence, ndim):
+    """c_k = omega_k / (2d) for an ordered weight sequence (one IEEE division each)."""
+    w = np.asarray(omega_sequence, dtype=np.float64)
+    return w / float(2 * ndim)
+
+
+def run(u, b, c_seq, nsweeps, k0=0):
+    """Apply ``nsweeps`` scheduled steps; step s uses c_seq[(k0 + s) mod M] (Sec. 2)."""
+    u = _c64(u).copy()
+    b = _c64(b)
+    c_seq = np.ascontiguousarray(c_seq, dtype=np.float64)
+    work = u.copy()
+    L = lib()
+    d = _dims(u)
+    if u.ndim == 2:
+        L.or_srj2d(d[0], d[1], _p(u), _p(b), _p(c_seq), len(c_seq), int(k0), int(nsweeps), _p(work))
+    else:
+        L.or_srj3d(d[0], d[1], d[2], _p(u), _p(b), _p(c_seq), len(c_seq), int(k0), int(nsweeps),
+                   _p(work))
+    return u
+
+
+def residual_norms(u, b):
+    """(sum r^2, max |r|) of r = b - A u on the interior, compensated summation."""
+    u = _c64(u)
+    b = _c64(b)
+    L = lib()
+    d = _dims(u)
+    out = np.zeros(2)
+    if u.ndim == 2:
+        rs = np.zeros(d[1])
+        rm = np.zeros(d[1])
+        L.or_residual2d(d[0], d[1], _p(u), _p(b), _p(out), _p(rs), _p(rm))
+    else:
+        rs = np.zeros(d[1] * d[2])
+        rm = np.zeros(d[1] * d[2])
+        L.or_residual3d(d[0], d[1], d[2], _p(u), _p(b), _p(out), _p(rs), _p(rm))
+    return float(out[0]), float(out[1])
+
+
+def residual_field(u, b):
+    """r = b - A u on the interior, 0 on the ring."""
+    u = _c64(u)
+    b = _c64(b)
+    r = np.empty_like(u)
+    L = lib()
+    d = _dims(u)
+    if u.ndim == 2:
+        L.or_residual_field2d(d[0], d[1], _p(u), _p(b), _p(r))
+    else:
+        L.or_residual_field3d(d[0], d[1], d[2], _p(u), _p(b), _p(r))
+    return r
+
+
+def zero_interior(u):
+    z = np.array(u, dtype=np.float64, copy=True)
+    z[tuple(slice(1, -1) for _ in range(z.ndim))] = 0.0
+    return z
+
+
+def source_norm2(u, b):
+    """||b~||_2^2: the squared residual of the state whose interior is zero."""
+    return residual_norms(zero_interior(u), b)[0]
+
+
+def relres(u, b, bt2=None):
+    if bt2 is None:
+        bt2 = source_norm2(u, b)
+    r2, _ = residual_norms(u, b)
+    return float(np.sqrt(r2) / np.sqrt(bt2)) if bt2 > 0 else 0.0
+
+
+def solve(u0, f, h, omega_sequence, tol, max_sweeps, history=False):
+    """SRJ to a relative residual: checks at k = 0 and at every cycle end (k = 0 mod M).
+
+    Returns a dict with u, sweeps, relres, status ('ok' | 'noconv' | 'diverged') and, if
+    ``history``, the relres at every check.  Plain Jacobi is the one-weight schedule
+    [1.0] and is then checked after every sweep.
+    """
+    u = _c64(u0).copy()
+    b = rhs(f, h)
+    c_seq = coefficients(omega_sequence, u.ndim)
+    M = len(c_seq)
+    bt2 = source_norm2(u, b)
+    hist = []
+    if bt2 == 0.0:
+        # zero source and zero boundary: u = 0 is exact
+        u[tuple(slice(1, -1) for _ in range(u.ndim))] = 0.0
+        return dict(u=u, sweeps=0, relres=0.0, status="ok", history=hist)
+    k = 0
+    while True:
+        r2, _ = residual_norms(u, b)
+        rr = float(np.sqrt(r2) / np.sqrt(bt2))
+        if history:
+            hist.append(rr)
+        if not np.isfinite(rr):
+            return dict(u=u, sweeps=k, relres=rr, status="diverged", history=hist)
+        if rr <= tol:
+            return dict(u=u, sweeps=k, relres=rr, status="ok", history=hist)
+        if k + M > max_sweeps:
+            return dict(u=u, sweeps=k, relres=rr, status="noconv", history=hist)
+        u = run(u, b, c_seq, M, k0=0)
+        k += M
+
+
+# ----------------------------------------------------------- reduced precision
+
+def to_bf16_bits(x32):
+    """binary32 -> bfloat16 bit patterns, round to nearest, ties to even."""
+    x32 = np.ascontiguousarray(x32, dtype=np.float32)
+    out = np.empty(x32.shape, dtype=np.uint16)
+    lib().or_f32_to_bf16(x32.size, _p(x32), _p(out))
+    return out
+
+
+def from_bf16_bits(h):
+    h = np.ascontiguousarray(h, dtype=np.uint16)
+    out = np.empty(h.shape, dtype=np.float32)
+    lib().or_bf16_to_f32(h.size, _p(h), _p(out))
+    return out
+
+
+def sweep_lo(u, b, c32, fmt):
+    """One step in binary32 arithmetic; storage binary32 ('f32') or bfloat16 bits ('bf16')."""
+    L = lib()
+    d = _dims(u)
+    out = u.copy()
+    if fmt == "f32":
+        if u.ndim == 2:
+            L.or_sweep2d_f32(d[0], d[1], _p(u), _p(b), float(c32), _p(out))
+        else:
+            L.or_sweep3d_f32(d[0], d[1], d[2], _p(u), _p(b), float(c32), _p(out))
+    elif fmt == "bf16":
+        if u.ndim == 2:
+            L.or_sweep2d_bf16(d[0], d[1], _p(u), _p(b), float(c32), _p(out))
+        else:
+            L.or_sweep3d_bf16(d[0], d[1], d[2], _p(u), _p(b), float(c32), _p(out))
+    else:
+        raise ValueError(fmt)
+    return out
+
+
+def lo_coefficients(omega_sequence, ndim):
+    """binary32 coefficients: the FP64 c_k rounded once to binary32."""
+    return coefficients(omega_sequence, ndim).astype(np.float32)
+
+
+def lo_cast(x64, fmt):
+    """FP64 -> storage format: binary32 rounding, then (bf16) a second rounding to bfloat16."""
+    x32 = np.ascontiguousarray(x64, dtype=np.float32)
+    return x32 if fmt == "f32" else to_bf16_bits(x32)
+
+
+def lo_widen(x, fmt):
+    return (x if fmt == "f32" else from_bf16_bits(x)).astype(np.float64)
+
+
+def solve_ir(u0, f, h, omega_sequence, tol, inner_cycles, max_outer, fmt):
+    """FP64 iterative refinement around low-precision SRJ sweeps.
+
+    Outer step: r = b - A u in FP64; stop if ||r|| / ||b~|| <= tol; otherwise solve
+    A d = r approximately by ``inner_cycles`` SRJ cycles from d = 0 with a zero ring,
+    in binary32 arithmetic on ``fmt`` storage (r cast to that storage first), then
+    u += d in FP64.  Parity unpinned beyond the FP64 residual it reports.
+    """
+    u = _c64(u0).copy()
+    b = rhs(f, h)
+    c32 = lo_coefficients(omega_sequence, u.ndim)
+    M = len(c32)
+    bt2 = source_norm2(u, b)
+    inner = tuple(slice(1, -1) for _ in range(u.ndim))
+    hist = []
+    sweeps = 0
+    for outer in range(max_outer + 1):
+        r = residual_field(u, b)
+        rr = float(np.sqrt(residual_norms(u, b)[0]) / np.sqrt(bt2)) if bt2 > 0 else 0.0
+        hist.append(rr)
+        if not np.isfinite(rr):
+            return dict(u=u, outer=outer, sweeps=sweeps, relres=rr, status="diverged", history=hist)
+        if rr <= tol:
+            return dict(u=u, outer=outer, sweeps=sweeps, relres=rr, status="ok", history=hist)
+        if outer == max_outer:
+            break
+        rl = lo_cast(r, fmt)
+        d = lo_cast(np.zeros_like(u), fmt)
+        for s in range(inner_cycles * M):
+            d = sweep_lo(d, rl, c32[s % M], fmt)
+        sweeps += inner_cycles * M
+        u[inner] = u[inner] + lo_widen(d, fmt)[inner]
+    return dict(u=u, outer=max_outer, sweeps=sweeps, relres=hist[-1], status="noconv", history=hist)

@@ -1,0 +1,136 @@
+"""Seeded synthetic inputs for the SRJ solver (host numpy, FP64).
+
+This module only draws and shapes input data; it holds none of the solver's arithmetic
+and is shared by the tests, the benchmark and the smoke check.  Every array has the
+full-grid shape with its Dirichlet ring: (n_y + 2, n_x + 2) in 2D, (n_z + 2, n_y + 2,
+n_x + 2) in 3D, x fastest, spacing h = 1 / (n + 1) on the unit square / cube.
+
+Random streams are numpy ``default_rng`` (PCG64) with the seeds given per workload.
+"""
+import math
+
+import numpy as np
+
+
+def grid_spacing(n):
+    return 1.0 / (n + 1)
+
+
+def coords(n):
+    return np.arange(n + 2, dtype=np.float64) * grid_spacing(n)
+
+
+def _set_ring_zero(a):
+    a[0, ...] = 0.0
+    a[-1, ...] = 0.0
+    if a.ndim >= 2:
+        a[:, 0, ...] = 0.0
+        a[:, -1, ...] = 0.0
+    if a.ndim == 3:
+        a[:, :, 0] = 0.0
+        a[:, :, -1] = 0.0
+    return a
+
+
+def random_ring(shape_full, rng, lo=-1.0, hi=1.0):
+    """Array of the full-grid shape: U(lo, hi) on the ring, 0 inside (corners included)."""
+    g = rng.uniform(lo, hi, size=shape_full)
+    inner = tuple(slice(1, -1) for _ in shape_full)
+    g[inner] = 0.0
+    return g
+
+
+def gaussian_blobs_2d(n, count, rng, sigma=(0.01, 0.1)):
+    """sum_j a_j exp(-((x-cx_j)^2 + (y-cy_j)^2) / (2 s_j^2)); centres U(0,1)^2,
+    s_j ~ U(sigma), a_j ~ N(0, 1); zero on the ring."""
+    x = coords(n)
+    cx = rng.uniform(0.0, 1.0, count)
+    cy = rng.uniform(0.0, 1.0, count)
+    s = rng.uniform(sigma[0], sigma[1], count)
+    a = rng.standard_normal(count)
+    f = np.zeros((n + 2, n + 2))
+    for j in range(count):
+        gx = np.exp(-((x - cx[j]) ** 2) / (2.0 * s[j] ** 2))
+        gy = np.exp(-((x - cy[j]) ** 2) / (2.0 * s[j] ** 2))
+        f += a[j] * np.outer(gy, gx)
+    return _set_ring_zero(f)
+
+
+def manufactured_noise_2d(n, seed=0, noise=1e-3):
+    """f = 2 pi^2 sin(pi x) sin(pi y) + N(0, noise^2) per interior point; ring 0."""
+    rng = np.random.default_rng(seed)
+    x = coords(n)
+    f = 2.0 * math.pi ** 2 * np.outer(np.sin(math.pi * x), np.sin(math.pi * x))
+    f[1:-1, 1:-1] += rng.normal(0.0, noise, size=(n, n))
+    return _set_ring_zero(f)
+
+
+def six_neighbour_mean(v):
+    """(1/6) sum of the six axis neighbours, with zero outside the interior (input shaping
+    for the 3D workload)."""
+    p = np.zeros_like(v)
+    p[1:-1, 1:-1, 1:-1] = v[1:-1, 1:-1, 1:-1]
+    out = np.zeros_like(v)
+    out[1:-1, 1:-1, 1:-1] = (p[1:-1, 1:-1, :-2] + p[1:-1, 1:-1, 2:] + p[1:-1, :-2, 1:-1] +
+                             p[1:-1, 2:, 1:-1] + p[:-2, 1:-1, 1:-1] + p[2:, 1:-1, 1:-1]) / 6.0
+    return out
+
+
+# ------------------------------------------------------------------ workloads
+
+def small_2d(n=64, seed=0):
+    """64 x 64 interior, zero ring, f = manufactured sin-sin source + N(0, 1e-3^2) noise."""
+    f = manufactured_noise_2d(n, seed)
+    u0 = np.zeros_like(f)
+    return dict(n=(n, n), h=grid_spacing(n), u0=u0, f=f)
+
+
+def blobs_2d(n=4096, seed=0, count=32):
+    """n x n interior, ring U(-1,1), f = 32 Gaussian blobs; u0 interior zero."""
+    rng = np.random.default_rng(seed)
+    u0 = random_ring((n + 2, n + 2), rng)
+    f = gaussian_blobs_2d(n, count, rng)
+    return dict(n=(n, n), h=grid_spacing(n), u0=u0, f=f)
+
+
+def smooth_3d(n=512, seed=0):
+    """n^3 interior, zero ring, f = U(-1,1) i.i.d. then one six-neighbour mean."""
+    rng = np.random.default_rng(seed)
+    v = np.zeros((n + 2, n + 2, n + 2))
+    v[1:-1, 1:-1, 1:-1] = rng.uniform(-1.0, 1.0, size=(n, n, n))
+    f = six_neighbour_mean(v)
+    u0 = np.zeros_like(f)
+    return dict(n=(n, n, n), h=grid_spacing(n), u0=u0, f=f)
+
+
+def batch_sizes(count=1024, seed=3, lo=32, hi=1024, plo=3, phi=8):
+    """Side N_j = floor(exp(U(ln lo, ln hi))) and levels P_j ~ U{plo..phi}."""
+    rng = np.random.default_rng(seed)
+    N = np.floor(np.exp(rng.uniform(math.log(lo), math.log(hi), count))).astype(np.int64)
+    N = np.clip(N, lo, hi)
+    P = rng.integers(plo, phi + 1, size=count)
+    return N, P
+
+
+def batch_problem(n, seed):
+    """One batch member: f ~ N(0,1) i.i.d. inside, zero ring, zero start."""
+    rng = np.random.default_rng(seed)
+    f = np.zeros((n + 2, n + 2))
+    f[1:-1, 1:-1] = rng.standard_normal((n, n))
+    return dict(n=(n, n), h=grid_spacing(n), u0=np.zeros_like(f), f=f)
+
+
+def adjoint_2d(n=2048, seed=0, target_seed=1):
+    """f = Gaussian blobs, boundary U(-1,1), u_target a blob field from another seed."""
+    rng = np.random.default_rng(seed)
+    g = random_ring((n + 2, n + 2), rng)
+    f = gaussian_blobs_2d(n, 32, rng)
+    rt = np.random.default_rng(target_seed)
+    ut = gaussian_blobs_2d(n, 32, rt)
+    return dict(n=(n, n), h=grid_spacing(n), g=g, f=f, u_target=ut)
+
+
+def random_state(shape_full, seed):
+    """Random field with a random ring (for single-sweep parity checks)."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(-1.0, 1.0, size=shape_full)

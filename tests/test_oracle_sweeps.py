@@ -1,0 +1,213 @@
+"""Pins of the oracle's sweeps, residuals and stopping rule against closed forms, library
+routines and brute force (CPU only)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import schedule, spectral, sweeps
+from paper_1511_04292_amd import workloads
+
+
+def _rand_problem(shape_interior, seed):
+    rng = np.random.default_rng(seed)
+    full = tuple(n + 2 for n in shape_interior)
+    u = workloads.random_ring(full, rng)
+    f = np.zeros(full)
+    f[tuple(slice(1, -1) for _ in full)] = rng.standard_normal(tuple(shape_interior))
+    return u, f
+
+
+@pytest.mark.parametrize("shape", [(9, 12), (4, 6, 5)])
+def test_dst_solve_equals_dense_lu(shape):
+    u, f = _rand_problem(shape, 1)
+    b = sweeps.rhs(f, 0.1)
+    a = spectral.exact_solve(u, b)
+    d = spectral.dense_solve(u, b)
+    assert np.max(np.abs(a - d)) <= 1e-12 * np.max(np.abs(d))
+
+
+@pytest.mark.parametrize("shape", [(17, 23), (6, 7, 5)])
+def test_residual_of_exact_solution_vanishes(shape):
+    u, f = _rand_problem(shape, 2)
+    b = sweeps.rhs(f, 1.0 / 24)
+    us = spectral.exact_solve(u, b)
+    r2, rmax = sweeps.residual_norms(us, b)
+    scale = np.max(np.abs(spectral.load_vector(u, b)))
+    assert rmax <= 1e-12 * scale
+    # and the source norm is the norm of the load vector b~ (ring terms included)
+    assert math.isclose(sweeps.source_norm2(u, b), float(np.sum(spectral.load_vector(u, b) ** 2)),
+                        rel_tol=1e-13)
+
+
+def test_residual_sum_is_exactly_rounded_sum():
+    u, f = _rand_problem((40, 33), 3)
+    u[1:-1, 1:-1] = np.random.default_rng(4).standard_normal((40, 33)) * 1e3
+    b = sweeps.rhs(f, 0.3)
+    r = sweeps.residual_field(u, b)
+    r2, rmax = sweeps.residual_norms(u, b)
+    exact = math.fsum(float(x) * float(x) for x in r[1:-1, 1:-1].ravel())
+    assert abs(r2 - exact) <= 4e-16 * exact
+    assert rmax == float(np.max(np.abs(r)))
+
+
+@pytest.mark.parametrize("shape", [(11, 8), (5, 4, 6)])
+def test_single_sweep_matches_matrix_form(shape):
+    # u' = u + c (b~ - A u) with A assembled as a dense matrix (independent route)
+    rng = np.random.default_rng(5)
+    full = tuple(n + 2 for n in shape)
+    u = rng.uniform(-1, 1, size=full)
+    f = rng.uniform(-1, 1, size=full)
+    b = sweeps.rhs(f, 0.05)
+    c = 37.5 / (2 * len(shape))
+    out = sweeps.sweep(u, b, c)
+    A = spectral.dense_matrix(shape)
+    inner = tuple(slice(1, -1) for _ in shape)
+    x = u[inner].ravel()
+    ref = x + c * (spectral.load_vector(u, b).ravel() - A @ x)
+    scale = np.max(np.abs(u)) * (1 + 2 * len(shape) * abs(c)) + abs(c) * np.max(np.abs(b))
+    assert np.max(np.abs(out[inner].ravel() - ref)) <= 8e-16 * scale
+    # ring untouched
+    ring = np.ones(full, bool)
+    ring[inner] = False
+    assert np.array_equal(out[ring], u[ring])
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_unit_weight_reduces_to_jacobi(ndim):
+    shape = (20, 17) if ndim == 2 else (9, 8, 7)
+    u, f = _rand_problem(shape, 6)
+    b = sweeps.rhs(f, 0.05)
+    a = sweeps.run(u, b, sweeps.coefficients([1.0], ndim), 1000)
+    j = u.copy()
+    for _ in range(1000):
+        j = sweeps.jacobi(j, b)
+    assert np.max(np.abs(a - j)) <= 1e-13 * np.max(np.abs(j))
+
+
+def test_cycles_follow_exact_modal_trajectory():
+    # after m full cycles the iterate is G^m e_0 + u* in every DST mode (Eq. cycleAmplFact)
+    shape = (23, 31)
+    u, f = _rand_problem(shape, 7)
+    b = sweeps.rhs(f, 1.0 / 32)
+    omega = [120.0, 9.0, 0.8]
+    q = [1, 4, 20]
+    seq = [0] + [2] * 5 + [1] + [2] * 5 + [1, 2, 2, 2, 2, 1] + [2] * 5 + [1] + [2]
+    assert sorted(seq) == sorted(sum(([i] * qi for i, qi in enumerate(q)), []))
+    wseq = np.array(omega)[seq]
+    M = len(seq)
+    for m in (1, 2, 5):
+        got = sweeps.run(u, b, sweeps.coefficients(wseq, 2), m * M)
+        ref = spectral.predicted_state(u, b, omega, q, m)
+        assert np.max(np.abs(got - ref)) <= 1e-11 * np.max(np.abs(ref))
+
+
+def test_cycle_amplification_equals_spectral_radius():
+    # brute force: the one-cycle iteration matrix on a tiny grid, its eigenvalues
+    shape = (4, 3)
+    omega = [9.5, 0.7]
+    q = [1, 3]
+    seq = [1, 0, 1, 1]
+    A = spectral.dense_matrix(shape)
+    n = A.shape[0]
+    E = np.eye(n)
+    for i in seq:
+        E = (np.eye(n) - (omega[i] / 4.0) * A) @ E
+    rad = float(np.max(np.abs(np.linalg.eigvals(E))))
+    assert math.isclose(spectral.cycle_amplification(omega, q, shape), rad, rel_tol=1e-10)
+
+
+def test_jacobi_relres_matches_prediction():
+    shape = (15, 15)
+    u, f = _rand_problem(shape, 8)
+    b = sweeps.rhs(f, 1.0 / 16)
+    res = sweeps.solve(u, f, 1.0 / 16, [1.0], 1e-30, 60, history=True)
+    pred = spectral.predicted_relres(u, b, [1.0], [1], 60)
+    np.testing.assert_allclose(res["history"], pred, rtol=1e-9)
+
+
+def test_manufactured_solution_closed_form():
+    n = 64
+    x, y, uh, f = spectral.manufactured_2d(n)
+    b = sweeps.rhs(f, 1.0 / (n + 1))
+    us = spectral.exact_solve(np.zeros_like(f), b)
+    assert np.max(np.abs(us - uh)) <= 1e-13
+    t = math.pi / (2 * (n + 1))
+    X, Y = np.meshgrid(x, y, indexing="xy")
+    s = np.sin(math.pi * X) * np.sin(math.pi * Y)
+    err = np.max(np.abs(uh - s))
+    assert math.isclose(err, ((t / math.sin(t)) ** 2 - 1.0) * np.max(s), rel_tol=1e-9)
+    assert 1.94e-4 < err < 1.95e-4  # about pi^2 h^2 / 12
+
+
+def test_solve_stops_at_first_cycle_end_below_tol():
+    w = workloads.small_2d(24, seed=1)
+    opt = schedule.optimal(2, schedule.kappa_min_dirichlet([24, 24]))
+    q = schedule.q_floor(opt["beta"])
+    seq = schedule.weight_sequence(opt["w"], schedule.order_even(q))
+    res = sweeps.solve(w["u0"], w["f"], w["h"], seq, 1e-6, 10 ** 6, history=True)
+    hist = res["history"]
+    assert res["status"] == "ok"
+    assert hist[-1] <= 1e-6 and all(hh > 1e-6 for hh in hist[:-1])
+    assert res["sweeps"] == len(seq) * (len(hist) - 1)
+    us = spectral.exact_solve(w["u0"], sweeps.rhs(w["f"], w["h"]))
+    cond = 8.0 / (8.0 * math.sin(math.pi / 50) ** 2)
+    assert np.max(np.abs(res["u"] - us)) <= 2 * cond * 1e-6 * np.max(np.abs(us))
+
+
+def test_zero_source_and_boundary_returns_immediately():
+    u = np.zeros((10, 10))
+    u[3, 3] = 5.0
+    res = sweeps.solve(u, np.zeros((10, 10)), 0.1, [1.0], 1e-10, 100)
+    assert res["sweeps"] == 0 and res["status"] == "ok" and not np.any(res["u"])
+
+
+def test_noconv_when_budget_too_small():
+    w = workloads.small_2d(16, seed=2)
+    res = sweeps.solve(w["u0"], w["f"], w["h"], [1.0], 1e-10, 10)
+    assert res["status"] == "noconv" and res["sweeps"] == 10
+
+
+def test_nan_source_reports_divergence():
+    w = workloads.small_2d(16, seed=2)
+    w["f"][5, 5] = np.nan
+    res = sweeps.solve(w["u0"], w["f"], w["h"], [1.0], 1e-10, 10)
+    assert res["status"] == "diverged"
+
+
+def test_f32_sweep_within_binary32_rounding():
+    rng = np.random.default_rng(9)
+    u = rng.uniform(-1, 1, size=(30, 41))
+    b = rng.uniform(-1e-3, 1e-3, size=(30, 41))
+    c64 = 1234.5 / 4.0
+    out64 = sweeps.sweep(u.astype(np.float32).astype(np.float64), b.astype(np.float32).astype(np.float64),
+                         float(np.float32(c64)))
+    out32 = sweeps.sweep_lo(u.astype(np.float32), b.astype(np.float32), np.float32(c64), "f32")
+    bound = 8 * 2.0 ** -24 * (np.abs(u) * (1 + 4 * c64) + 4 * c64 * 1.0 + c64 * 1e-3)
+    assert np.all(np.abs(out32.astype(np.float64) - out64) <= bound + 1e-30)
+
+
+def test_bf16_rounding_matches_torch():
+    rng = np.random.default_rng(10)
+    x = np.concatenate([rng.standard_normal(100000).astype(np.float32),
+                        np.array([1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, -(1.0 + 2 ** -8), 3.0e38, -0.0,
+                                  np.inf, -np.inf, 1e-40, 2 ** -126], dtype=np.float32)])
+    mine = sweeps.to_bf16_bits(x)
+    ref = torch.from_numpy(x).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
+    assert np.array_equal(mine, ref)
+    back = sweeps.from_bf16_bits(mine)
+    assert np.array_equal(back, torch.from_numpy(ref.view(np.int16)).view(torch.bfloat16).float().numpy())
+
+
+def test_ir_reaches_tolerance_in_both_formats():
+    w = workloads.small_2d(31, seed=3)
+    km = schedule.kappa_min_dirichlet([31, 31])
+    opt = schedule.optimal(3, km)
+    q = schedule.q_floor(opt["beta"])
+    seq = schedule.weight_sequence(opt["w"], schedule.order_balanced(opt["w"], q, km))
+    us = spectral.exact_solve(w["u0"], sweeps.rhs(w["f"], w["h"]))
+    for fmt in ("f32", "bf16"):
+        res = sweeps.solve_ir(w["u0"], w["f"], w["h"], seq, 1e-10, 4, 60, fmt)
+        assert res["status"] == "ok", (fmt, res["history"][-5:])
+        assert np.max(np.abs(res["u"] - us)) <= 1e-7 * np.max(np.abs(us))
