@@ -1,0 +1,162 @@
+/*
+ * libsrj -- Scheduled Relaxation Jacobi (SRJ) solver for the finite-difference Poisson
+ * problem on one AMD Instinct MI355X (gfx950).  C ABI.
+ *
+ * Method: Adsuara, Cordero-Carrion, Cerda-Duran, Aloy, "Scheduled Relaxation Jacobi
+ * method: improvements and applications".  Sec. 2 defines the scheme (P weights
+ * w_1 > ... > w_P, weight i applied q_i times per cycle of M = sum q_i steps, cycles
+ * repeated); Sec. 3.1 (Eq. 2nd-order_CD) the weighted-Jacobi step; Sec. 3 the optimal
+ * weights; Sec. 4.3 the integer counts; Sec. 5.1 the Dirichlet Poisson setting and the
+ * need to spread the large weights over the cycle.
+ *
+ * Problem solved:  -lap(u) = f  on a box of n_i interior points per axis with equal
+ * spacing h on every axis and Dirichlet data on the ring of points around the box.
+ * With b = (h*h) f, one step with weight w (c = w / (2d)) is
+ *     u' = u + c * ( (sum of the 2d neighbours + b) - 2d u ),
+ * evaluated with the fixed association ((W+E)+(S+N))[+(D+U)], then + b, then - 2d u,
+ * then u + c*t, with no fused multiply-add.  The residual r = b - A u (A = 2d I minus
+ * the neighbour sum, units of h^2) is the t of that step; relres = ||r||_2 / ||b~||_2,
+ * b~ being the residual of the state with a zero interior (source plus boundary terms).
+ *
+ * Array layout at the ABI: dense, row-major, x fastest, ring included:
+ *   2D: (n[1] + 2) rows of (n[0] + 2) doubles;  3D: (n[2]+2) x (n[1]+2) x (n[0]+2).
+ * u and f are DEVICE pointers to binary64 arrays owned by the caller.  u is in/out:
+ * its ring holds the Dirichlet values (never written), its interior the initial guess on
+ * entry and the result on return.  f's ring is ignored.
+ *
+ * Errors: every call returns an srj_status; no exception crosses the ABI.
+ * srj_last_error() returns a thread-local message for the last failing call.
+ * Streams: all device work runs on the plan's stream (a hipStream_t passed as void*,
+ * NULL = default stream).  One plan must not be used from two host threads at once.
+ */
+#ifndef SRJ_H
+#define SRJ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SRJ_MAX_LEVELS 16
+
+typedef enum {
+    SRJ_OK = 0,
+    SRJ_EINVAL = 1,     /* bad argument: null pointer, n < 1, ndim not 2/3, bad schedule */
+    SRJ_ENOMEM = 2,     /* device or host allocation failed */
+    SRJ_EHIP = 3,       /* a HIP runtime call failed */
+    SRJ_ESCHEDULE = 4,  /* optimiser did not converge, or the integer scheme has Gamma_q >= 1 */
+    SRJ_ENOCONV = 5,    /* tolerance not reached within the sweep / outer budget */
+    SRJ_EDIVERGED = 6   /* residual became inf or NaN */
+} srj_status;
+
+/* Storage format of the iterate during sweeps.  SRJ_F64 computes in binary64;
+ * SRJ_F32 stores and computes in binary32; SRJ_BF16 stores bfloat16 (round to nearest
+ * even on every store) and computes in binary32.  Residual norms are always binary64. */
+typedef enum { SRJ_F64 = 0, SRJ_F32 = 1, SRJ_BF16 = 2 } srj_dtype;
+
+typedef struct {
+    int32_t ndim;     /* 2 or 3 */
+    int64_t n[3];     /* interior points per axis, n[0] = x (fastest); n[2] unused in 2D */
+    double h;         /* grid spacing, equal on every axis (unit box: 1 / (n + 1)) */
+    int32_t dtype;    /* srj_dtype of the sweeps */
+} srj_grid;
+
+/* Schedule request (Sec. 2-4).
+ *  omega == NULL: optimise P levels (Sec. 3) on [kappa_min, 2] (Eq. boundaries), counts
+ *    q_i = floor(beta_i / beta_1) (Sec. 4.3).  kappa_min == 0 takes the exact smallest
+ *    Jacobi symbol of the grid, (2/d) sum_i sin^2(pi / (2 (n_i + 1))) (Eq.
+ *    effectiveNDirichlet with N_i = n_i + 1 zones); kappa_min > 0 uses the value given
+ *    (e.g. sin^2(pi / 2N) of a Neumann table row, Eq. boundaries).
+ *  omega != NULL: P explicit weights, strictly descending, with P counts q >= 1.
+ *  ordering: 0 balanced greedy order of the M steps (default), 1 even spread of each
+ *    weight over the cycle (Sec. 5.1), 2 explicit: sequence[0..M) of level indices. */
+typedef struct {
+    int32_t P;
+    const double* omega;
+    const int64_t* q;
+    double kappa_min;
+    int32_t ordering;
+    const int32_t* sequence;
+    int64_t M;
+} srj_schedule;
+
+/* Description of a plan's schedule (srj_plan_describe). */
+typedef struct {
+    int32_t P;
+    int64_t M;
+    double omega[SRJ_MAX_LEVELS];
+    double beta[SRJ_MAX_LEVELS];   /* real fractions (0 for explicit schedules) */
+    int64_t q[SRJ_MAX_LEVELS];
+    double kappa_min, kappa_max;   /* interval the scheme was checked on */
+    double rho;                    /* sum w_i beta_i (Eq. rho); with integer q: sum w_i q_i / M */
+    double gamma_q_max;            /* max over [kappa_min, kappa_max] of |prod (1-w_i k)^q_i|^(1/M) */
+    double prefix_peak_log10;      /* largest partial product of the ordered cycle, log10 */
+    double suffix_peak_log10;
+    int32_t fused_sweeps;          /* sweeps fused per launch by the 2D/3D kernels */
+} srj_plan_desc;
+
+typedef struct {
+    int64_t sweeps;   /* weighted-Jacobi sweeps applied */
+    int64_t cycles;   /* completed M-cycles (IR: outer steps) */
+    double relres;    /* relres of the returned state */
+    double seconds;   /* device time between the first and the last kernel of the call */
+    int32_t status;
+} srj_solve_info;
+
+typedef struct srj_plan_s* srj_plan_t;
+
+/* Create a plan: validates the grid, builds the schedule, uploads c_k = w_k / (2d),
+ * allocates the plan-owned device buffers (two iterate buffers in the sweep format, the
+ * scaled source, reduction scratch).  Returns SRJ_ESCHEDULE if the optimiser fails or
+ * the integer scheme is not convergent on the grid's spectrum. */
+srj_status srj_plan(const srj_grid* grid, const srj_schedule* schedule, void* stream,
+                    srj_plan_t* out);
+void srj_plan_destroy(srj_plan_t plan);
+srj_status srj_plan_describe(srj_plan_t plan, srj_plan_desc* out);
+/* Copy the ordered level indices of one cycle (cap >= M) into seq. */
+srj_status srj_plan_sequence(srj_plan_t plan, int32_t* seq, int64_t cap);
+/* Override the number of sweeps fused per launch (0 = unfused reference kernel). */
+srj_status srj_plan_set_fusion(srj_plan_t plan, int32_t fused_sweeps);
+
+/* Solve to ||r||_2 / ||b~||_2 <= tol, checked at sweep 0 and at every cycle end (every
+ * sweep for M = 1).  Stops with SRJ_ENOCONV when the next cycle would exceed max_sweeps
+ * (u then holds the last checked state), SRJ_EDIVERGED on a non-finite residual (u
+ * unspecified).  Synchronises with the host once per check. */
+srj_status srj_solve(srj_plan_t plan, double* u, const double* f, double tol, int64_t max_sweeps,
+                     srj_solve_info* info);
+
+/* Apply exactly nsweeps scheduled sweeps to u, the first one being step k0 (mod M) of the
+ * cycle.  No convergence checks. */
+srj_status srj_sweeps(srj_plan_t plan, double* u, const double* f, int64_t k0, int64_t nsweeps);
+
+/* norms[0] = ||r||_2, norms[1] = max |r|, norms[2] = ||b~||_2, norms[3] = relres, for
+ * r = b - A u in binary64.  r_out (device, full-grid layout, ring set to 0) may be NULL. */
+srj_status srj_residual(srj_plan_t plan, const double* u, const double* f, double* r_out,
+                        double norms[4]);
+
+/* FP64 iterative refinement around the plan's low-precision sweeps (plan dtype F32 or
+ * BF16; an F64 plan runs the same loop in binary64): repeat { r = b - A u (binary64);
+ * stop if relres <= tol; d = inner_cycles SRJ cycles on A d = r from d = 0 with a zero
+ * ring, in the plan's format; u += d (binary64) } at most max_outer times. */
+srj_status srj_solve_ir(srj_plan_t plan, double* u, const double* f, double tol,
+                        int32_t inner_cycles, int32_t max_outer, srj_solve_info* info);
+
+/* Host-only schedule computations (no device needed). */
+/* Optimal P-level weights/fractions on [kappa_min, kappa_max] (Sec. 3) and counts
+ * q_i = floor(beta_i / beta_1) (Sec. 4.3).  kappa (P-1 values, may be NULL) receives the
+ * interior maxima of Gamma. */
+srj_status srj_schedule_optimal(int32_t P, double kappa_min, double kappa_max, double* omega,
+                                double* beta, int64_t* q, double* kappa);
+/* Order of the M steps for weights omega / counts q (ordering 0 balanced, 1 even). */
+srj_status srj_schedule_order(int32_t P, const double* omega, const int64_t* q, double kappa_min,
+                              double kappa_max, int32_t ordering, int32_t* seq);
+
+const char* srj_status_string(srj_status s);
+const char* srj_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SRJ_H */

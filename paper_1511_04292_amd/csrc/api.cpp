@@ -1,0 +1,546 @@
+// libsrj C ABI: plans, solves, residuals and iterative refinement on one gfx950 GPU.
+// See include/srj.h for the contract of every entry point.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/srj.h"
+#include "kernels.h"
+#include "planner.h"
+
+using namespace srj;
+
+namespace {
+
+thread_local std::string g_err;
+
+srj_status fail(srj_status s, const std::string& msg)
+{
+    g_err = msg;
+    return s;
+}
+
+#define HIPCHK(expr)                                                                      \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(SRJ_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));     \
+    } while (0)
+
+constexpr int64_t kAlignBytes = 512;
+
+// A field in one storage format: origin points at element (0, 0, 0); the allocation is
+// shifted so that interior column 1 of every row starts on a 512-byte boundary.
+struct DField {
+    void* alloc = nullptr;
+    void* origin = nullptr;
+};
+
+}  // namespace
+
+struct srj_plan_s {
+    srj_grid grid{};
+    Fmt fmt = FMT_F64;
+    hipStream_t stream = nullptr;
+    Geo geo{};
+    size_t field_elems = 0;  // elements per allocation (including alignment slack)
+
+    // schedule
+    int P = 0;
+    double omega[SRJ_MAX_LEVELS] = {0};
+    double beta[SRJ_MAX_LEVELS] = {0};
+    int64_t q[SRJ_MAX_LEVELS] = {0};
+    int64_t M = 0;
+    std::vector<int32_t> seq;
+    std::vector<double> cseq;  // c_k = w_seq[k] / (2d)
+    double kappa_min = 0, kappa_max = 0, rho = 0, gamma_q = 0, pre = 0, suf = 0;
+    int fuse = 8;
+
+    // device buffers
+    DField A, B, blo, b64f;  // iterate pair, b in the sweep format, FP64 b (low-precision plans)
+    double* b64 = nullptr;   // FP64 b: blo itself for FP64 plans, else b64f
+    double* partials = nullptr;
+    double* dres = nullptr;   // device {sum, max}
+    double* hres = nullptr;   // pinned host copy
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+namespace {
+
+srj_status alloc_field(srj_plan_t p, Fmt f, DField* d)
+{
+    size_t es = fmt_size(f);
+    size_t bytes = p->field_elems * es;
+    if (hipMalloc(&d->alloc, bytes) != hipSuccess) {
+        d->alloc = nullptr;
+        return fail(SRJ_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+    int64_t off = kAlignBytes / (int64_t)es - 1;
+    d->origin = (char*)d->alloc + off * es;
+    return SRJ_OK;
+}
+
+void free_field(DField* d)
+{
+    if (d->alloc) (void)hipFree(d->alloc);
+    d->alloc = d->origin = nullptr;
+}
+
+bool is_finite(double x) { return std::isfinite(x); }
+
+srj_status build_schedule(srj_plan_t p, const srj_schedule* sc)
+{
+    const int d = p->grid.ndim;
+    const double kmax_grid = grid_kappa_max(d, p->grid.n);
+    p->kappa_min = sc->kappa_min > 0 ? sc->kappa_min : grid_kappa_min(d, p->grid.n);
+    p->kappa_max = 2.0;
+    if (sc->P < 1 || sc->P > SRJ_MAX_LEVELS) return fail(SRJ_EINVAL, "P must be in [1, 16]");
+    p->P = sc->P;
+    if (sc->omega) {
+        if (!sc->q) return fail(SRJ_EINVAL, "explicit weights need counts q");
+        for (int i = 0; i < p->P; ++i) {
+            if (!is_finite(sc->omega[i]) || sc->omega[i] <= 0) return fail(SRJ_EINVAL, "weights must be positive");
+            if (i > 0 && !(sc->omega[i] < sc->omega[i - 1]))
+                return fail(SRJ_EINVAL, "weights must be strictly descending");
+            if (sc->q[i] < 1) return fail(SRJ_EINVAL, "counts must be >= 1");
+            p->omega[i] = sc->omega[i];
+            p->q[i] = sc->q[i];
+            p->beta[i] = 0.0;
+        }
+    } else {
+        Optimum o;
+        std::string err;
+        if (!optimal_schedule(p->P, p->kappa_min, p->kappa_max, &o, &err))
+            return fail(SRJ_ESCHEDULE, "schedule optimiser: " + err);
+        std::vector<int64_t> qq = floor_counts(o.beta);
+        for (int i = 0; i < p->P; ++i) {
+            p->omega[i] = o.w[i];
+            p->beta[i] = o.beta[i];
+            p->q[i] = qq[i];
+        }
+    }
+    p->M = 0;
+    for (int i = 0; i < p->P; ++i) p->M += p->q[i];
+    if (sc->ordering == 2) {
+        if (!sc->sequence || sc->M != p->M) return fail(SRJ_EINVAL, "explicit sequence must have M entries");
+        std::vector<int64_t> cnt(p->P, 0);
+        for (int64_t k = 0; k < p->M; ++k) {
+            int32_t i = sc->sequence[k];
+            if (i < 0 || i >= p->P) return fail(SRJ_EINVAL, "sequence index out of range");
+            cnt[i]++;
+        }
+        for (int i = 0; i < p->P; ++i)
+            if (cnt[i] != p->q[i]) return fail(SRJ_EINVAL, "sequence counts differ from q");
+        p->seq.assign(sc->sequence, sc->sequence + p->M);
+    } else if (sc->ordering == 0 || sc->ordering == 1) {
+        p->seq = order_steps(p->P, p->omega, p->q, p->kappa_min, p->kappa_max, sc->ordering);
+    } else {
+        return fail(SRJ_EINVAL, "ordering must be 0, 1 or 2");
+    }
+    // convergence of the integer scheme on the grid's own spectrum (Sec. 4.3)
+    p->gamma_q = gamma_q_max(p->P, p->omega, p->q, p->kappa_min, std::max(kmax_grid, p->kappa_min * 1.0000001));
+    if (!(p->gamma_q < 1.0))
+        return fail(SRJ_ESCHEDULE, "integer scheme not convergent: max Gamma_q = " + std::to_string(p->gamma_q));
+    partial_peaks(p->P, p->omega, p->seq, p->kappa_min, p->kappa_max, &p->pre, &p->suf);
+    double r = 0;
+    for (int i = 0; i < p->P; ++i) r += p->omega[i] * (double)p->q[i];
+    p->rho = r / (double)p->M;
+    p->cseq.resize(p->M);
+    for (int64_t k = 0; k < p->M; ++k) p->cseq[k] = p->omega[p->seq[k]] / (double)(2 * d);
+    return SRJ_OK;
+}
+
+void destroy(srj_plan_t p)
+{
+    if (!p) return;
+    free_field(&p->A);
+    free_field(&p->B);
+    free_field(&p->blo);
+    free_field(&p->b64f);
+    if (p->partials) (void)hipFree(p->partials);
+    if (p->dres) (void)hipFree(p->dres);
+    if (p->hres) (void)hipHostFree(p->hres);
+    if (p->ev0) (void)hipEventDestroy(p->ev0);
+    if (p->ev1) (void)hipEventDestroy(p->ev1);
+    delete p;
+}
+
+srj_status residual_now(srj_plan_t p, const void* u, Fmt f, int zero_int, double* sum, double* mx)
+{
+    HIPCHK(launch_residual(f, u, p->b64, p->geo, zero_int, p->partials, p->dres, p->stream));
+    HIPCHK(hipMemcpyAsync(p->hres, p->dres, 2 * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));
+    *sum = p->hres[0];
+    *mx = p->hres[1];
+    return SRJ_OK;
+}
+
+// Run sweeps k0 .. k0+n-1 on the ping-pong pair; *cur is updated to the buffer holding the
+// result.  Fused launches never straddle a cycle boundary.
+srj_status run_sweeps(srj_plan_t p, DField** cur, DField** nxt, const void* b, int64_t k0, int64_t n)
+{
+    int64_t k = k0;
+    const int64_t end = k0 + n;
+    while (k < end) {
+        if (p->fuse <= 0 || p->geo.ndim != 2) {
+            HIPCHK(launch_sweep_unfused(p->fmt, (*cur)->origin, (*nxt)->origin, b, p->geo,
+                                        p->cseq[k % p->M], p->stream));
+            k += 1;
+        } else {
+            int64_t to_cycle_end = p->M - (k % p->M);
+            int T = (int)std::min<int64_t>({(int64_t)p->fuse, end - k, to_cycle_end});
+            Coefs co;
+            for (int l = 0; l < T; ++l) co.c[l] = p->cseq[(k + l) % p->M];
+            HIPCHK(launch_sweep_fused(p->fmt, (*cur)->origin, (*nxt)->origin, b, p->geo, co, T, p->stream));
+            k += T;
+        }
+        std::swap(*cur, *nxt);
+    }
+    return SRJ_OK;
+}
+
+void fill_info(srj_solve_info* info, int64_t sweeps, int64_t cycles, double relres, double sec, srj_status st)
+{
+    if (!info) return;
+    info->sweeps = sweeps;
+    info->cycles = cycles;
+    info->relres = relres;
+    info->seconds = sec;
+    info->status = (int32_t)st;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* srj_status_string(srj_status s)
+{
+    switch (s) {
+    case SRJ_OK: return "ok";
+    case SRJ_EINVAL: return "invalid argument";
+    case SRJ_ENOMEM: return "out of memory";
+    case SRJ_EHIP: return "HIP runtime error";
+    case SRJ_ESCHEDULE: return "schedule error";
+    case SRJ_ENOCONV: return "tolerance not reached";
+    case SRJ_EDIVERGED: return "diverged";
+    }
+    return "unknown status";
+}
+
+const char* srj_last_error(void) { return g_err.c_str(); }
+
+srj_status srj_plan(const srj_grid* grid, const srj_schedule* schedule, void* stream, srj_plan_t* out)
+{
+    if (!grid || !schedule || !out) return fail(SRJ_EINVAL, "null argument");
+    *out = nullptr;
+    if (grid->ndim != 2 && grid->ndim != 3) return fail(SRJ_EINVAL, "ndim must be 2 or 3");
+    for (int i = 0; i < grid->ndim; ++i)
+        if (grid->n[i] < 1 || grid->n[i] > (1 << 20)) return fail(SRJ_EINVAL, "n must be in [1, 2^20]");
+    if (!(grid->h > 0) || !is_finite(grid->h)) return fail(SRJ_EINVAL, "h must be positive");
+    if (grid->dtype < 0 || grid->dtype > 2) return fail(SRJ_EINVAL, "dtype must be 0, 1 or 2");
+    srj_plan_t p = new (std::nothrow) srj_plan_s();
+    if (!p) return fail(SRJ_ENOMEM, "host allocation failed");
+    p->grid = *grid;
+    if (grid->ndim == 2) p->grid.n[2] = 1;
+    p->fmt = (Fmt)grid->dtype;
+    p->stream = (hipStream_t)stream;
+    srj_status st = build_schedule(p, schedule);
+    if (st != SRJ_OK) {
+        destroy(p);
+        return st;
+    }
+    Geo& g = p->geo;
+    g.ndim = grid->ndim;
+    g.nx = grid->n[0];
+    g.ny = grid->n[1];
+    g.nz = grid->ndim == 3 ? grid->n[2] : 1;
+    // pitch: multiple of 512 bytes for the narrowest format used (bf16 -> 256 elements)
+    const int64_t ae = kAlignBytes / 2;
+    g.px = ((g.nx + 2 + ae - 1) / ae) * ae;
+    g.py = g.ny + 2;
+    const int64_t rows = (g.ndim == 3 ? g.nz + 2 : 1) * g.py;
+    p->field_elems = (size_t)(rows * g.px + kAlignBytes);
+    if ((st = alloc_field(p, p->fmt, &p->A)) != SRJ_OK || (st = alloc_field(p, p->fmt, &p->B)) != SRJ_OK ||
+        (st = alloc_field(p, p->fmt, &p->blo)) != SRJ_OK) {
+        destroy(p);
+        return st;
+    }
+    if (p->fmt == FMT_F64) {
+        p->b64 = (double*)p->blo.origin;
+    } else {
+        if ((st = alloc_field(p, FMT_F64, &p->b64f)) != SRJ_OK) {
+            destroy(p);
+            return st;
+        }
+        p->b64 = (double*)p->b64f.origin;
+    }
+    const int nb = residual_blocks(g);
+    if (hipMalloc(&p->partials, sizeof(double) * 2 * (size_t)nb) != hipSuccess ||
+        hipMalloc(&p->dres, sizeof(double) * 4) != hipSuccess ||
+        hipHostMalloc(&p->hres, sizeof(double) * 4, hipHostMallocDefault) != hipSuccess ||
+        hipEventCreate(&p->ev0) != hipSuccess || hipEventCreate(&p->ev1) != hipSuccess) {
+        destroy(p);
+        return fail(SRJ_ENOMEM, "allocation of reduction scratch failed");
+    }
+    if (launch_zero(p->fmt, p->blo.origin, g, p->stream) != hipSuccess ||
+        (p->fmt != FMT_F64 && launch_zero(FMT_F64, p->b64, g, p->stream) != hipSuccess)) {
+        destroy(p);
+        return fail(SRJ_EHIP, "initial fill failed");
+    }
+    p->fuse = (g.ndim == 2) ? 8 : 0;
+    *out = p;
+    return SRJ_OK;
+}
+
+void srj_plan_destroy(srj_plan_t plan)
+{
+    if (plan) (void)hipStreamSynchronize(plan->stream);
+    destroy(plan);
+}
+
+srj_status srj_plan_describe(srj_plan_t p, srj_plan_desc* out)
+{
+    if (!p || !out) return fail(SRJ_EINVAL, "null argument");
+    std::memset(out, 0, sizeof(*out));
+    out->P = p->P;
+    out->M = p->M;
+    for (int i = 0; i < p->P; ++i) {
+        out->omega[i] = p->omega[i];
+        out->beta[i] = p->beta[i];
+        out->q[i] = p->q[i];
+    }
+    out->kappa_min = p->kappa_min;
+    out->kappa_max = p->kappa_max;
+    out->rho = p->rho;
+    out->gamma_q_max = p->gamma_q;
+    out->prefix_peak_log10 = p->pre;
+    out->suffix_peak_log10 = p->suf;
+    out->fused_sweeps = p->fuse;
+    return SRJ_OK;
+}
+
+srj_status srj_plan_sequence(srj_plan_t p, int32_t* seq, int64_t cap)
+{
+    if (!p || !seq) return fail(SRJ_EINVAL, "null argument");
+    if (cap < p->M) return fail(SRJ_EINVAL, "capacity below M");
+    std::memcpy(seq, p->seq.data(), sizeof(int32_t) * (size_t)p->M);
+    return SRJ_OK;
+}
+
+srj_status srj_plan_set_fusion(srj_plan_t p, int32_t fused)
+{
+    if (!p) return fail(SRJ_EINVAL, "null plan");
+    if (fused < 0 || fused > kMaxFuse) return fail(SRJ_EINVAL, "fusion depth must be in [0, 8]");
+    if (fused > 0 && p->geo.ndim != 2) return fail(SRJ_EINVAL, "fused sweeps are 2D only");
+    p->fuse = fused;
+    return SRJ_OK;
+}
+
+srj_status srj_residual(srj_plan_t p, const double* u, const double* f, double* r_out, double norms[4])
+{
+    if (!p || !u || !f || !norms) return fail(SRJ_EINVAL, "null argument");
+    const double hh = p->grid.h * p->grid.h;
+    srj_status st;
+    DField uf, rf;
+    struct Guard {
+        DField *a, *b;
+        ~Guard() { free_field(a); free_field(b); }
+    } guard{&uf, &rf};
+    if ((st = alloc_field(p, FMT_F64, &uf)) != SRJ_OK) return st;
+    HIPCHK(launch_copy_in(FMT_F64, u, uf.origin, p->geo, p->stream));
+    HIPCHK(launch_rhs(p->fmt, f, hh, p->blo.origin, p->fmt == FMT_F64 ? nullptr : p->b64, p->geo, p->stream));
+    double s0, m0, s1, m1;
+    if ((st = residual_now(p, uf.origin, FMT_F64, 1, &s0, &m0)) != SRJ_OK) return st;
+    if (r_out) {
+        if ((st = alloc_field(p, FMT_F64, &rf)) != SRJ_OK) return st;
+        HIPCHK(launch_zero(FMT_F64, rf.origin, p->geo, p->stream));
+        HIPCHK(launch_residual_to_lo(FMT_F64, (const double*)uf.origin, p->b64, rf.origin, p->geo, p->partials,
+                                     p->dres, p->stream));
+        const size_t user_elems =
+            (size_t)((p->geo.ndim == 3 ? p->geo.nz + 2 : 1) * p->geo.py * (p->geo.nx + 2));
+        HIPCHK(hipMemsetAsync(r_out, 0, sizeof(double) * user_elems, p->stream));
+        HIPCHK(launch_copy_out(FMT_F64, rf.origin, r_out, p->geo, p->stream));
+    }
+    if ((st = residual_now(p, uf.origin, FMT_F64, 0, &s1, &m1)) != SRJ_OK) return st;
+    norms[0] = std::sqrt(s1);
+    norms[1] = m1;
+    norms[2] = std::sqrt(s0);
+    norms[3] = s0 > 0 ? std::sqrt(s1) / std::sqrt(s0) : 0.0;
+    return SRJ_OK;
+}
+
+srj_status srj_sweeps(srj_plan_t p, double* u, const double* f, int64_t k0, int64_t n)
+{
+    if (!p || !u || !f) return fail(SRJ_EINVAL, "null argument");
+    if (k0 < 0 || n < 0) return fail(SRJ_EINVAL, "k0 and nsweeps must be >= 0");
+    const double hh = p->grid.h * p->grid.h;
+    HIPCHK(launch_copy_in(p->fmt, u, p->A.origin, p->geo, p->stream));
+    HIPCHK(launch_copy_in(p->fmt, u, p->B.origin, p->geo, p->stream));
+    HIPCHK(launch_rhs(p->fmt, f, hh, p->blo.origin, p->fmt == FMT_F64 ? nullptr : p->b64, p->geo, p->stream));
+    DField *cur = &p->A, *nxt = &p->B;
+    srj_status st = run_sweeps(p, &cur, &nxt, p->blo.origin, k0 % p->M, n);
+    if (st != SRJ_OK) return st;
+    HIPCHK(launch_copy_out(p->fmt, cur->origin, u, p->geo, p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));
+    return SRJ_OK;
+}
+
+srj_status srj_solve(srj_plan_t p, double* u, const double* f, double tol, int64_t max_sweeps,
+                     srj_solve_info* info)
+{
+    fill_info(info, 0, 0, NAN, 0, SRJ_EINVAL);
+    if (!p || !u || !f) return fail(SRJ_EINVAL, "null argument");
+    if (!(tol >= 0) || max_sweeps < 0) return fail(SRJ_EINVAL, "bad tolerance or sweep budget");
+    const double hh = p->grid.h * p->grid.h;
+    HIPCHK(hipEventRecord(p->ev0, p->stream));
+    HIPCHK(launch_copy_in(p->fmt, u, p->A.origin, p->geo, p->stream));
+    HIPCHK(launch_copy_in(p->fmt, u, p->B.origin, p->geo, p->stream));
+    HIPCHK(launch_rhs(p->fmt, f, hh, p->blo.origin, p->fmt == FMT_F64 ? nullptr : p->b64, p->geo, p->stream));
+    double bt2, bmax;
+    srj_status st = residual_now(p, p->A.origin, p->fmt, 1, &bt2, &bmax);
+    if (st != SRJ_OK) return st;
+    DField *cur = &p->A, *nxt = &p->B;
+    int64_t k = 0, cycles = 0;
+    double rr = 0.0;
+    srj_status result = SRJ_OK;
+    if (!is_finite(bt2)) {
+        result = SRJ_EDIVERGED;
+        rr = NAN;
+    } else if (bt2 == 0.0) {
+        // zero source and zero boundary: u = 0 is exact
+        HIPCHK(launch_zero(p->fmt, cur->origin, p->geo, p->stream));
+        rr = 0.0;
+    } else {
+        for (;;) {
+            double r2, rmax;
+            if ((st = residual_now(p, cur->origin, p->fmt, 0, &r2, &rmax)) != SRJ_OK) return st;
+            rr = std::sqrt(r2) / std::sqrt(bt2);
+            if (!is_finite(rr)) {
+                result = SRJ_EDIVERGED;
+                break;
+            }
+            if (rr <= tol) break;
+            if (k + p->M > max_sweeps) {
+                result = SRJ_ENOCONV;
+                break;
+            }
+            if ((st = run_sweeps(p, &cur, &nxt, p->blo.origin, 0, p->M)) != SRJ_OK) return st;
+            k += p->M;
+            cycles += 1;
+        }
+    }
+    if (result != SRJ_EDIVERGED) HIPCHK(launch_copy_out(p->fmt, cur->origin, u, p->geo, p->stream));
+    HIPCHK(hipEventRecord(p->ev1, p->stream));
+    HIPCHK(hipEventSynchronize(p->ev1));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, p->ev0, p->ev1));
+    fill_info(info, k, cycles, rr, ms * 1e-3, result);
+    if (result == SRJ_ENOCONV) return fail(result, "tolerance not reached within max_sweeps");
+    if (result == SRJ_EDIVERGED) return fail(result, "non-finite residual");
+    return SRJ_OK;
+}
+
+srj_status srj_solve_ir(srj_plan_t p, double* u, const double* f, double tol, int32_t inner_cycles,
+                        int32_t max_outer, srj_solve_info* info)
+{
+    fill_info(info, 0, 0, NAN, 0, SRJ_EINVAL);
+    if (!p || !u || !f) return fail(SRJ_EINVAL, "null argument");
+    if (!(tol >= 0) || inner_cycles < 1 || max_outer < 0) return fail(SRJ_EINVAL, "bad IR parameters");
+    const double hh = p->grid.h * p->grid.h;
+    srj_status st;
+    // the FP64 iterate lives in its own field; the plan's A/B hold the correction d and blo
+    // the low-precision residual
+    DField u64;
+    if ((st = alloc_field(p, FMT_F64, &u64)) != SRJ_OK) return st;
+    struct Guard {
+        DField* f;
+        ~Guard() { free_field(f); }
+    } guard{&u64};
+    HIPCHK(hipEventRecord(p->ev0, p->stream));
+    HIPCHK(launch_copy_in(FMT_F64, u, u64.origin, p->geo, p->stream));
+    HIPCHK(launch_rhs(FMT_F64, f, hh, nullptr, p->b64, p->geo, p->stream));
+    double bt2, bmax;
+    if ((st = residual_now(p, u64.origin, FMT_F64, 1, &bt2, &bmax)) != SRJ_OK) return st;
+    srj_status result = SRJ_OK;
+    double rr = 0.0;
+    int64_t sweeps = 0;
+    int outer = 0;
+    if (!is_finite(bt2)) {
+        result = SRJ_EDIVERGED;
+        rr = NAN;
+    } else if (bt2 == 0.0) {
+        HIPCHK(launch_zero(FMT_F64, u64.origin, p->geo, p->stream));
+    } else {
+        for (;;) {
+            HIPCHK(launch_residual_to_lo(p->fmt, (const double*)u64.origin, p->b64, p->blo.origin, p->geo,
+                                         p->partials, p->dres, p->stream));
+            HIPCHK(hipMemcpyAsync(p->hres, p->dres, 2 * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+            HIPCHK(hipStreamSynchronize(p->stream));
+            rr = std::sqrt(p->hres[0]) / std::sqrt(bt2);
+            if (!is_finite(rr)) {
+                result = SRJ_EDIVERGED;
+                break;
+            }
+            if (rr <= tol) break;
+            if (outer >= max_outer) {
+                result = SRJ_ENOCONV;
+                break;
+            }
+            HIPCHK(launch_zero(p->fmt, p->A.origin, p->geo, p->stream));
+            HIPCHK(launch_zero(p->fmt, p->B.origin, p->geo, p->stream));
+            DField *cur = &p->A, *nxt = &p->B;
+            if ((st = run_sweeps(p, &cur, &nxt, p->blo.origin, 0, (int64_t)inner_cycles * p->M)) != SRJ_OK)
+                return st;
+            sweeps += (int64_t)inner_cycles * p->M;
+            HIPCHK(launch_update(p->fmt, (double*)u64.origin, cur->origin, p->geo, p->stream));
+            outer += 1;
+        }
+    }
+    if (result != SRJ_EDIVERGED) HIPCHK(launch_copy_out(FMT_F64, u64.origin, u, p->geo, p->stream));
+    HIPCHK(hipEventRecord(p->ev1, p->stream));
+    HIPCHK(hipEventSynchronize(p->ev1));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, p->ev0, p->ev1));
+    fill_info(info, sweeps, outer, rr, ms * 1e-3, result);
+    if (result == SRJ_ENOCONV) return fail(result, "tolerance not reached within max_outer");
+    if (result == SRJ_EDIVERGED) return fail(result, "non-finite residual");
+    return SRJ_OK;
+}
+
+srj_status srj_schedule_optimal(int32_t P, double kappa_min, double kappa_max, double* omega, double* beta,
+                                int64_t* q, double* kappa)
+{
+    if (!omega || !beta || !q) return fail(SRJ_EINVAL, "null argument");
+    Optimum o;
+    std::string err;
+    if (!optimal_schedule(P, kappa_min, kappa_max, &o, &err)) return fail(SRJ_ESCHEDULE, err);
+    std::vector<int64_t> qq = floor_counts(o.beta);
+    for (int i = 0; i < P; ++i) {
+        omega[i] = o.w[i];
+        beta[i] = o.beta[i];
+        q[i] = qq[i];
+    }
+    if (kappa)
+        for (int j = 0; j + 1 < P; ++j) kappa[j] = o.kappa[j];
+    return SRJ_OK;
+}
+
+srj_status srj_schedule_order(int32_t P, const double* omega, const int64_t* q, double kappa_min,
+                              double kappa_max, int32_t ordering, int32_t* seq)
+{
+    if (!omega || !q || !seq) return fail(SRJ_EINVAL, "null argument");
+    if (P < 1 || P > SRJ_MAX_LEVELS) return fail(SRJ_EINVAL, "P must be in [1, 16]");
+    if (ordering != 0 && ordering != 1) return fail(SRJ_EINVAL, "ordering must be 0 or 1");
+    if (!(kappa_min > 0) || !(kappa_max > kappa_min)) return fail(SRJ_EINVAL, "bad interval");
+    std::vector<int32_t> s = order_steps(P, omega, q, kappa_min, kappa_max, ordering);
+    std::memcpy(seq, s.data(), sizeof(int32_t) * s.size());
+    return SRJ_OK;
+}
+
+}  // extern "C"

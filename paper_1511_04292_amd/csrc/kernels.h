@@ -1,0 +1,55 @@
+// Launchers of the SRJ device kernels (gfx950).  All pointers are device pointers to
+// padded fields: element (k, i, j) of a field lives at origin[(k * py + i) * px + j], with
+// i, j, k running over 0..n+1 (ring included), px the row pitch and py = ny + 2.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace srj {
+
+enum Fmt { FMT_F64 = 0, FMT_F32 = 1, FMT_BF16 = 2 };
+
+constexpr int kMaxFuse = 8;  // largest number of sweeps fused into one launch
+
+struct Geo {
+    int ndim;
+    int64_t nx, ny, nz;  // interior sizes (nz = 1 in 2D)
+    int64_t px, py;      // row pitch (elements) and rows per plane (ny + 2)
+};
+
+struct Coefs {
+    double c[kMaxFuse];  // c = w / (2d) of consecutive sweeps
+};
+
+size_t fmt_size(Fmt f);
+
+// user (dense FP64, ring included) -> field in format f (all points, ring included)
+hipError_t launch_copy_in(Fmt f, const double* user, void* field, const Geo& g, hipStream_t s);
+// field -> user interior (ring of user untouched)
+hipError_t launch_copy_out(Fmt f, const void* field, double* user, const Geo& g, hipStream_t s);
+// b = (h*h) * f on the interior: blo in format f (may be null), b64 in FP64 (may be null)
+hipError_t launch_rhs(Fmt f, const double* user_f, double hh, void* blo, double* b64, const Geo& g,
+                      hipStream_t s);
+// T consecutive sweeps in -> out with coefficients co.c[0..T).  T = 0 selects nothing;
+// fused = false runs T unfused launches (ping-pong through `tmp`, which must then be a
+// third buffer or equal to `in` when T is odd... see caller).
+hipError_t launch_sweep_unfused(Fmt f, const void* in, void* out, const void* b, const Geo& g,
+                                double c, hipStream_t s);
+hipError_t launch_sweep_fused(Fmt f, const void* in, void* out, const void* b, const Geo& g,
+                              const Coefs& co, int T, hipStream_t s);
+// sum r^2 and max |r| of r = b64 - A u (binary64); zero_interior treats u's interior as 0.
+// partials must hold 2 * residual_blocks(g) doubles; result receives {sum, max}.
+int residual_blocks(const Geo& g);
+hipError_t launch_residual(Fmt f, const void* u, const double* b64, const Geo& g, int zero_interior,
+                           double* partials, double* result, hipStream_t s);
+// IR: r = b64 - A u64 (binary64) written to rlo in format f, with its norms (as above).
+hipError_t launch_residual_to_lo(Fmt f, const double* u64, const double* b64, void* rlo,
+                                 const Geo& g, double* partials, double* result, hipStream_t s);
+// IR: u64 interior += widen(d)
+hipError_t launch_update(Fmt f, double* u64, const void* d, const Geo& g, hipStream_t s);
+// set every element of the field (ring included) to zero with a fill kernel
+hipError_t launch_zero(Fmt f, void* field, const Geo& g, hipStream_t s);
+
+}  // namespace srj

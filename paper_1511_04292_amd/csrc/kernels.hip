@@ -1,0 +1,588 @@
+// SRJ device kernels for gfx950 (CDNA4, wave64).
+//
+// The weighted-Jacobi step (Sec. 3.1, Eq. 2nd-order_CD, Poisson form with b = h^2 f):
+//     s = (W + E) + (S + N)  [ + (D + U) in 3D ]
+//     t = (s + b) - 2d * u
+//     u' = u + c * t,        c = w / (2d)
+// with exactly this association and no fused multiply-add (the file is built with
+// -ffp-contract=off), so every kernel below -- unfused or temporally blocked -- produces
+// bit-identical iterates for the same sweep sequence.  Storage formats: binary64,
+// binary32, and bfloat16 (binary32 arithmetic, round-to-nearest-even on every store).
+//
+// The sweep is bound by HBM bandwidth (0.3 flop per byte unfused), so no kernel here uses
+// the matrix cores.  The 2D temporally-blocked kernel gives each wavefront a strip of
+// 64*C columns (C per lane) and a segment of rows, streams the rows from top to bottom
+// and keeps T time levels of a 3-row window in registers: one HBM read of u and b and one
+// write of u serve T sweeps.  Horizontal neighbours cross lanes by shuffles; no LDS and no
+// barriers are needed because every wave is independent (strips overlap by T columns
+// on each side, segments by T rows, the overlap being recomputed).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.h"
+
+namespace srj {
+
+size_t fmt_size(Fmt f) { return f == FMT_F64 ? 8 : (f == FMT_F32 ? 4 : 2); }
+
+// ------------------------------------------------------------------- formats
+
+struct bf16_t {
+    uint16_t v;
+};
+
+template <class S> struct Tr;
+template <> struct Tr<double> {
+    using C = double;
+    static __device__ __forceinline__ double ld(double x) { return x; }
+    static __device__ __forceinline__ double st(double x) { return x; }
+    static __device__ __forceinline__ double from64(double x) { return x; }
+};
+template <> struct Tr<float> {
+    using C = float;
+    static __device__ __forceinline__ float ld(float x) { return x; }
+    static __device__ __forceinline__ float st(float x) { return x; }
+    static __device__ __forceinline__ float from64(double x) { return (float)x; }
+};
+template <> struct Tr<bf16_t> {
+    using C = float;
+    static __device__ __forceinline__ float ld(bf16_t x) { return __uint_as_float((uint32_t)x.v << 16); }
+    static __device__ __forceinline__ bf16_t st(float f)
+    {
+        uint32_t x = __float_as_uint(f);
+        bf16_t r;
+        if ((x & 0x7fffffffu) > 0x7f800000u) {
+            r.v = (uint16_t)((x >> 16) | 0x40u);
+        } else {
+            x += 0x7fffu + ((x >> 16) & 1u);
+            r.v = (uint16_t)(x >> 16);
+        }
+        return r;
+    }
+    // binary64 -> binary32 (round to nearest) -> bfloat16 (round to nearest even)
+    static __device__ __forceinline__ bf16_t from64(double x) { return st((float)x); }
+};
+
+template <class S> __device__ __forceinline__ S zero_of();
+template <> __device__ __forceinline__ double zero_of<double>() { return 0.0; }
+template <> __device__ __forceinline__ float zero_of<float>() { return 0.0f; }
+template <> __device__ __forceinline__ bf16_t zero_of<bf16_t>() { return bf16_t{0}; }
+
+template <class C> __device__ __forceinline__ C shfl_up1(C v) { return __shfl_up(v, 1, 64); }
+template <class C> __device__ __forceinline__ C shfl_dn1(C v) { return __shfl_down(v, 1, 64); }
+
+// ------------------------------------------------------------ copy / rhs / fill
+
+template <class S>
+__global__ __launch_bounds__(256) void k_copy_in(const double* __restrict__ user, S* __restrict__ f,
+                                                 Geo g)
+{
+    const int64_t rows = (g.ndim == 3 ? g.nz + 2 : 1) * g.py;
+    const int64_t w = g.nx + 2;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < rows * w;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        int64_t row = idx / w, j = idx % w;
+        f[row * g.px + j] = Tr<S>::from64(user[idx]);
+    }
+}
+
+template <class S>
+__global__ __launch_bounds__(256) void k_copy_out(const S* __restrict__ f, double* __restrict__ user,
+                                                  Geo g)
+{
+    const int64_t planes = (g.ndim == 3 ? g.nz : 1);
+    const int64_t n = planes * g.ny * g.nx;
+    const int64_t w = g.nx + 2;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        int64_t j = idx % g.nx + 1;
+        int64_t t = idx / g.nx;
+        int64_t i = t % g.ny + 1;
+        int64_t k = (g.ndim == 3) ? t / g.ny + 1 : 0;
+        int64_t row = k * g.py + i;
+        user[row * w + j] = (double)Tr<S>::ld(f[row * g.px + j]);
+    }
+}
+
+template <class S>
+__global__ __launch_bounds__(256) void k_rhs(const double* __restrict__ uf, double hh, S* __restrict__ blo,
+                                             double* __restrict__ b64, Geo g)
+{
+    const int64_t planes = (g.ndim == 3 ? g.nz : 1);
+    const int64_t n = planes * g.ny * g.nx;
+    const int64_t w = g.nx + 2;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        int64_t j = idx % g.nx + 1;
+        int64_t t = idx / g.nx;
+        int64_t i = t % g.ny + 1;
+        int64_t k = (g.ndim == 3) ? t / g.ny + 1 : 0;
+        int64_t row = k * g.py + i;
+        double b = hh * uf[row * w + j];
+        if (b64) b64[row * g.px + j] = b;
+        if (blo) blo[row * g.px + j] = Tr<S>::from64(b);
+    }
+}
+
+template <class S>
+__global__ __launch_bounds__(256) void k_zero(S* __restrict__ f, int64_t n)
+{
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n;
+         idx += (int64_t)gridDim.x * blockDim.x)
+        f[idx] = zero_of<S>();
+}
+
+// ------------------------------------------------------------- unfused sweeps
+
+// One sweep, one thread per interior point (reference kernel; also small grids).
+template <class S>
+__global__ __launch_bounds__(256) void k_sweep2d(const S* __restrict__ u, S* __restrict__ o,
+                                                 const S* __restrict__ b, int64_t px, int nx, int ny,
+                                                 double c64)
+{
+    using Cm = typename Tr<S>::C;
+    const int j = blockIdx.x * 64 + threadIdx.x + 1;
+    const int i = blockIdx.y * 4 + threadIdx.y + 1;
+    if (j > nx || i > ny) return;
+    const Cm c = (Cm)c64;
+    const int64_t p = (int64_t)i * px + j;
+    Cm m = Tr<S>::ld(u[p]);
+    Cm s = (Tr<S>::ld(u[p - 1]) + Tr<S>::ld(u[p + 1])) + (Tr<S>::ld(u[p - px]) + Tr<S>::ld(u[p + px]));
+    Cm t = (s + Tr<S>::ld(b[p])) - (Cm)4 * m;
+    o[p] = Tr<S>::st(m + c * t);
+}
+
+// One 3D sweep: threads over (x, y), each walking a run of z planes with the z
+// neighbours kept in registers.
+template <class S>
+__global__ __launch_bounds__(256) void k_sweep3d(const S* __restrict__ u, S* __restrict__ o,
+                                                 const S* __restrict__ b, int64_t px, int64_t py,
+                                                 int nx, int ny, int nz, int zrun, double c64)
+{
+    using Cm = typename Tr<S>::C;
+    const int j = blockIdx.x * 64 + threadIdx.x + 1;
+    const int i = blockIdx.y * 4 + threadIdx.y + 1;
+    if (j > nx || i > ny) return;
+    const int k0 = blockIdx.z * zrun + 1;
+    const int k1 = min(k0 + zrun, nz + 1);
+    const Cm c = (Cm)c64;
+    const int64_t pl = px * py;
+    int64_t p = (int64_t)k0 * pl + (int64_t)i * px + j;
+    Cm dn = Tr<S>::ld(u[p - pl]);
+    Cm m = Tr<S>::ld(u[p]);
+    for (int k = k0; k < k1; ++k, p += pl) {
+        Cm up = Tr<S>::ld(u[p + pl]);
+        Cm s = ((Tr<S>::ld(u[p - 1]) + Tr<S>::ld(u[p + 1])) + (Tr<S>::ld(u[p - px]) + Tr<S>::ld(u[p + px]))) +
+               (dn + up);
+        Cm t = (s + Tr<S>::ld(b[p])) - (Cm)6 * m;
+        o[p] = Tr<S>::st(m + c * t);
+        dn = m;
+        m = up;
+    }
+}
+
+// --------------------------------------------------- temporally blocked 2D sweeps
+
+template <int T> struct CoefsT {
+    double c[T];
+};
+
+// Wave layout: strip `st` covers columns x0 .. x0 + 64C - 1 with x0 = 1 + st*SW - T
+// (SW = 64C - 2T output columns per strip); segment `sg` outputs rows y0 .. y1-1.
+// At step r the wave loads row r (level 0) and computes level l for row r - l,
+// l = 1..T, from level l-1 rows r-l-1, r-l, r-l+1.  Ring rows/columns never change,
+// columns outside the grid are held at 0, and only points whose dependence cone lies
+// inside the loaded window are stored.
+template <class S, int T, int C>
+__global__ __launch_bounds__(256) void k_sweep2d_tb(const S* __restrict__ uin, S* __restrict__ uout,
+                                                    const S* __restrict__ bb, int64_t px, int nx,
+                                                    int ny, CoefsT<T> co, int nstrip, int nwaves,
+                                                    int H)
+{
+    using Cm = typename Tr<S>::C;
+    constexpr int SW = 64 * C - 2 * T;
+    const int lane = threadIdx.x & 63;
+    const int wid = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (wid >= nwaves) return;
+    const int st = wid % nstrip;
+    const int sg = wid / nstrip;
+    const int64_t x0 = 1 + (int64_t)st * SW - T + (int64_t)lane * C;
+    const int y0 = 1 + sg * H;
+    const int y1 = min(y0 + H, ny + 1);
+    const int rb = max(0, y0 - T);
+    const int rl = y1 - 1 + T;
+
+    bool live[C], upd[C], outc[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const int64_t x = x0 + c;
+        const int off = lane * C + c;
+        live[c] = (x >= 0 && x <= (int64_t)nx + 1);
+        upd[c] = (x >= 1 && x <= (int64_t)nx);
+        outc[c] = upd[c] && off >= T && off < 64 * C - T;
+    }
+    Cm cf[T];
+#pragma unroll
+    for (int l = 0; l < T; ++l) cf[l] = (Cm)co.c[l];
+
+    Cm p1[T][C], p2[T][C], bq[T][C];
+#pragma unroll
+    for (int l = 0; l < T; ++l)
+#pragma unroll
+        for (int c = 0; c < C; ++c) p1[l][c] = p2[l][c] = bq[l][c] = (Cm)0;
+
+    Cm cu[C], cb[C];
+    auto load_row = [&](int r, Cm* vu, Cm* vb) {
+        if (r <= ny + 1) {
+            const S* pu = uin + (int64_t)r * px + x0;
+            const S* pb = bb + (int64_t)r * px + x0;
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                vu[c] = live[c] ? Tr<S>::ld(pu[c]) : (Cm)0;
+                vb[c] = (live[c] && r >= 1 && r <= ny) ? Tr<S>::ld(pb[c]) : (Cm)0;
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < C; ++c) vu[c] = vb[c] = (Cm)0;
+        }
+    };
+    load_row(rb, cu, cb);
+
+    for (int r = rb; r <= rl; ++r) {
+        Cm nu[C], nb[C];
+        load_row(r + 1, nu, nb);
+        Cm in[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) in[c] = cu[c];
+#pragma unroll
+        for (int l = 1; l <= T; ++l) {
+            const int j = r - l;
+            Cm out[C];
+            if (j >= 1 && j <= ny) {
+                const Cm wn = shfl_up1(p1[l - 1][C - 1]);
+                const Cm en = shfl_dn1(p1[l - 1][0]);
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    const Cm W = (c == 0) ? wn : p1[l - 1][c - 1];
+                    const Cm E = (c == C - 1) ? en : p1[l - 1][c + 1];
+                    const Cm m = p1[l - 1][c];
+                    const Cm s = (W + E) + (p2[l - 1][c] + in[c]);
+                    const Cm t = (s + bq[l - 1][c]) - (Cm)4 * m;
+                    const Cm v = Tr<S>::ld(Tr<S>::st(m + cf[l - 1] * t));
+                    out[c] = upd[c] ? v : m;
+                }
+            } else {
+#pragma unroll
+                for (int c = 0; c < C; ++c) out[c] = p1[l - 1][c];
+            }
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                p2[l - 1][c] = p1[l - 1][c];
+                p1[l - 1][c] = in[c];
+                in[c] = out[c];
+            }
+        }
+        const int j = r - T;
+        if (j >= y0 && j < y1) {
+            S* po = uout + (int64_t)j * px + x0;
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                if (outc[c]) po[c] = Tr<S>::st(in[c]);
+        }
+#pragma unroll
+        for (int l = T - 1; l > 0; --l)
+#pragma unroll
+            for (int c = 0; c < C; ++c) bq[l][c] = bq[l - 1][c];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            bq[0][c] = cb[c];
+            cu[c] = nu[c];
+            cb[c] = nb[c];
+        }
+    }
+}
+
+// ------------------------------------------------------------------ residuals
+
+__device__ __forceinline__ void nanmax(double& m, double a)
+{
+    if (a > m || a != a) m = a;
+}
+
+// Block reduction of (sum, max) over 256 threads; thread 0 returns the result.
+__device__ void block_reduce(double& s, double& m)
+{
+    __shared__ double ss[4], sm[4];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        double so = __shfl_xor(s, o, 64);
+        double mo = __shfl_xor(m, o, 64);
+        s = s + so;
+        nanmax(m, mo);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        ss[w] = s;
+        sm[w] = m;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        s = (ss[0] + ss[1]) + (ss[2] + ss[3]);
+        m = sm[0];
+        nanmax(m, sm[1]);
+        nanmax(m, sm[2]);
+        nanmax(m, sm[3]);
+    }
+}
+
+constexpr int kResRows = 8;  // rows (2D) or (k, i) lines (3D) per residual block
+
+template <class S>
+__device__ __forceinline__ double ldz(const S* u, int64_t p, bool zero)
+{
+    return zero ? 0.0 : (double)Tr<S>::ld(u[p]);
+}
+
+// r at interior point p (binary64).  With zero_int, interior values of u read as 0.
+template <class S>
+__device__ __forceinline__ double res_at(const S* u, const double* b64, int64_t p, int64_t px,
+                                         int64_t pl, int ndim, int i, int j, int k, const Geo& g,
+                                         bool zi)
+{
+    const bool zl = zi && j - 1 >= 1, zr = zi && j + 1 <= g.nx;
+    const bool zs = zi && i - 1 >= 1, zn = zi && i + 1 <= g.ny;
+    double s = (ldz(u, p - 1, zl) + ldz(u, p + 1, zr)) + (ldz(u, p - px, zs) + ldz(u, p + px, zn));
+    double twod_u;
+    if (ndim == 3) {
+        const bool zd = zi && k - 1 >= 1, zu = zi && k + 1 <= g.nz;
+        s = s + (ldz(u, p - pl, zd) + ldz(u, p + pl, zu));
+        twod_u = 6.0 * ldz(u, p, zi);
+    } else {
+        twod_u = 4.0 * ldz(u, p, zi);
+    }
+    return (s + b64[p]) - twod_u;
+}
+
+template <class S>
+__global__ __launch_bounds__(256) void k_residual(const S* __restrict__ u, const double* __restrict__ b64,
+                                                  Geo g, int zero_int, double* __restrict__ partials)
+{
+    const int64_t lines = g.ny * (g.ndim == 3 ? g.nz : 1);
+    const int64_t pl = g.px * g.py;
+    double s = 0.0, m = 0.0;
+    const int64_t q0 = (int64_t)blockIdx.x * kResRows;
+    for (int64_t q = q0; q < min(q0 + kResRows, lines); ++q) {
+        const int i = (int)(q % g.ny) + 1;
+        const int k = (g.ndim == 3) ? (int)(q / g.ny) + 1 : 0;
+        const int64_t rowp = (int64_t)k * pl + (int64_t)i * g.px;
+        for (int j = threadIdx.x + 1; j <= g.nx; j += 256) {
+            double r = res_at(u, b64, rowp + j, g.px, pl, g.ndim, i, j, k, g, zero_int != 0);
+            s = s + r * r;
+            nanmax(m, fabs(r));
+        }
+    }
+    block_reduce(s, m);
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = s;
+        partials[2 * blockIdx.x + 1] = m;
+    }
+}
+
+template <class S>
+__global__ __launch_bounds__(256) void k_residual_to_lo(const double* __restrict__ u,
+                                                        const double* __restrict__ b64,
+                                                        S* __restrict__ rlo, Geo g,
+                                                        double* __restrict__ partials)
+{
+    const int64_t lines = g.ny * (g.ndim == 3 ? g.nz : 1);
+    const int64_t pl = g.px * g.py;
+    double s = 0.0, m = 0.0;
+    const int64_t q0 = (int64_t)blockIdx.x * kResRows;
+    for (int64_t q = q0; q < min(q0 + kResRows, lines); ++q) {
+        const int i = (int)(q % g.ny) + 1;
+        const int k = (g.ndim == 3) ? (int)(q / g.ny) + 1 : 0;
+        const int64_t rowp = (int64_t)k * pl + (int64_t)i * g.px;
+        for (int j = threadIdx.x + 1; j <= g.nx; j += 256) {
+            double r = res_at(u, b64, rowp + j, g.px, pl, g.ndim, i, j, k, g, false);
+            rlo[rowp + j] = Tr<S>::from64(r);
+            s = s + r * r;
+            nanmax(m, fabs(r));
+        }
+    }
+    block_reduce(s, m);
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = s;
+        partials[2 * blockIdx.x + 1] = m;
+    }
+}
+
+// Deterministic final reduction: thread t folds partials t, t+256, ... in order.
+__global__ __launch_bounds__(256) void k_reduce_final(const double* __restrict__ partials, int n,
+                                                      double* __restrict__ result)
+{
+    double s = 0.0, m = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) {
+        s = s + partials[2 * i];
+        nanmax(m, partials[2 * i + 1]);
+    }
+    block_reduce(s, m);
+    if (threadIdx.x == 0) {
+        result[0] = s;
+        result[1] = m;
+    }
+}
+
+template <class S>
+__global__ __launch_bounds__(256) void k_update(double* __restrict__ u, const S* __restrict__ d, Geo g)
+{
+    const int64_t planes = (g.ndim == 3 ? g.nz : 1);
+    const int64_t n = planes * g.ny * g.nx;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        int64_t j = idx % g.nx + 1;
+        int64_t t = idx / g.nx;
+        int64_t i = t % g.ny + 1;
+        int64_t k = (g.ndim == 3) ? t / g.ny + 1 : 0;
+        int64_t p = (k * g.py + i) * g.px + j;
+        u[p] = u[p] + (double)Tr<S>::ld(d[p]);
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+
+static dim3 grid1d(int64_t n)
+{
+    int64_t b = (n + 255) / 256;
+    if (b > 65536) b = 65536;
+    if (b < 1) b = 1;
+    return dim3((unsigned)b);
+}
+
+static int64_t field_rows(const Geo& g) { return (g.ndim == 3 ? g.nz + 2 : 1) * g.py; }
+
+#define SRJ_DISPATCH(f, KCALL)                               \
+    switch (f) {                                             \
+    case FMT_F64: { using S = double; KCALL; break; }        \
+    case FMT_F32: { using S = float; KCALL; break; }         \
+    default: { using S = bf16_t; KCALL; break; }             \
+    }
+
+hipError_t launch_copy_in(Fmt f, const double* user, void* field, const Geo& g, hipStream_t s)
+{
+    int64_t n = field_rows(g) * (g.nx + 2);
+    SRJ_DISPATCH(f, hipLaunchKernelGGL(k_copy_in<S>, grid1d(n), dim3(256), 0, s, user, (S*)field, g));
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_out(Fmt f, const void* field, double* user, const Geo& g, hipStream_t s)
+{
+    int64_t n = (g.ndim == 3 ? g.nz : 1) * g.ny * g.nx;
+    SRJ_DISPATCH(f, hipLaunchKernelGGL(k_copy_out<S>, grid1d(n), dim3(256), 0, s, (const S*)field, user, g));
+    return hipGetLastError();
+}
+
+hipError_t launch_rhs(Fmt f, const double* uf, double hh, void* blo, double* b64, const Geo& g,
+                      hipStream_t s)
+{
+    int64_t n = (g.ndim == 3 ? g.nz : 1) * g.ny * g.nx;
+    SRJ_DISPATCH(f, hipLaunchKernelGGL(k_rhs<S>, grid1d(n), dim3(256), 0, s, uf, hh, (S*)blo, b64, g));
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(Fmt f, void* field, const Geo& g, hipStream_t s)
+{
+    int64_t n = field_rows(g) * g.px;
+    SRJ_DISPATCH(f, hipLaunchKernelGGL(k_zero<S>, grid1d(n), dim3(256), 0, s, (S*)field, n));
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_unfused(Fmt f, const void* in, void* out, const void* b, const Geo& g,
+                                double c, hipStream_t s)
+{
+    if (g.ndim == 2) {
+        dim3 grid((unsigned)((g.nx + 63) / 64), (unsigned)((g.ny + 3) / 4));
+        SRJ_DISPATCH(f, hipLaunchKernelGGL(k_sweep2d<S>, grid, dim3(64, 4), 0, s, (const S*)in, (S*)out,
+                                           (const S*)b, g.px, (int)g.nx, (int)g.ny, c));
+    } else {
+        const int zrun = 8;
+        dim3 grid((unsigned)((g.nx + 63) / 64), (unsigned)((g.ny + 3) / 4), (unsigned)((g.nz + zrun - 1) / zrun));
+        SRJ_DISPATCH(f, hipLaunchKernelGGL(k_sweep3d<S>, grid, dim3(64, 4), 0, s, (const S*)in, (S*)out,
+                                           (const S*)b, g.px, g.py, (int)g.nx, (int)g.ny, (int)g.nz, zrun, c));
+    }
+    return hipGetLastError();
+}
+
+template <class S, int T, int C>
+static void tb2d(const S* in, S* out, const S* b, const Geo& g, const Coefs& co, hipStream_t s)
+{
+    constexpr int SW = 64 * C - 2 * T;
+    const int H = 64;
+    CoefsT<T> ct;
+    for (int l = 0; l < T; ++l) ct.c[l] = co.c[l];
+    const int nstrip = (int)((g.nx + SW - 1) / SW);
+    const int nseg = (int)((g.ny + H - 1) / H);
+    const int nwaves = nstrip * nseg;
+    hipLaunchKernelGGL((k_sweep2d_tb<S, T, C>), dim3((nwaves + 3) / 4), dim3(256), 0, s, in, out, b, g.px,
+                       (int)g.nx, (int)g.ny, ct, nstrip, nwaves, H);
+}
+
+template <class S>
+static void tb2d_dispatch(const S* in, S* out, const S* b, const Geo& g, const Coefs& co, int T,
+                          hipStream_t s)
+{
+    constexpr int C = 2;
+    switch (T) {
+    case 1: tb2d<S, 1, C>(in, out, b, g, co, s); break;
+    case 2: tb2d<S, 2, C>(in, out, b, g, co, s); break;
+    case 3: tb2d<S, 3, C>(in, out, b, g, co, s); break;
+    case 4: tb2d<S, 4, C>(in, out, b, g, co, s); break;
+    case 5: tb2d<S, 5, C>(in, out, b, g, co, s); break;
+    case 6: tb2d<S, 6, C>(in, out, b, g, co, s); break;
+    case 7: tb2d<S, 7, C>(in, out, b, g, co, s); break;
+    default: tb2d<S, 8, C>(in, out, b, g, co, s); break;
+    }
+}
+
+hipError_t launch_sweep_fused(Fmt f, const void* in, void* out, const void* b, const Geo& g,
+                              const Coefs& co, int T, hipStream_t s)
+{
+    if (g.ndim != 2 || T < 1 || T > kMaxFuse) return hipErrorInvalidValue;
+    SRJ_DISPATCH(f, tb2d_dispatch<S>((const S*)in, (S*)out, (const S*)b, g, co, T, s));
+    return hipGetLastError();
+}
+
+int residual_blocks(const Geo& g)
+{
+    int64_t lines = g.ny * (g.ndim == 3 ? g.nz : 1);
+    return (int)((lines + kResRows - 1) / kResRows);
+}
+
+hipError_t launch_residual(Fmt f, const void* u, const double* b64, const Geo& g, int zero_interior,
+                           double* partials, double* result, hipStream_t s)
+{
+    int nb = residual_blocks(g);
+    SRJ_DISPATCH(f, hipLaunchKernelGGL(k_residual<S>, dim3(nb), dim3(256), 0, s, (const S*)u, b64, g,
+                                       zero_interior, partials));
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, s, partials, nb, result);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual_to_lo(Fmt f, const double* u64, const double* b64, void* rlo, const Geo& g,
+                                 double* partials, double* result, hipStream_t s)
+{
+    int nb = residual_blocks(g);
+    SRJ_DISPATCH(f, hipLaunchKernelGGL(k_residual_to_lo<S>, dim3(nb), dim3(256), 0, s, u64, b64, (S*)rlo, g,
+                                       partials));
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, s, partials, nb, result);
+    return hipGetLastError();
+}
+
+hipError_t launch_update(Fmt f, double* u64, const void* d, const Geo& g, hipStream_t s)
+{
+    int64_t n = (g.ndim == 3 ? g.nz : 1) * g.ny * g.nx;
+    SRJ_DISPATCH(f, hipLaunchKernelGGL(k_update<S>, grid1d(n), dim3(256), 0, s, u64, (const S*)d, g));
+    return hipGetLastError();
+}
+
+}  // namespace srj

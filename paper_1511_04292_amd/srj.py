@@ -1,0 +1,252 @@
+"""Thin ctypes binding of libsrj (include/srj.h): argument marshalling only.
+
+Every step of the solver runs in the HIP library; PyTorch supplies device memory (float64
+CUDA tensors, dense, ring included) and the current stream.  The library must have been
+built (``__graft_entry__.build()`` or ``python paper_1511_04292_amd/build.py``); importing
+this module without it raises -- there is no fallback path.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SO = os.path.join(HERE, "libsrj.so")
+
+SRJ_F64, SRJ_F32, SRJ_BF16 = 0, 1, 2
+DTYPES = {"f64": SRJ_F64, "f32": SRJ_F32, "bf16": SRJ_BF16}
+MAX_LEVELS = 16
+STATUS = {0: "ok", 1: "einval", 2: "enomem", 3: "ehip", 4: "eschedule", 5: "enoconv", 6: "ediverged"}
+
+
+class SrjError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("n", ctypes.c_int64 * 3), ("h", ctypes.c_double),
+                ("dtype", ctypes.c_int32)]
+
+
+class _Schedule(ctypes.Structure):
+    _fields_ = [("P", ctypes.c_int32), ("omega", ctypes.POINTER(ctypes.c_double)),
+                ("q", ctypes.POINTER(ctypes.c_int64)), ("kappa_min", ctypes.c_double),
+                ("ordering", ctypes.c_int32), ("sequence", ctypes.POINTER(ctypes.c_int32)),
+                ("M", ctypes.c_int64)]
+
+
+class _Desc(ctypes.Structure):
+    _fields_ = [("P", ctypes.c_int32), ("M", ctypes.c_int64),
+                ("omega", ctypes.c_double * MAX_LEVELS), ("beta", ctypes.c_double * MAX_LEVELS),
+                ("q", ctypes.c_int64 * MAX_LEVELS), ("kappa_min", ctypes.c_double),
+                ("kappa_max", ctypes.c_double), ("rho", ctypes.c_double),
+                ("gamma_q_max", ctypes.c_double), ("prefix_peak_log10", ctypes.c_double),
+                ("suffix_peak_log10", ctypes.c_double), ("fused_sweeps", ctypes.c_int32)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("sweeps", ctypes.c_int64), ("cycles", ctypes.c_int64), ("relres", ctypes.c_double),
+                ("seconds", ctypes.c_double), ("status", ctypes.c_int32)]
+
+
+_lib = None
+
+EXPORTS = ["srj_plan", "srj_plan_destroy", "srj_plan_describe", "srj_plan_sequence",
+           "srj_plan_set_fusion", "srj_solve", "srj_sweeps", "srj_residual", "srj_solve_ir",
+           "srj_schedule_optimal", "srj_schedule_order", "srj_status_string", "srj_last_error"]
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(SO):
+        raise ImportError(f"libsrj.so is not built ({SO}); run __graft_entry__.build()")
+    L = ctypes.CDLL(SO)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    L.srj_plan.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Schedule), vp, ctypes.POINTER(vp)]
+    L.srj_plan_destroy.argtypes = [vp]
+    L.srj_plan_destroy.restype = None
+    L.srj_plan_describe.argtypes = [vp, ctypes.POINTER(_Desc)]
+    L.srj_plan_sequence.argtypes = [vp, ctypes.POINTER(i32), i64]
+    L.srj_plan_set_fusion.argtypes = [vp, i32]
+    L.srj_solve.argtypes = [vp, vp, vp, dbl, i64, ctypes.POINTER(_Info)]
+    L.srj_sweeps.argtypes = [vp, vp, vp, i64, i64]
+    L.srj_residual.argtypes = [vp, vp, vp, vp, ctypes.POINTER(dbl)]
+    L.srj_solve_ir.argtypes = [vp, vp, vp, dbl, i32, i32, ctypes.POINTER(_Info)]
+    L.srj_schedule_optimal.argtypes = [i32, dbl, dbl, ctypes.POINTER(dbl), ctypes.POINTER(dbl),
+                                       ctypes.POINTER(i64), ctypes.POINTER(dbl)]
+    L.srj_schedule_order.argtypes = [i32, ctypes.POINTER(dbl), ctypes.POINTER(i64), dbl, dbl, i32,
+                                     ctypes.POINTER(i32)]
+    L.srj_status_string.argtypes = [i32]
+    L.srj_status_string.restype = ctypes.c_char_p
+    L.srj_last_error.argtypes = []
+    L.srj_last_error.restype = ctypes.c_char_p
+    for name in ["srj_plan", "srj_plan_describe", "srj_plan_sequence", "srj_plan_set_fusion", "srj_solve",
+                 "srj_sweeps", "srj_residual", "srj_solve_ir", "srj_schedule_optimal", "srj_schedule_order"]:
+        getattr(L, name).restype = i32
+    _lib = L
+    return L
+
+
+def _check(st, allowed=(0,)):
+    if st not in allowed:
+        raise SrjError(st, lib().srj_last_error().decode())
+    return st
+
+
+def _dptr(t, shape=None):
+    import torch
+
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a CUDA tensor")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError("expected a contiguous float64 tensor")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"expected shape {tuple(shape)}, got {tuple(t.shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_handle():
+    import torch
+
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Plan:
+    """Owns an srj_plan_t; destroyed with the object."""
+
+    def __init__(self, handle, n, ndim):
+        self.handle = handle
+        self.n = tuple(n)
+        self.ndim = ndim
+
+    @property
+    def full_shape(self):
+        return tuple(x + 2 for x in reversed(self.n[:self.ndim]))
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            _lib.srj_plan_destroy(h)
+            self.handle = None
+
+
+def srj_plan(n, h, P=None, omega=None, q=None, kappa_min=0.0, ordering=0, sequence=None,
+             dtype="f64", stream=None):
+    """Create a plan for a grid of interior sizes n = (n_x, n_y[, n_z]) and spacing h.
+
+    Either P (optimised schedule) or omega/q (explicit) is given; ordering 0 balanced,
+    1 even spread, 2 explicit sequence.
+    """
+    L = lib()
+    g = _Grid()
+    g.ndim = len(n)
+    for i, v in enumerate(n):
+        g.n[i] = int(v)
+    g.h = float(h)
+    g.dtype = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
+    s = _Schedule()
+    keep = []
+    if omega is not None:
+        w = np.ascontiguousarray(omega, dtype=np.float64)
+        qq = np.ascontiguousarray(q, dtype=np.int64)
+        keep += [w, qq]
+        s.P = len(w)
+        s.omega = w.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        s.q = qq.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    else:
+        s.P = int(P)
+    s.kappa_min = float(kappa_min)
+    s.ordering = int(ordering)
+    if sequence is not None:
+        sq = np.ascontiguousarray(sequence, dtype=np.int32)
+        keep.append(sq)
+        s.sequence = sq.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        s.M = len(sq)
+        s.ordering = 2
+    out = ctypes.c_void_p()
+    st = stream if stream is not None else _stream_handle()
+    _check(L.srj_plan(ctypes.byref(g), ctypes.byref(s), st, ctypes.byref(out)))
+    return Plan(out, n, len(n))
+
+
+def srj_plan_describe(plan):
+    d = _Desc()
+    _check(lib().srj_plan_describe(plan.handle, ctypes.byref(d)))
+    P = d.P
+    return dict(P=P, M=d.M, omega=np.array(d.omega[:P]), beta=np.array(d.beta[:P]),
+                q=np.array(d.q[:P], dtype=np.int64), kappa_min=d.kappa_min, kappa_max=d.kappa_max,
+                rho=d.rho, gamma_q_max=d.gamma_q_max, prefix_peak_log10=d.prefix_peak_log10,
+                suffix_peak_log10=d.suffix_peak_log10, fused_sweeps=d.fused_sweeps)
+
+
+def srj_plan_sequence(plan):
+    M = srj_plan_describe(plan)["M"]
+    seq = np.zeros(M, dtype=np.int32)
+    _check(lib().srj_plan_sequence(plan.handle, seq.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), M))
+    return seq
+
+
+def srj_plan_set_fusion(plan, fused):
+    _check(lib().srj_plan_set_fusion(plan.handle, int(fused)))
+
+
+def _info(i):
+    return dict(sweeps=i.sweeps, cycles=i.cycles, relres=i.relres, seconds=i.seconds,
+                status=STATUS.get(i.status, i.status))
+
+
+def srj_solve(plan, u, f, tol, max_sweeps, raise_on_noconv=False):
+    """Solve in place on u; returns the info dict (status 'ok' | 'enoconv' | 'ediverged')."""
+    info = _Info()
+    st = lib().srj_solve(plan.handle, _dptr(u, plan.full_shape), _dptr(f, plan.full_shape), float(tol),
+                         int(max_sweeps), ctypes.byref(info))
+    _check(st, (0, 5, 6) if not raise_on_noconv else (0,))
+    return _info(info)
+
+
+def srj_sweeps(plan, u, f, k0, nsweeps):
+    _check(lib().srj_sweeps(plan.handle, _dptr(u, plan.full_shape), _dptr(f, plan.full_shape), int(k0),
+                            int(nsweeps)))
+
+
+def srj_residual(plan, u, f, r_out=None):
+    norms = (ctypes.c_double * 4)()
+    rp = _dptr(r_out, plan.full_shape) if r_out is not None else None
+    _check(lib().srj_residual(plan.handle, _dptr(u, plan.full_shape), _dptr(f, plan.full_shape), rp, norms))
+    return dict(l2=norms[0], linf=norms[1], source_l2=norms[2], relres=norms[3])
+
+
+def srj_solve_ir(plan, u, f, tol, inner_cycles, max_outer):
+    info = _Info()
+    st = lib().srj_solve_ir(plan.handle, _dptr(u, plan.full_shape), _dptr(f, plan.full_shape), float(tol),
+                            int(inner_cycles), int(max_outer), ctypes.byref(info))
+    _check(st, (0, 5, 6))
+    return _info(info)
+
+
+def srj_schedule_optimal(P, kappa_min, kappa_max=2.0):
+    w = np.zeros(P)
+    b = np.zeros(P)
+    q = np.zeros(P, dtype=np.int64)
+    k = np.zeros(max(P - 1, 1))
+    _check(lib().srj_schedule_optimal(int(P), float(kappa_min), float(kappa_max),
+                                      w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                      b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                      q.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                      k.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return dict(w=w, beta=b, q=q, kappa=k[:P - 1])
+
+
+def srj_schedule_order(omega, q, kappa_min, kappa_max=2.0, ordering=0):
+    w = np.ascontiguousarray(omega, dtype=np.float64)
+    qq = np.ascontiguousarray(q, dtype=np.int64)
+    seq = np.zeros(int(qq.sum()), dtype=np.int32)
+    _check(lib().srj_schedule_order(len(w), w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    qq.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), float(kappa_min),
+                                    float(kappa_max), int(ordering),
+                                    seq.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+    return seq

@@ -1,0 +1,81 @@
+"""The C-ABI library loads, exports every entry point its header declares, and its
+host-only planner agrees with the oracle's (CPU only: no device calls)."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import schedule as S
+from paper_1511_04292_amd import srj
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "srj.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(srj_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(srj.SO)
+    names = header_functions()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(srj.EXPORTS) == names
+
+
+def test_status_strings():
+    L = srj.lib()
+    assert L.srj_status_string(0) == b"ok"
+    assert L.srj_status_string(5) == b"tolerance not reached"
+
+
+@pytest.mark.parametrize("P,N", [(2, 45.957), (3, 100), (5, 500), (8, 362.745), (9, 1448.86),
+                                 (10, 550), (10, 2897.016), (6, 23.3257)])
+def test_planner_matches_oracle(P, N):
+    km = S.kappa_min_neumann(N)
+    o = S.optimal(P, km)
+    m = srj.srj_schedule_optimal(P, km)
+    np.testing.assert_allclose(m["w"], o["w"], rtol=1e-8)
+    np.testing.assert_allclose(m["beta"], o["beta"], rtol=1e-8)
+    np.testing.assert_allclose(m["kappa"], o["kappa"], rtol=1e-7)
+    ratio = o["beta"] / o["beta"][0]
+    qo = S.q_floor(o["beta"])
+    for i in range(P):  # counts agree unless beta_i / beta_1 sits on an integer
+        if abs(ratio[i] - round(ratio[i])) > 1e-7:
+            assert m["q"][i] == qo[i]
+
+
+def test_worked_example_counts_from_product_planner(golden_dir):
+    d = {}
+    for line in open(os.path.join(golden_dir, "worked_example.txt")):
+        if line.strip() and not line.startswith("#"):
+            k, *v = line.split()
+            d[k] = v
+    m = srj.srj_schedule_optimal(10, S.kappa_min_neumann(550.0))
+    assert list(m["q"]) == [int(x) for x in d["q"]]
+    assert [float(f"{x:.6g}") for x in m["w"][:3]] == [float(x) for x in d["omega_head"]]
+
+
+@pytest.mark.parametrize("P,N,ordering", [(2, 45.957, 0), (8, 362.745, 0), (10, 550, 0), (10, 550, 1),
+                                          (6, 100, 0)])
+def test_orderings_match_oracle(P, N, ordering):
+    km = S.kappa_min_neumann(N)
+    o = S.optimal(P, km)
+    q = S.q_floor(o["beta"])
+    ref = S.order_balanced(o["w"], q, km) if ordering == 0 else S.order_even(q)
+    got = srj.srj_schedule_order(o["w"], q, km, 2.0, ordering)
+    assert np.array_equal(got, ref)
+
+
+def test_grid_kappa_min_matches_oracle():
+    # the plan's own kappa_min for a Dirichlet grid equals the oracle's formula
+    for shape in [(64, 64), (4096, 4096), (512, 512, 512), (37, 91)]:
+        d = len(shape)
+        v = (2.0 / d) * sum(math.sin(math.pi / (2.0 * (n + 1))) ** 2 for n in shape)
+        assert v == S.kappa_min_dirichlet(shape)

@@ -1,0 +1,269 @@
+"""GPU parity of the HIP path (through the C ABI) against the CPU oracle.
+
+FP64 sweeps use the same association as the oracle and no fused multiply-add, so the
+iterates must be bit-identical; residual norms are sums in a different order and are
+compared to 1e-12 relative.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import schedule as S
+from oracle import spectral, sweeps
+from paper_1511_04292_amd import srj, workloads
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rand_case(shape_interior, seed):
+    full = tuple(n + 2 for n in reversed(shape_interior))
+    u = workloads.random_state(full, seed)
+    f = workloads.random_state(full, seed + 1000)
+    return u, f
+
+
+def oracle_schedule(P, n_interior, ordering=0):
+    km = S.kappa_min_dirichlet(n_interior)
+    o = S.optimal(P, km)
+    q = S.q_floor(o["beta"])
+    seq = S.order_balanced(o["w"], q, km) if ordering == 0 else S.order_even(q)
+    return o["w"], q, seq
+
+
+_SCHED = {}
+
+
+def shared_schedule(P=3, n_ref=(300, 300)):
+    """Oracle schedule optimised for a 300 x 300 grid; convergent on every smaller grid
+    because their spectra lie inside its interval."""
+    key = (P, n_ref)
+    if key not in _SCHED:
+        _SCHED[key] = oracle_schedule(P, n_ref)
+    return _SCHED[key]
+
+
+def big_first(P=3):
+    """The shared schedule rotated so that its largest weight is applied first."""
+    w, q, seq = shared_schedule(P)
+    k = int(np.argmax(np.asarray(seq) == 0))
+    return w, q, np.roll(seq, -k)
+
+
+def explicit_plan(n, h, w, q, seq, dtype="f64", fuse=None):
+    p = srj.srj_plan(n, h, omega=w, q=q, sequence=seq, dtype=dtype)
+    if fuse is not None:
+        srj.srj_plan_set_fusion(p, fuse)
+    return p
+
+
+# ------------------------------------------------------------------ single sweeps
+
+@pytest.mark.parametrize("n", [(1, 1), (2, 3), (67, 45), (130, 257), (1, 9), (300, 2)])
+def test_single_sweep_2d_bitwise(n):
+    h = 1.0 / (max(n) + 1)
+    u, f = rand_case(n, 1)
+    w, q, seq = big_first()
+    p = explicit_plan(n, h, w, q, seq, fuse=0)
+    ug = dev(u)
+    srj.srj_sweeps(p, ug, dev(f), 0, 1)
+    ref = sweeps.sweep(u, sweeps.rhs(f, h), w[0] / 4.0)
+    assert np.array_equal(host(ug), ref)
+
+
+@pytest.mark.parametrize("n", [(1, 1, 1), (5, 7, 3), (33, 17, 40), (64, 1, 9)])
+def test_single_sweep_3d_bitwise(n):
+    h = 1.0 / (max(n) + 1)
+    u, f = rand_case(n, 2)
+    w, q, seq = big_first()
+    p = explicit_plan(n, h, w, q, seq)
+    ug = dev(u)
+    srj.srj_sweeps(p, ug, dev(f), 0, 1)
+    ref = sweeps.sweep(u, sweeps.rhs(f, h), w[0] / 6.0)
+    assert np.array_equal(host(ug), ref)
+
+
+# ------------------------------------------------------- temporally blocked sweeps
+
+@pytest.mark.parametrize("T", [1, 2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("n", [(300, 200), (129, 150), (2, 2), (1, 70), (250, 1)])
+def test_fused_sweeps_bitwise(T, n):
+    h = 1.0 / (max(n) + 1)
+    u, f = rand_case(n, 3)
+    w, q, seq = shared_schedule()
+    nsweeps = 2 * len(seq) + 5  # crosses cycle ends and leaves a ragged last launch
+    p = explicit_plan(n, h, w, q, seq, fuse=T)
+    ug = dev(u)
+    srj.srj_sweeps(p, ug, dev(f), 3, nsweeps)
+    c = sweeps.coefficients(np.array(w)[seq], 2)
+    ref = sweeps.run(u, sweeps.rhs(f, h), c, nsweeps, k0=3)
+    assert np.array_equal(host(ug), ref)
+
+
+def test_fused_equals_unfused_on_gpu():
+    n = (517, 389)
+    h = 1.0 / 518
+    u, f = rand_case(n, 4)
+    w, q, seq = oracle_schedule(5, n)
+    outs = []
+    for T in (0, 8):
+        p = explicit_plan(n, h, w, q, seq, fuse=T)
+        ug = dev(u)
+        srj.srj_sweeps(p, ug, dev(f), 0, 2 * int(np.sum(q)) + 3)
+        outs.append(host(ug))
+    assert np.array_equal(outs[0], outs[1])
+
+
+# ------------------------------------------------------------------ residuals
+
+@pytest.mark.parametrize("n", [(64, 64), (123, 77), (9, 10, 11)])
+def test_residual_norms(n):
+    h = 1.0 / (max(n) + 1)
+    u, f = rand_case(n, 5)
+    p = srj.srj_plan(n, h, omega=[1.0], q=[1])
+    r = torch.zeros_like(dev(u))
+    got = srj.srj_residual(p, dev(u), dev(f), r)
+    b = sweeps.rhs(f, h)
+    r2, rmax = sweeps.residual_norms(u, b)
+    bt2 = sweeps.source_norm2(u, b)
+    assert math.isclose(got["l2"], math.sqrt(r2), rel_tol=1e-12)
+    assert got["linf"] == rmax
+    assert math.isclose(got["source_l2"], math.sqrt(bt2), rel_tol=1e-12)
+    assert np.array_equal(host(r), sweeps.residual_field(u, b))
+
+
+# ------------------------------------------------------------------ solves
+
+def test_solve_small_2d_srj_matches_oracle():
+    wl = workloads.small_2d(64, seed=0)
+    w, q, seq = oracle_schedule(2, wl["n"])
+    wseq = np.array(w)[seq]
+    ref = sweeps.solve(wl["u0"], wl["f"], wl["h"], wseq, 1e-10, 10 ** 6)
+    for fuse in (0, 8):
+        p = explicit_plan(wl["n"], wl["h"], w, q, seq, fuse=fuse)
+        ug = dev(wl["u0"])
+        info = srj.srj_solve(p, ug, dev(wl["f"]), 1e-10, 10 ** 6)
+        assert info["status"] == "ok" and ref["status"] == "ok"
+        assert info["sweeps"] == ref["sweeps"]
+        assert abs(info["relres"] - ref["relres"]) <= 1e-12 * ref["relres"]
+        assert np.array_equal(host(ug), ref["u"])
+    # the converged iterate is within the conditioning bound of the exact discrete solution
+    us = spectral.exact_solve(wl["u0"], sweeps.rhs(wl["f"], wl["h"]))
+    cond = math.cos(math.pi / 130) ** 2 / math.sin(math.pi / 130) ** 2
+    assert np.max(np.abs(ref["u"] - us)) <= cond * 1e-10 * np.max(np.abs(us))
+
+
+def test_solve_jacobi_matches_oracle():
+    wl = workloads.small_2d(20, seed=1)
+    ref = sweeps.solve(wl["u0"], wl["f"], wl["h"], [1.0], 1e-6, 10 ** 6)
+    p = srj.srj_plan(wl["n"], wl["h"], omega=[1.0], q=[1])
+    ug = dev(wl["u0"])
+    info = srj.srj_solve(p, ug, dev(wl["f"]), 1e-6, 10 ** 6)
+    assert info["sweeps"] == ref["sweeps"]
+    assert np.array_equal(host(ug), ref["u"])
+
+
+def test_solve_3d_matches_oracle():
+    n = (20, 17, 23)
+    h = 1.0 / 24
+    rng = np.random.default_rng(7)
+    full = tuple(x + 2 for x in reversed(n))
+    u0 = workloads.random_ring(full, rng)
+    f = rng.standard_normal(full)
+    w, q, seq = oracle_schedule(4, n)
+    wseq = np.array(w)[seq]
+    ref = sweeps.solve(u0, f, h, wseq, 1e-10, 10 ** 6)
+    p = explicit_plan(n, h, w, q, seq)
+    ug = dev(u0)
+    info = srj.srj_solve(p, ug, dev(f), 1e-10, 10 ** 6)
+    assert info["sweeps"] == ref["sweeps"]
+    assert np.array_equal(host(ug), ref["u"])
+
+
+def test_product_planner_plan_solves_cfg_small():
+    # a plan that runs its own optimiser and ordering converges and reports its schedule
+    wl = workloads.small_2d(64, seed=0)
+    p = srj.srj_plan(wl["n"], wl["h"], P=2)
+    d = srj.srj_plan_describe(p)
+    assert d["M"] == int(np.sum(d["q"])) and d["gamma_q_max"] < 1
+    ug = dev(wl["u0"])
+    info = srj.srj_solve(p, ug, dev(wl["f"]), 1e-10, 10 ** 6)
+    assert info["status"] == "ok" and info["relres"] <= 1e-10
+
+
+# ----------------------------------------------------------- reduced precision
+
+@pytest.mark.parametrize("fmt", ["f32", "bf16"])
+@pytest.mark.parametrize("fuse", [0, 5, 8])
+def test_lowprec_sweeps_bitwise(fmt, fuse):
+    n = (200, 131)
+    h = 1.0 / 201
+    u, f = rand_case(n, 8)
+    w, q, seq = big_first()
+    nsw = 17
+    p = explicit_plan(n, h, w, q, seq, dtype=fmt, fuse=fuse)
+    ug = dev(u)
+    srj.srj_sweeps(p, ug, dev(f), 0, nsw)
+    c32 = sweeps.lo_coefficients(np.array(w)[seq], 2)
+    x = sweeps.lo_cast(u, fmt)
+    b = sweeps.lo_cast(sweeps.rhs(f, h), fmt)
+    for s in range(nsw):
+        x = sweeps.sweep_lo(x, b, c32[s % len(seq)], fmt)
+    ref = sweeps.lo_widen(x, fmt)
+    got = host(ug)
+    inner = (slice(1, -1), slice(1, -1))
+    assert np.array_equal(got[inner], ref[inner])
+
+
+@pytest.mark.parametrize("fmt", ["f32", "bf16"])
+def test_ir_matches_oracle(fmt):
+    wl = workloads.small_2d(63, seed=4)
+    w, q, seq = oracle_schedule(4, wl["n"])
+    wseq = np.array(w)[seq]
+    ref = sweeps.solve_ir(wl["u0"], wl["f"], wl["h"], wseq, 1e-10, 1, 60, fmt)
+    p = explicit_plan(wl["n"], wl["h"], w, q, seq, dtype=fmt)
+    ug = dev(wl["u0"])
+    info = srj.srj_solve_ir(p, ug, dev(wl["f"]), 1e-10, 1, 60)
+    assert ref["status"] == "ok" and info["status"] == "ok"
+    assert info["cycles"] == ref["outer"]
+    assert abs(info["relres"] - ref["relres"]) <= 1e-12 * ref["relres"]
+    assert np.array_equal(host(ug), ref["u"])
+
+
+# ------------------------------------------------------------------ error paths
+
+def test_errors():
+    with pytest.raises(srj.SrjError) as e:
+        srj.srj_plan((0, 5), 0.1, omega=[1.0], q=[1])
+    assert e.value.status == 1
+    with pytest.raises(srj.SrjError) as e:
+        srj.srj_plan((5, 5), 0.1, omega=[3.0], q=[1])  # |1 - 3 kappa| > 1 near kappa = 2
+    assert e.value.status == 4
+    with pytest.raises(srj.SrjError) as e:
+        srj.srj_plan((5, 5), 0.1, omega=[1.0, 2.0], q=[1, 1])  # not descending
+    assert e.value.status == 1
+    wl = workloads.small_2d(16, seed=2)
+    p = srj.srj_plan(wl["n"], wl["h"], omega=[1.0], q=[1])
+    info = srj.srj_solve(p, dev(wl["u0"]), dev(wl["f"]), 1e-10, 10)
+    assert info["status"] == "enoconv" and info["sweeps"] == 10
+    f = wl["f"].copy()
+    f[4, 4] = np.nan
+    info = srj.srj_solve(p, dev(wl["u0"]), dev(f), 1e-10, 10)
+    assert info["status"] == "ediverged"
+    z = np.zeros_like(wl["f"])
+    ug = dev(z + 0.0)
+    ug[3, 3] = 7.0
+    info = srj.srj_solve(p, ug, dev(z), 1e-10, 10)
+    assert info["status"] == "ok" and info["sweeps"] == 0 and float(ug.abs().max()) == 0.0
