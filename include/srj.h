@@ -106,7 +106,8 @@ typedef struct {
 
 typedef struct srj_plan_s* srj_plan_t;
 
-/* Create a plan: validates the grid, builds the schedule, uploads c_k = w_k / (2d),
+/* Create a plan: validates the grid, builds the schedule and its coefficient sequence
+ * c_k = w_k / (2d),
  * allocates the plan-owned device buffers (two iterate buffers in the sweep format, the
  * scaled source, reduction scratch).  Returns SRJ_ESCHEDULE if the optimiser fails or
  * the integer scheme is not convergent on the grid's spectrum. */
@@ -116,8 +117,10 @@ void srj_plan_destroy(srj_plan_t plan);
 srj_status srj_plan_describe(srj_plan_t plan, srj_plan_desc* out);
 /* Copy the ordered level indices of one cycle (cap >= M) into seq. */
 srj_status srj_plan_sequence(srj_plan_t plan, int32_t* seq, int64_t cap);
-/* Override the number of sweeps fused per launch (0 = unfused reference kernel). */
-srj_status srj_plan_set_fusion(srj_plan_t plan, int32_t fused_sweeps);
+/* Override the number of sweeps fused per launch (0 = unfused reference kernel, at most 8)
+ * and, if seg_rows > 0, the output rows each wave of the fused 2D kernel computes.  The
+ * results do not depend on either value. */
+srj_status srj_plan_set_fusion(srj_plan_t plan, int32_t fused_sweeps, int32_t seg_rows);
 
 /* Solve to ||r||_2 / ||b~||_2 <= tol, checked at sweep 0 and at every cycle end (every
  * sweep for M = 1).  Stops with SRJ_ENOCONV when the next cycle would exceed max_sweeps
@@ -127,8 +130,11 @@ srj_status srj_solve(srj_plan_t plan, double* u, const double* f, double tol, in
                      srj_solve_info* info);
 
 /* Apply exactly nsweeps scheduled sweeps to u, the first one being step k0 (mod M) of the
- * cycle.  No convergence checks. */
-srj_status srj_sweeps(srj_plan_t plan, double* u, const double* f, int64_t k0, int64_t nsweeps);
+ * cycle.  No convergence checks.  If stats is not NULL, stats[0] receives the device time
+ * in seconds of the sweep launches alone (HIP events on the plan's stream around them) and
+ * stats[1] the number of kernel launches they took. */
+srj_status srj_sweeps(srj_plan_t plan, double* u, const double* f, int64_t k0, int64_t nsweeps,
+                      double* stats);
 
 /* norms[0] = ||r||_2, norms[1] = max |r|, norms[2] = ||b~||_2, norms[3] = relres, for
  * r = b - A u in binary64.  r_out (device, full-grid layout, ring set to 0) may be NULL. */

@@ -61,6 +61,7 @@ struct srj_plan_s {
     std::vector<double> cseq;  // c_k = w_seq[k] / (2d)
     double kappa_min = 0, kappa_max = 0, rho = 0, gamma_q = 0, pre = 0, suf = 0;
     int fuse = 8;
+    int seg_rows = 64;  // output rows per wave in the fused 2D kernel
 
     // device buffers
     DField A, B, blo, b64f;  // iterate pair, b in the sweep format, FP64 b (low-precision plans)
@@ -183,7 +184,8 @@ srj_status residual_now(srj_plan_t p, const void* u, Fmt f, int zero_int, double
 
 // Run sweeps k0 .. k0+n-1 on the ping-pong pair; *cur is updated to the buffer holding the
 // result.  Fused launches never straddle a cycle boundary.
-srj_status run_sweeps(srj_plan_t p, DField** cur, DField** nxt, const void* b, int64_t k0, int64_t n)
+srj_status run_sweeps(srj_plan_t p, DField** cur, DField** nxt, const void* b, int64_t k0, int64_t n,
+                      int64_t* launches = nullptr)
 {
     int64_t k = k0;
     const int64_t end = k0 + n;
@@ -197,9 +199,11 @@ srj_status run_sweeps(srj_plan_t p, DField** cur, DField** nxt, const void* b, i
             int T = (int)std::min<int64_t>({(int64_t)p->fuse, end - k, to_cycle_end});
             Coefs co;
             for (int l = 0; l < T; ++l) co.c[l] = p->cseq[(k + l) % p->M];
-            HIPCHK(launch_sweep_fused(p->fmt, (*cur)->origin, (*nxt)->origin, b, p->geo, co, T, p->stream));
+            HIPCHK(launch_sweep_fused(p->fmt, (*cur)->origin, (*nxt)->origin, b, p->geo, co, T, p->seg_rows,
+                                      p->stream));
             k += T;
         }
+        if (launches) *launches += 1;
         std::swap(*cur, *nxt);
     }
     return SRJ_OK;
@@ -333,12 +337,14 @@ srj_status srj_plan_sequence(srj_plan_t p, int32_t* seq, int64_t cap)
     return SRJ_OK;
 }
 
-srj_status srj_plan_set_fusion(srj_plan_t p, int32_t fused)
+srj_status srj_plan_set_fusion(srj_plan_t p, int32_t fused, int32_t seg_rows)
 {
     if (!p) return fail(SRJ_EINVAL, "null plan");
     if (fused < 0 || fused > kMaxFuse) return fail(SRJ_EINVAL, "fusion depth must be in [0, 8]");
     if (fused > 0 && p->geo.ndim != 2) return fail(SRJ_EINVAL, "fused sweeps are 2D only");
+    if (seg_rows < 0 || seg_rows > (1 << 20)) return fail(SRJ_EINVAL, "segment rows must be in [0, 2^20]");
     p->fuse = fused;
+    if (seg_rows > 0) p->seg_rows = seg_rows;
     return SRJ_OK;
 }
 
@@ -375,7 +381,7 @@ srj_status srj_residual(srj_plan_t p, const double* u, const double* f, double* 
     return SRJ_OK;
 }
 
-srj_status srj_sweeps(srj_plan_t p, double* u, const double* f, int64_t k0, int64_t n)
+srj_status srj_sweeps(srj_plan_t p, double* u, const double* f, int64_t k0, int64_t n, double* stats)
 {
     if (!p || !u || !f) return fail(SRJ_EINVAL, "null argument");
     if (k0 < 0 || n < 0) return fail(SRJ_EINVAL, "k0 and nsweeps must be >= 0");
@@ -384,10 +390,19 @@ srj_status srj_sweeps(srj_plan_t p, double* u, const double* f, int64_t k0, int6
     HIPCHK(launch_copy_in(p->fmt, u, p->B.origin, p->geo, p->stream));
     HIPCHK(launch_rhs(p->fmt, f, hh, p->blo.origin, p->fmt == FMT_F64 ? nullptr : p->b64, p->geo, p->stream));
     DField *cur = &p->A, *nxt = &p->B;
-    srj_status st = run_sweeps(p, &cur, &nxt, p->blo.origin, k0 % p->M, n);
+    int64_t launches = 0;
+    HIPCHK(hipEventRecord(p->ev0, p->stream));
+    srj_status st = run_sweeps(p, &cur, &nxt, p->blo.origin, k0 % p->M, n, &launches);
     if (st != SRJ_OK) return st;
+    HIPCHK(hipEventRecord(p->ev1, p->stream));
     HIPCHK(launch_copy_out(p->fmt, cur->origin, u, p->geo, p->stream));
     HIPCHK(hipStreamSynchronize(p->stream));
+    if (stats) {
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, p->ev0, p->ev1));
+        stats[0] = ms * 1e-3;
+        stats[1] = (double)launches;
+    }
     return SRJ_OK;
 }
 

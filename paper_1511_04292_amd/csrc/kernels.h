@@ -32,13 +32,13 @@ hipError_t launch_copy_out(Fmt f, const void* field, double* user, const Geo& g,
 // b = (h*h) * f on the interior: blo in format f (may be null), b64 in FP64 (may be null)
 hipError_t launch_rhs(Fmt f, const double* user_f, double hh, void* blo, double* b64, const Geo& g,
                       hipStream_t s);
-// T consecutive sweeps in -> out with coefficients co.c[0..T).  T = 0 selects nothing;
-// fused = false runs T unfused launches (ping-pong through `tmp`, which must then be a
-// third buffer or equal to `in` when T is odd... see caller).
+// One sweep in -> out with coefficient c (2D or 3D).
 hipError_t launch_sweep_unfused(Fmt f, const void* in, void* out, const void* b, const Geo& g,
                                 double c, hipStream_t s);
+// T consecutive 2D sweeps in -> out in one launch with coefficients co.c[0..T), row
+// segments of H output rows per wave.
 hipError_t launch_sweep_fused(Fmt f, const void* in, void* out, const void* b, const Geo& g,
-                              const Coefs& co, int T, hipStream_t s);
+                              const Coefs& co, int T, int H, hipStream_t s);
 // sum r^2 and max |r| of r = b64 - A u (binary64); zero_interior treats u's interior as 0.
 // partials must hold 2 * residual_blocks(g) doubles; result receives {sum, max}.
 int residual_blocks(const Geo& g);

@@ -9,68 +9,19 @@
 // bit-identical iterates for the same sweep sequence.  Storage formats: binary64,
 // binary32, and bfloat16 (binary32 arithmetic, round-to-nearest-even on every store).
 //
-// The sweep is bound by HBM bandwidth (0.3 flop per byte unfused), so no kernel here uses
-// the matrix cores.  The 2D temporally-blocked kernel gives each wavefront a strip of
-// 64*C columns (C per lane) and a segment of rows, streams the rows from top to bottom
-// and keeps T time levels of a 3-row window in registers: one HBM read of u and b and one
-// write of u serve T sweeps.  Horizontal neighbours cross lanes by shuffles; no LDS and no
-// barriers are needed because every wave is independent (strips overlap by T columns
-// on each side, segments by T rows, the overlap being recomputed).
+// The sweep is bound by HBM bandwidth (0.3 flop per byte unfused), so no kernel uses the
+// matrix cores.  This file holds the unfused sweeps, data movement, residual reductions
+// and refinement helpers; the temporally blocked 2D sweep is in sweep2d_tb.hip.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
 
+#include "formats.h"
 #include "kernels.h"
 
 namespace srj {
 
 size_t fmt_size(Fmt f) { return f == FMT_F64 ? 8 : (f == FMT_F32 ? 4 : 2); }
-
-// ------------------------------------------------------------------- formats
-
-struct bf16_t {
-    uint16_t v;
-};
-
-template <class S> struct Tr;
-template <> struct Tr<double> {
-    using C = double;
-    static __device__ __forceinline__ double ld(double x) { return x; }
-    static __device__ __forceinline__ double st(double x) { return x; }
-    static __device__ __forceinline__ double from64(double x) { return x; }
-};
-template <> struct Tr<float> {
-    using C = float;
-    static __device__ __forceinline__ float ld(float x) { return x; }
-    static __device__ __forceinline__ float st(float x) { return x; }
-    static __device__ __forceinline__ float from64(double x) { return (float)x; }
-};
-template <> struct Tr<bf16_t> {
-    using C = float;
-    static __device__ __forceinline__ float ld(bf16_t x) { return __uint_as_float((uint32_t)x.v << 16); }
-    static __device__ __forceinline__ bf16_t st(float f)
-    {
-        uint32_t x = __float_as_uint(f);
-        bf16_t r;
-        if ((x & 0x7fffffffu) > 0x7f800000u) {
-            r.v = (uint16_t)((x >> 16) | 0x40u);
-        } else {
-            x += 0x7fffu + ((x >> 16) & 1u);
-            r.v = (uint16_t)(x >> 16);
-        }
-        return r;
-    }
-    // binary64 -> binary32 (round to nearest) -> bfloat16 (round to nearest even)
-    static __device__ __forceinline__ bf16_t from64(double x) { return st((float)x); }
-};
-
-template <class S> __device__ __forceinline__ S zero_of();
-template <> __device__ __forceinline__ double zero_of<double>() { return 0.0; }
-template <> __device__ __forceinline__ float zero_of<float>() { return 0.0f; }
-template <> __device__ __forceinline__ bf16_t zero_of<bf16_t>() { return bf16_t{0}; }
-
-template <class C> __device__ __forceinline__ C shfl_up1(C v) { return __shfl_up(v, 1, 64); }
-template <class C> __device__ __forceinline__ C shfl_dn1(C v) { return __shfl_down(v, 1, 64); }
 
 // ------------------------------------------------------------ copy / rhs / fill
 
@@ -179,127 +130,6 @@ __global__ __launch_bounds__(256) void k_sweep3d(const S* __restrict__ u, S* __r
         o[p] = Tr<S>::st(m + c * t);
         dn = m;
         m = up;
-    }
-}
-
-// --------------------------------------------------- temporally blocked 2D sweeps
-
-template <int T> struct CoefsT {
-    double c[T];
-};
-
-// Wave layout: strip `st` covers columns x0 .. x0 + 64C - 1 with x0 = 1 + st*SW - T
-// (SW = 64C - 2T output columns per strip); segment `sg` outputs rows y0 .. y1-1.
-// At step r the wave loads row r (level 0) and computes level l for row r - l,
-// l = 1..T, from level l-1 rows r-l-1, r-l, r-l+1.  Ring rows/columns never change,
-// columns outside the grid are held at 0, and only points whose dependence cone lies
-// inside the loaded window are stored.
-template <class S, int T, int C>
-__global__ __launch_bounds__(256) void k_sweep2d_tb(const S* __restrict__ uin, S* __restrict__ uout,
-                                                    const S* __restrict__ bb, int64_t px, int nx,
-                                                    int ny, CoefsT<T> co, int nstrip, int nwaves,
-                                                    int H)
-{
-    using Cm = typename Tr<S>::C;
-    constexpr int SW = 64 * C - 2 * T;
-    const int lane = threadIdx.x & 63;
-    const int wid = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (wid >= nwaves) return;
-    const int st = wid % nstrip;
-    const int sg = wid / nstrip;
-    const int64_t x0 = 1 + (int64_t)st * SW - T + (int64_t)lane * C;
-    const int y0 = 1 + sg * H;
-    const int y1 = min(y0 + H, ny + 1);
-    const int rb = max(0, y0 - T);
-    const int rl = y1 - 1 + T;
-
-    bool live[C], upd[C], outc[C];
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-        const int64_t x = x0 + c;
-        const int off = lane * C + c;
-        live[c] = (x >= 0 && x <= (int64_t)nx + 1);
-        upd[c] = (x >= 1 && x <= (int64_t)nx);
-        outc[c] = upd[c] && off >= T && off < 64 * C - T;
-    }
-    Cm cf[T];
-#pragma unroll
-    for (int l = 0; l < T; ++l) cf[l] = (Cm)co.c[l];
-
-    Cm p1[T][C], p2[T][C], bq[T][C];
-#pragma unroll
-    for (int l = 0; l < T; ++l)
-#pragma unroll
-        for (int c = 0; c < C; ++c) p1[l][c] = p2[l][c] = bq[l][c] = (Cm)0;
-
-    Cm cu[C], cb[C];
-    auto load_row = [&](int r, Cm* vu, Cm* vb) {
-        if (r <= ny + 1) {
-            const S* pu = uin + (int64_t)r * px + x0;
-            const S* pb = bb + (int64_t)r * px + x0;
-#pragma unroll
-            for (int c = 0; c < C; ++c) {
-                vu[c] = live[c] ? Tr<S>::ld(pu[c]) : (Cm)0;
-                vb[c] = (live[c] && r >= 1 && r <= ny) ? Tr<S>::ld(pb[c]) : (Cm)0;
-            }
-        } else {
-#pragma unroll
-            for (int c = 0; c < C; ++c) vu[c] = vb[c] = (Cm)0;
-        }
-    };
-    load_row(rb, cu, cb);
-
-    for (int r = rb; r <= rl; ++r) {
-        Cm nu[C], nb[C];
-        load_row(r + 1, nu, nb);
-        Cm in[C];
-#pragma unroll
-        for (int c = 0; c < C; ++c) in[c] = cu[c];
-#pragma unroll
-        for (int l = 1; l <= T; ++l) {
-            const int j = r - l;
-            Cm out[C];
-            if (j >= 1 && j <= ny) {
-                const Cm wn = shfl_up1(p1[l - 1][C - 1]);
-                const Cm en = shfl_dn1(p1[l - 1][0]);
-#pragma unroll
-                for (int c = 0; c < C; ++c) {
-                    const Cm W = (c == 0) ? wn : p1[l - 1][c - 1];
-                    const Cm E = (c == C - 1) ? en : p1[l - 1][c + 1];
-                    const Cm m = p1[l - 1][c];
-                    const Cm s = (W + E) + (p2[l - 1][c] + in[c]);
-                    const Cm t = (s + bq[l - 1][c]) - (Cm)4 * m;
-                    const Cm v = Tr<S>::ld(Tr<S>::st(m + cf[l - 1] * t));
-                    out[c] = upd[c] ? v : m;
-                }
-            } else {
-#pragma unroll
-                for (int c = 0; c < C; ++c) out[c] = p1[l - 1][c];
-            }
-#pragma unroll
-            for (int c = 0; c < C; ++c) {
-                p2[l - 1][c] = p1[l - 1][c];
-                p1[l - 1][c] = in[c];
-                in[c] = out[c];
-            }
-        }
-        const int j = r - T;
-        if (j >= y0 && j < y1) {
-            S* po = uout + (int64_t)j * px + x0;
-#pragma unroll
-            for (int c = 0; c < C; ++c)
-                if (outc[c]) po[c] = Tr<S>::st(in[c]);
-        }
-#pragma unroll
-        for (int l = T - 1; l > 0; --l)
-#pragma unroll
-            for (int c = 0; c < C; ++c) bq[l][c] = bq[l - 1][c];
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            bq[0][c] = cb[c];
-            cu[c] = nu[c];
-            cb[c] = nb[c];
-        }
     }
 }
 
@@ -461,12 +291,6 @@ static dim3 grid1d(int64_t n)
 
 static int64_t field_rows(const Geo& g) { return (g.ndim == 3 ? g.nz + 2 : 1) * g.py; }
 
-#define SRJ_DISPATCH(f, KCALL)                               \
-    switch (f) {                                             \
-    case FMT_F64: { using S = double; KCALL; break; }        \
-    case FMT_F32: { using S = float; KCALL; break; }         \
-    default: { using S = bf16_t; KCALL; break; }             \
-    }
 
 hipError_t launch_copy_in(Fmt f, const double* user, void* field, const Geo& g, hipStream_t s)
 {
@@ -510,45 +334,6 @@ hipError_t launch_sweep_unfused(Fmt f, const void* in, void* out, const void* b,
         SRJ_DISPATCH(f, hipLaunchKernelGGL(k_sweep3d<S>, grid, dim3(64, 4), 0, s, (const S*)in, (S*)out,
                                            (const S*)b, g.px, g.py, (int)g.nx, (int)g.ny, (int)g.nz, zrun, c));
     }
-    return hipGetLastError();
-}
-
-template <class S, int T, int C>
-static void tb2d(const S* in, S* out, const S* b, const Geo& g, const Coefs& co, hipStream_t s)
-{
-    constexpr int SW = 64 * C - 2 * T;
-    const int H = 64;
-    CoefsT<T> ct;
-    for (int l = 0; l < T; ++l) ct.c[l] = co.c[l];
-    const int nstrip = (int)((g.nx + SW - 1) / SW);
-    const int nseg = (int)((g.ny + H - 1) / H);
-    const int nwaves = nstrip * nseg;
-    hipLaunchKernelGGL((k_sweep2d_tb<S, T, C>), dim3((nwaves + 3) / 4), dim3(256), 0, s, in, out, b, g.px,
-                       (int)g.nx, (int)g.ny, ct, nstrip, nwaves, H);
-}
-
-template <class S>
-static void tb2d_dispatch(const S* in, S* out, const S* b, const Geo& g, const Coefs& co, int T,
-                          hipStream_t s)
-{
-    constexpr int C = 2;
-    switch (T) {
-    case 1: tb2d<S, 1, C>(in, out, b, g, co, s); break;
-    case 2: tb2d<S, 2, C>(in, out, b, g, co, s); break;
-    case 3: tb2d<S, 3, C>(in, out, b, g, co, s); break;
-    case 4: tb2d<S, 4, C>(in, out, b, g, co, s); break;
-    case 5: tb2d<S, 5, C>(in, out, b, g, co, s); break;
-    case 6: tb2d<S, 6, C>(in, out, b, g, co, s); break;
-    case 7: tb2d<S, 7, C>(in, out, b, g, co, s); break;
-    default: tb2d<S, 8, C>(in, out, b, g, co, s); break;
-    }
-}
-
-hipError_t launch_sweep_fused(Fmt f, const void* in, void* out, const void* b, const Geo& g,
-                              const Coefs& co, int T, hipStream_t s)
-{
-    if (g.ndim != 2 || T < 1 || T > kMaxFuse) return hipErrorInvalidValue;
-    SRJ_DISPATCH(f, tb2d_dispatch<S>((const S*)in, (S*)out, (const S*)b, g, co, T, s));
     return hipGetLastError();
 }
 

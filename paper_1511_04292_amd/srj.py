@@ -71,9 +71,9 @@ def lib():
     L.srj_plan_destroy.restype = None
     L.srj_plan_describe.argtypes = [vp, ctypes.POINTER(_Desc)]
     L.srj_plan_sequence.argtypes = [vp, ctypes.POINTER(i32), i64]
-    L.srj_plan_set_fusion.argtypes = [vp, i32]
+    L.srj_plan_set_fusion.argtypes = [vp, i32, i32]
     L.srj_solve.argtypes = [vp, vp, vp, dbl, i64, ctypes.POINTER(_Info)]
-    L.srj_sweeps.argtypes = [vp, vp, vp, i64, i64]
+    L.srj_sweeps.argtypes = [vp, vp, vp, i64, i64, ctypes.POINTER(dbl)]
     L.srj_residual.argtypes = [vp, vp, vp, vp, ctypes.POINTER(dbl)]
     L.srj_solve_ir.argtypes = [vp, vp, vp, dbl, i32, i32, ctypes.POINTER(_Info)]
     L.srj_schedule_optimal.argtypes = [i32, dbl, dbl, ctypes.POINTER(dbl), ctypes.POINTER(dbl),
@@ -190,8 +190,8 @@ def srj_plan_sequence(plan):
     return seq
 
 
-def srj_plan_set_fusion(plan, fused):
-    _check(lib().srj_plan_set_fusion(plan.handle, int(fused)))
+def srj_plan_set_fusion(plan, fused, seg_rows=0):
+    _check(lib().srj_plan_set_fusion(plan.handle, int(fused), int(seg_rows)))
 
 
 def _info(i):
@@ -209,8 +209,12 @@ def srj_solve(plan, u, f, tol, max_sweeps, raise_on_noconv=False):
 
 
 def srj_sweeps(plan, u, f, k0, nsweeps):
+    """Apply nsweeps scheduled sweeps in place; returns (device seconds of the sweep
+    launches, number of launches)."""
+    stats = (ctypes.c_double * 2)()
     _check(lib().srj_sweeps(plan.handle, _dptr(u, plan.full_shape), _dptr(f, plan.full_shape), int(k0),
-                            int(nsweeps)))
+                            int(nsweeps), stats))
+    return stats[0], int(stats[1])
 
 
 def srj_residual(plan, u, f, r_out=None):

@@ -62,10 +62,10 @@ def big_first(P=3):
     return w, q, np.roll(seq, -k)
 
 
-def explicit_plan(n, h, w, q, seq, dtype="f64", fuse=None):
+def explicit_plan(n, h, w, q, seq, dtype="f64", fuse=None, seg_rows=0):
     p = srj.srj_plan(n, h, omega=w, q=q, sequence=seq, dtype=dtype)
     if fuse is not None:
-        srj.srj_plan_set_fusion(p, fuse)
+        srj.srj_plan_set_fusion(p, fuse, seg_rows)
     return p
 
 
@@ -109,6 +109,21 @@ def test_fused_sweeps_bitwise(T, n):
     srj.srj_sweeps(p, ug, dev(f), 3, nsweeps)
     c = sweeps.coefficients(np.array(w)[seq], 2)
     ref = sweeps.run(u, sweeps.rhs(f, h), c, nsweeps, k0=3)
+    assert np.array_equal(host(ug), ref)
+
+
+@pytest.mark.parametrize("T,H", [(8, 8), (8, 13), (3, 100), (5, 1), (8, 512)])
+def test_fused_segment_heights_bitwise(T, H):
+    n = (300, 203)
+    h = 1.0 / 301
+    u, f = rand_case(n, 9)
+    w, q, seq = shared_schedule()
+    nsweeps = 3 * T + 1
+    p = explicit_plan(n, h, w, q, seq, fuse=T, seg_rows=H)
+    ug = dev(u)
+    srj.srj_sweeps(p, ug, dev(f), 0, nsweeps)
+    c = sweeps.coefficients(np.array(w)[seq], 2)
+    ref = sweeps.run(u, sweeps.rhs(f, h), c, nsweeps)
     assert np.array_equal(host(ug), ref)
 
 
