@@ -118,12 +118,21 @@ def manufactured_2d(n):
 
 
 def cycle_factor(omega, q, kappa):
-    """prod_i (1 - w_i kappa)^q_i  (Eq. cycleAmplFact), elementwise over kappa."""
+    """prod_i (1 - w_i kappa)^q_i  (Eq. cycleAmplFact), elementwise over kappa.
+
+    The factors are accumulated as a sign and a sum of q_i log|1 - w_i kappa|: single powers
+    such as (1 - w kappa)^q overflow binary64 for the large weights and counts of P >= 8
+    schemes although the full product is small."""
     kappa = np.asarray(kappa, dtype=np.float64)
-    out = np.ones_like(kappa)
-    for w, qi in zip(omega, q):
-        out = out * (1.0 - float(w) * kappa) ** int(qi)
-    return out
+    logmag = np.zeros_like(kappa)
+    sign = np.ones_like(kappa)
+    with np.errstate(divide="ignore"):
+        for w, qi in zip(omega, q):
+            base = 1.0 - float(w) * kappa
+            logmag = logmag + int(qi) * np.log(np.abs(base))
+            if int(qi) % 2 == 1:
+                sign = sign * np.sign(base)
+    return sign * np.exp(logmag)
 
 
 def cycle_amplification(omega, q, shape_interior):

@@ -211,3 +211,22 @@ def test_ir_reaches_tolerance_in_both_formats():
         res = sweeps.solve_ir(w["u0"], w["f"], w["h"], seq, 1e-10, 4, 60, fmt)
         assert res["status"] == "ok", (fmt, res["history"][-5:])
         assert np.max(np.abs(res["u"] - us)) <= 1e-7 * np.max(np.abs(us))
+
+
+def test_modal_prediction_with_large_schedule():
+    # P = 10 scheme: single powers (1 - w kappa)^q overflow, the cycle factor must not;
+    # two full cycles of the oracle's sweeps follow the exact modal relres
+    n = (95, 95)
+    wl = workloads.blobs_2d(95, seed=3)
+    km = schedule.kappa_min_dirichlet(n)
+    o = schedule.optimal(10, km)
+    q = schedule.q_floor(o["beta"])
+    G = spectral.cycle_factor(o["w"], q, spectral.kappas(n))
+    assert np.all(np.isfinite(G)) and np.max(np.abs(G)) < 1.0
+    seq = schedule.order_balanced(o["w"], q, km)
+    b = sweeps.rhs(wl["f"], wl["h"])
+    M = int(np.sum(q))
+    u = sweeps.run(wl["u0"], b, sweeps.coefficients(np.asarray(o["w"])[seq], 2), 2 * M)
+    pred = spectral.predicted_relres(wl["u0"], b, o["w"], q, 2)
+    got = sweeps.relres(u, b)
+    assert abs(got - pred[2]) <= 1e-3 * pred[2]
