@@ -148,6 +148,21 @@ srj_status srj_residual(srj_plan_t plan, const double* u, const double* f, doubl
 srj_status srj_solve_ir(srj_plan_t plan, double* u, const double* f, double tol,
                         int32_t inner_cycles, int32_t max_outer, srj_solve_info* info);
 
+/* Adjoint of srj_solve for a loss L(u) of the solution (the differentiable solve).
+ * The forward map is (f, g) -> u with u = g on the ring and A u = b~ inside, where
+ * A = 2d I - (interior neighbour sum) is symmetric and b~ = h^2 f + (ring values next to
+ * each point) (Sec. 5.1 setting).  Given grad_u = dL/du (device, full layout) this solves
+ * A lambda = (interior of grad_u) with the plan's schedule and stopping rule (zero ring,
+ * zero start), then writes
+ *     df = h^2 lambda on the interior, 0 on the ring;
+ *     dg = grad_u + (lambda at the interior neighbour) on each ring cell -- the neighbour
+ *          term is absent on ring cells no stencil reads (2D corners; 3D edges and
+ *          corners) -- and 0 on the interior.
+ * df or dg may be NULL.  No forward iterate is needed or stored.  FP64 plans only.
+ * Status as srj_solve. */
+srj_status srj_adjoint(srj_plan_t plan, const double* grad_u, double tol, int64_t max_sweeps,
+                       double* df, double* dg, srj_solve_info* info);
+
 /* Host-only schedule computations (no device needed). */
 /* Optimal P-level weights/fractions on [kappa_min, kappa_max] (Sec. 3) and counts
  * q_i = floor(beta_i / beta_1) (Sec. 4.3).  kappa (P-1 values, may be NULL) receives the

@@ -219,6 +219,63 @@ void fill_info(srj_solve_info* info, int64_t sweeps, int64_t cycles, double relr
     info->status = (int32_t)st;
 }
 
+// Solve on the plan's fields: A and B hold the initial state (ring included), blo/b64 the
+// scaled source.  On return *cur points at the field with the returned state.
+srj_status solve_fields(srj_plan_t p, double tol, int64_t max_sweeps, DField** cur, int64_t* k_out,
+                        int64_t* cycles_out, double* rr_out, srj_status* result)
+{
+    double bt2, bmax;
+    srj_status st = residual_now(p, p->A.origin, p->fmt, 1, &bt2, &bmax);
+    if (st != SRJ_OK) return st;
+    *cur = &p->A;
+    DField* nxt = &p->B;
+    int64_t k = 0, cycles = 0;
+    double rr = 0.0;
+    *result = SRJ_OK;
+    if (!is_finite(bt2)) {
+        *result = SRJ_EDIVERGED;
+        rr = NAN;
+    } else if (bt2 == 0.0) {
+        // zero source and zero boundary: u = 0 is exact
+        HIPCHK(launch_zero(p->fmt, (*cur)->origin, p->geo, p->stream));
+        rr = 0.0;
+    } else {
+        for (;;) {
+            double r2, rmax;
+            if ((st = residual_now(p, (*cur)->origin, p->fmt, 0, &r2, &rmax)) != SRJ_OK) return st;
+            rr = std::sqrt(r2) / std::sqrt(bt2);
+            if (!is_finite(rr)) {
+                *result = SRJ_EDIVERGED;
+                break;
+            }
+            if (rr <= tol) break;
+            if (k + p->M > max_sweeps) {
+                *result = SRJ_ENOCONV;
+                break;
+            }
+            if ((st = run_sweeps(p, cur, &nxt, p->blo.origin, 0, p->M)) != SRJ_OK) return st;
+            k += p->M;
+            cycles += 1;
+        }
+    }
+    *k_out = k;
+    *cycles_out = cycles;
+    *rr_out = rr;
+    return SRJ_OK;
+}
+
+srj_status finish_info(srj_plan_t p, srj_solve_info* info, int64_t k, int64_t cycles, double rr, srj_status result)
+{
+    HIPCHK(hipEventRecord(p->ev1, p->stream));
+    HIPCHK(hipEventSynchronize(p->ev1));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, p->ev0, p->ev1));
+    fill_info(info, k, cycles, rr, ms * 1e-3, result);
+    if (result == SRJ_ENOCONV) return fail(result, "tolerance not reached within the sweep budget");
+    if (result == SRJ_EDIVERGED) return fail(result, "non-finite residual");
+    return SRJ_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -417,48 +474,38 @@ srj_status srj_solve(srj_plan_t p, double* u, const double* f, double tol, int64
     HIPCHK(launch_copy_in(p->fmt, u, p->A.origin, p->geo, p->stream));
     HIPCHK(launch_copy_in(p->fmt, u, p->B.origin, p->geo, p->stream));
     HIPCHK(launch_rhs(p->fmt, f, hh, p->blo.origin, p->fmt == FMT_F64 ? nullptr : p->b64, p->geo, p->stream));
-    double bt2, bmax;
-    srj_status st = residual_now(p, p->A.origin, p->fmt, 1, &bt2, &bmax);
-    if (st != SRJ_OK) return st;
-    DField *cur = &p->A, *nxt = &p->B;
+    DField* cur = nullptr;
     int64_t k = 0, cycles = 0;
-    double rr = 0.0;
-    srj_status result = SRJ_OK;
-    if (!is_finite(bt2)) {
-        result = SRJ_EDIVERGED;
-        rr = NAN;
-    } else if (bt2 == 0.0) {
-        // zero source and zero boundary: u = 0 is exact
-        HIPCHK(launch_zero(p->fmt, cur->origin, p->geo, p->stream));
-        rr = 0.0;
-    } else {
-        for (;;) {
-            double r2, rmax;
-            if ((st = residual_now(p, cur->origin, p->fmt, 0, &r2, &rmax)) != SRJ_OK) return st;
-            rr = std::sqrt(r2) / std::sqrt(bt2);
-            if (!is_finite(rr)) {
-                result = SRJ_EDIVERGED;
-                break;
-            }
-            if (rr <= tol) break;
-            if (k + p->M > max_sweeps) {
-                result = SRJ_ENOCONV;
-                break;
-            }
-            if ((st = run_sweeps(p, &cur, &nxt, p->blo.origin, 0, p->M)) != SRJ_OK) return st;
-            k += p->M;
-            cycles += 1;
-        }
-    }
+    double rr = 0;
+    srj_status result;
+    srj_status st = solve_fields(p, tol, max_sweeps, &cur, &k, &cycles, &rr, &result);
+    if (st != SRJ_OK) return st;
     if (result != SRJ_EDIVERGED) HIPCHK(launch_copy_out(p->fmt, cur->origin, u, p->geo, p->stream));
-    HIPCHK(hipEventRecord(p->ev1, p->stream));
-    HIPCHK(hipEventSynchronize(p->ev1));
-    float ms = 0;
-    HIPCHK(hipEventElapsedTime(&ms, p->ev0, p->ev1));
-    fill_info(info, k, cycles, rr, ms * 1e-3, result);
-    if (result == SRJ_ENOCONV) return fail(result, "tolerance not reached within max_sweeps");
-    if (result == SRJ_EDIVERGED) return fail(result, "non-finite residual");
-    return SRJ_OK;
+    return finish_info(p, info, k, cycles, rr, result);
+}
+
+srj_status srj_adjoint(srj_plan_t p, const double* grad_u, double tol, int64_t max_sweeps, double* df,
+                       double* dg, srj_solve_info* info)
+{
+    fill_info(info, 0, 0, NAN, 0, SRJ_EINVAL);
+    if (!p || !grad_u) return fail(SRJ_EINVAL, "null argument");
+    if (p->fmt != FMT_F64) return fail(SRJ_EINVAL, "the adjoint solve needs an FP64 plan");
+    if (!(tol >= 0) || max_sweeps < 0) return fail(SRJ_EINVAL, "bad tolerance or sweep budget");
+    HIPCHK(hipEventRecord(p->ev0, p->stream));
+    HIPCHK(launch_zero(p->fmt, p->A.origin, p->geo, p->stream));
+    HIPCHK(launch_zero(p->fmt, p->B.origin, p->geo, p->stream));
+    // right-hand side taken as given: b = 1.0 * grad_u exactly
+    HIPCHK(launch_rhs(p->fmt, grad_u, 1.0, p->blo.origin, nullptr, p->geo, p->stream));
+    DField* cur = nullptr;
+    int64_t k = 0, cycles = 0;
+    double rr = 0;
+    srj_status result;
+    srj_status st = solve_fields(p, tol, max_sweeps, &cur, &k, &cycles, &rr, &result);
+    if (st != SRJ_OK) return st;
+    if (result != SRJ_EDIVERGED && (df || dg))
+        HIPCHK(launch_adjoint_out((const double*)cur->origin, grad_u, p->grid.h * p->grid.h, df, dg, p->geo,
+                                  p->stream));
+    return finish_info(p, info, k, cycles, rr, result);
 }
 
 srj_status srj_solve_ir(srj_plan_t p, double* u, const double* f, double tol, int32_t inner_cycles,

@@ -49,6 +49,11 @@ hipError_t launch_residual_to_lo(Fmt f, const double* u64, const double* b64, vo
                                  const Geo& g, double* partials, double* result, hipStream_t s);
 // IR: u64 interior += widen(d)
 hipError_t launch_update(Fmt f, double* u64, const void* d, const Geo& g, hipStream_t s);
+// adjoint outputs from the FP64 field lam: user df = hh * lam (interior, ring 0) and user
+// dg = grad_u + lam at the interior neighbour, on each ring cell (interior 0); df or dg may
+// be null
+hipError_t launch_adjoint_out(const double* lam, const double* grad_u, double hh, double* df, double* dg,
+                              const Geo& g, hipStream_t s);
 // set every element of the field (ring included) to zero with a fill kernel
 hipError_t launch_zero(Fmt f, void* field, const Geo& g, hipStream_t s);
 

@@ -279,6 +279,42 @@ __global__ __launch_bounds__(256) void k_update(double* __restrict__ u, const S*
     }
 }
 
+// Adjoint outputs, one thread per point of the user (dense, ring included) layout.
+__global__ __launch_bounds__(256) void k_adjoint_out(const double* __restrict__ lam,
+                                                     const double* __restrict__ gu, double hh,
+                                                     double* __restrict__ df, double* __restrict__ dg,
+                                                     Geo g)
+{
+    const int64_t nxw = g.nx + 2, nyw = g.ny + 2, nzw = (g.ndim == 3 ? g.nz + 2 : 1);
+    const int64_t n = nxw * nyw * nzw;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = idx % nxw;
+        const int64_t t = idx / nxw;
+        const int64_t i = t % nyw;
+        const int64_t k = (g.ndim == 3) ? t / nyw : 0;
+        const bool ix = j >= 1 && j <= g.nx, iy = i >= 1 && i <= g.ny;
+        const bool iz = (g.ndim == 3) ? (k >= 1 && k <= g.nz) : true;
+        const int64_t p = (k * g.py + i) * g.px + j;
+        if (df) df[idx] = (ix && iy && iz) ? hh * lam[p] : 0.0;
+        if (dg) {
+            double v = 0.0;
+            // a ring cell is read by exactly one stencil when it lies outside the box along
+            // exactly one axis; its reader is the adjacent interior cell along that axis
+            const int outs = (!ix) + (!iy) + ((g.ndim == 3) && !iz);
+            if (outs == 1) {
+                int64_t jj = j, ii = i, kk = k;
+                if (!ix) jj = (j == 0) ? 1 : g.nx;
+                if (!iy) ii = (i == 0) ? 1 : g.ny;
+                if (g.ndim == 3 && !iz) kk = (k == 0) ? 1 : g.nz;
+                v = lam[(kk * g.py + ii) * g.px + jj];
+            }
+            // the ring of u is g itself: its own gradient passes straight through
+            dg[idx] = (ix && iy && iz) ? 0.0 : v + gu[idx];
+        }
+    }
+}
+
 // ------------------------------------------------------------------ launchers
 
 static dim3 grid1d(int64_t n)
@@ -360,6 +396,14 @@ hipError_t launch_residual_to_lo(Fmt f, const double* u64, const double* b64, vo
     SRJ_DISPATCH(f, hipLaunchKernelGGL(k_residual_to_lo<S>, dim3(nb), dim3(256), 0, s, u64, b64, (S*)rlo, g,
                                        partials));
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, s, partials, nb, result);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_out(const double* lam, const double* grad_u, double hh, double* df, double* dg,
+                              const Geo& g, hipStream_t s)
+{
+    int64_t n = (g.ndim == 3 ? g.nz + 2 : 1) * (g.ny + 2) * (g.nx + 2);
+    hipLaunchKernelGGL(k_adjoint_out, grid1d(n), dim3(256), 0, s, lam, grad_u, hh, df, dg, g);
     return hipGetLastError();
 }
 

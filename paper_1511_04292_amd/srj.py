@@ -55,7 +55,8 @@ _lib = None
 
 EXPORTS = ["srj_plan", "srj_plan_destroy", "srj_plan_describe", "srj_plan_sequence",
            "srj_plan_set_fusion", "srj_solve", "srj_sweeps", "srj_residual", "srj_solve_ir",
-           "srj_schedule_optimal", "srj_schedule_order", "srj_status_string", "srj_last_error"]
+           "srj_schedule_optimal", "srj_schedule_order", "srj_status_string", "srj_last_error",
+           "srj_adjoint"]
 
 
 def lib():
@@ -76,6 +77,7 @@ def lib():
     L.srj_sweeps.argtypes = [vp, vp, vp, i64, i64, ctypes.POINTER(dbl)]
     L.srj_residual.argtypes = [vp, vp, vp, vp, ctypes.POINTER(dbl)]
     L.srj_solve_ir.argtypes = [vp, vp, vp, dbl, i32, i32, ctypes.POINTER(_Info)]
+    L.srj_adjoint.argtypes = [vp, vp, dbl, i64, vp, vp, ctypes.POINTER(_Info)]
     L.srj_schedule_optimal.argtypes = [i32, dbl, dbl, ctypes.POINTER(dbl), ctypes.POINTER(dbl),
                                        ctypes.POINTER(i64), ctypes.POINTER(dbl)]
     L.srj_schedule_order.argtypes = [i32, ctypes.POINTER(dbl), ctypes.POINTER(i64), dbl, dbl, i32,
@@ -85,7 +87,8 @@ def lib():
     L.srj_last_error.argtypes = []
     L.srj_last_error.restype = ctypes.c_char_p
     for name in ["srj_plan", "srj_plan_describe", "srj_plan_sequence", "srj_plan_set_fusion", "srj_solve",
-                 "srj_sweeps", "srj_residual", "srj_solve_ir", "srj_schedule_optimal", "srj_schedule_order"]:
+                 "srj_sweeps", "srj_residual", "srj_solve_ir", "srj_schedule_optimal", "srj_schedule_order",
+                 "srj_adjoint"]:
         getattr(L, name).restype = i32
     _lib = L
     return L
@@ -228,6 +231,17 @@ def srj_solve_ir(plan, u, f, tol, inner_cycles, max_outer):
     info = _Info()
     st = lib().srj_solve_ir(plan.handle, _dptr(u, plan.full_shape), _dptr(f, plan.full_shape), float(tol),
                             int(inner_cycles), int(max_outer), ctypes.byref(info))
+    _check(st, (0, 5, 6))
+    return _info(info)
+
+
+def srj_adjoint(plan, grad_u, tol, max_sweeps, df=None, dg=None):
+    """Adjoint solve: A lambda = grad_u, then df = h^2 lambda, dg = boundary gather of
+    lambda (device tensors, full layout; either may be None).  Returns the info dict."""
+    info = _Info()
+    st = lib().srj_adjoint(plan.handle, _dptr(grad_u, plan.full_shape), float(tol), int(max_sweeps),
+                           _dptr(df, plan.full_shape) if df is not None else None,
+                           _dptr(dg, plan.full_shape) if dg is not None else None, ctypes.byref(info))
     _check(st, (0, 5, 6))
     return _info(info)
 

@@ -26,7 +26,7 @@ def test_library_exports_every_declared_symbol():
     assert len(names) >= 12
     for name in names:
         assert hasattr(lib, name), name
-    assert sorted(srj.EXPORTS) == names
+    assert sorted(srj.EXPORTS) == names, (sorted(srj.EXPORTS), names)
 
 
 def test_status_strings():

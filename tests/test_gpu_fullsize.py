@@ -1,0 +1,81 @@
+"""Parity at the benchmark's full sizes, in the launch configuration bench.py times.
+
+4096^2 FP64 (P = 10) and 512^3 FP64 (P = 8): a window of sweeps is compared bit for bit with
+the oracle run on the whole grid; the full 4096^2 solve must stop at the cycle the exact
+DST-mode trajectory predicts, with the relres it predicts.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import schedule as S
+from oracle import spectral, sweeps
+from paper_1511_04292_amd import srj, workloads
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+_CACHE = {}
+
+
+def oracle_schedule(P, n):
+    key = (P, n)
+    if key not in _CACHE:
+        km = S.kappa_min_dirichlet(n)
+        o = S.optimal(P, km)
+        q = S.q_floor(o["beta"])
+        _CACHE[key] = (o["w"], q, S.order_balanced(o["w"], q, km))
+    return _CACHE[key]
+
+
+@pytest.fixture(scope="module")
+def blobs():
+    return workloads.blobs_2d(4096, seed=0)
+
+
+def test_blobs_4096_window_bitwise(blobs):
+    wl = blobs
+    w, q, seq = oracle_schedule(10, wl["n"])
+    M = int(np.sum(q))
+    plan = srj.srj_plan(wl["n"], wl["h"], omega=w, q=q, sequence=seq)
+    assert srj.srj_plan_describe(plan)["fused_sweeps"] == 8
+    c = sweeps.coefficients(np.asarray(w)[seq], 2)
+    b = sweeps.rhs(wl["f"], wl["h"])
+    for k0, n in ((0, 64), (M - 21, 43)):  # the second window crosses the cycle end
+        u = torch.from_numpy(wl["u0"]).to(DEV)
+        srj.srj_sweeps(plan, u, torch.from_numpy(wl["f"]).to(DEV), k0, n)
+        ref = sweeps.run(wl["u0"], b, c, n, k0=k0)
+        assert np.array_equal(u.cpu().numpy(), ref), (k0, n)
+
+
+def test_blobs_4096_solve_stops_where_predicted(blobs):
+    wl = blobs
+    w, q, seq = oracle_schedule(10, wl["n"])
+    M = int(np.sum(q))
+    tol = 1e-10
+    b = sweeps.rhs(wl["f"], wl["h"])
+    pred = spectral.predicted_relres(wl["u0"], b, w, q, 12)
+    m_pred = int(np.argmax(pred <= tol))
+    assert pred[m_pred] <= tol
+    plan = srj.srj_plan(wl["n"], wl["h"], omega=w, q=q, sequence=seq)
+    u = torch.from_numpy(wl["u0"]).to(DEV)
+    info = srj.srj_solve(plan, u, torch.from_numpy(wl["f"]).to(DEV), tol, 50 * M)
+    assert info["status"] == "ok"
+    near = abs(pred[m_pred] - tol) < 0.01 * tol or abs(pred[m_pred - 1] - tol) < 0.01 * tol
+    assert info["cycles"] == m_pred or (near and abs(info["cycles"] - m_pred) == 1)
+    assert info["sweeps"] == info["cycles"] * M
+    assert abs(info["relres"] - pred[info["cycles"]]) <= 2e-3 * pred[info["cycles"]]
+
+
+def test_smooth_512cube_window_bitwise():
+    wl = workloads.smooth_3d(512, seed=0)
+    w, q, seq = oracle_schedule(8, wl["n"])
+    plan = srj.srj_plan(wl["n"], wl["h"], omega=w, q=q, sequence=seq)
+    c = sweeps.coefficients(np.asarray(w)[seq], 3)
+    b = sweeps.rhs(wl["f"], wl["h"])
+    n = 3
+    u = torch.from_numpy(wl["u0"]).to(DEV)
+    srj.srj_sweeps(plan, u, torch.from_numpy(wl["f"]).to(DEV), 0, n)
+    ref = sweeps.run(wl["u0"], b, c, n)
+    got = u.cpu().numpy()
+    assert np.array_equal(got, ref)
