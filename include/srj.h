@@ -163,6 +163,28 @@ srj_status srj_solve_ir(srj_plan_t plan, double* u, const double* f, double tol,
 srj_status srj_adjoint(srj_plan_t plan, const double* grad_u, double tol, int64_t max_sweeps,
                        double* df, double* dg, srj_solve_info* info);
 
+/* Batched solves: many independent 2D grids (sizes, spacings and schedules may all
+ * differ; one storage format per batch), each solved by the same FP64 refinement as
+ * srj_solve_ir with its own schedule (Sec. 2-4 per problem), all advanced together on
+ * the device: one kernel applies the scheduled sweeps to every problem that is sweeping,
+ * another forms u + d and the binary64 residual of every problem that finished an inner
+ * solve and decides it.  The iterations are replayed from a captured HIP graph on an
+ * internal stream (the plan's stream is synchronised first).  Problems never wait on one
+ * another; finished problems drop out. */
+typedef struct srj_batch_s* srj_batch_t;
+/* grids[count], schedules[count] as for srj_plan (ndim must be 2, one dtype for all).  The
+ * batch owns all device buffers (about 3 FP64 + 3 sweep-format fields per problem). */
+srj_status srj_batch_plan(int32_t count, const srj_grid* grids, const srj_schedule* schedules,
+                          void* stream, srj_batch_t* out);
+/* u[j], f[j]: device FP64 arrays of problem j in the ABI layout (u in/out).  infos[j] (may be
+ * NULL) as srj_solve_ir's; seconds[j] (may be NULL): device time from the start of the
+ * iterations to the decision that problem j converged (0 if it did not).  Returns SRJ_OK if
+ * every problem converged, else SRJ_EDIVERGED or SRJ_ENOCONV (per-problem status in infos). */
+srj_status srj_batch_solve(srj_batch_t batch, double* const* u, const double* const* f, double tol,
+                           int32_t inner_cycles, int32_t max_outer, srj_solve_info* infos,
+                           double* seconds);
+void srj_batch_destroy(srj_batch_t batch);
+
 /* Host-only schedule computations (no device needed). */
 /* Optimal P-level weights/fractions on [kappa_min, kappa_max] (Sec. 3) and counts
  * q_i = floor(beta_i / beta_1) (Sec. 4.3).  kappa (P-1 values, may be NULL) receives the

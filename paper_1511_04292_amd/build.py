@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 SO = os.path.join(HERE, "libsrj.so")
-SOURCES = ["kernels.hip", "sweep2d_tb.hip", "api.cpp", "planner.cpp"]
+SOURCES = ["kernels.hip", "sweep2d_tb.hip", "batch.hip", "api.cpp", "batch_api.cpp", "planner.cpp"]
 ARCH = "gfx950"
 
 
@@ -34,7 +34,7 @@ def build(verbose=False, jobs=4):
         obj = os.path.join(objdir, src.replace(".", "_") + ".o")
         objs.append(obj)
         path = os.path.join(CSRC, src)
-        if src.endswith(".hip") or src == "api.cpp":
+        if src.endswith(".hip") or src in ("api.cpp", "batch_api.cpp"):
             cmd = [hipcc(), "-x", "hip"] + hip_flags + common + ["-c", path, "-o", obj]
         else:
             cmd = ["g++"] + common + ["-c", path, "-o", obj]

@@ -44,6 +44,11 @@ struct DField {
 
 }  // namespace
 
+namespace srj {
+// Error reporting shared with the batched entry points.
+srj_status report(srj_status s, const std::string& msg) { return fail(s, msg); }
+}  // namespace srj
+
 struct srj_plan_s {
     srj_grid grid{};
     Fmt fmt = FMT_F64;

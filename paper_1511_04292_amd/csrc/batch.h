@@ -1,0 +1,61 @@
+// Batched SRJ solves: many independent 2D grids, each with its own schedule, refined in
+// FP64 around sweeps in the batch's storage format, advanced together by two kernels per
+// iteration (see batch.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.h"
+
+namespace srj {
+
+// Immutable per-problem descriptor (device copy uploaded at solve start).
+struct BProb {
+    int32_t nx, ny;
+    int64_t px;              // row pitch of every field of this problem (elements)
+    double* u64[2];          // FP64 iterate ping-pong (origins, ring included)
+    double* b64;             // FP64 scaled source h^2 f
+    void* d[2];              // correction ping-pong in the sweep format
+    void* rlo;               // residual cast to the sweep format (the inner right-hand side)
+    const double* bt2;       // -> ||b~||^2 of this problem
+    int32_t M, coff;         // cycle length and offset of its c_k in the coefficient table
+    int32_t inner_total;     // sweeps per inner solve (inner_cycles * M)
+    int32_t nstrip;          // strips of the fused sweep kernel
+    int32_t item0, nitems;   // first item and item count in the sweep work list
+    int32_t rb0, nrb;        // first residual block and block count in the residual list
+    int32_t pbase;           // first slot of its partial sums
+    int32_t pad;
+};
+
+// Mutable per-problem state, written only by the kernels (single lane, vector stores).
+enum { BP_SWEEP = 1, BP_DONE = 2, BP_DIVERGED = 3, BP_RESIDUAL = 4, BP_NOCONV = 5 };
+struct BState {
+    int32_t phase, k, ucur, dcur;
+    int32_t outer, cnt_s, cnt_r, pad;
+    double relres;
+    uint64_t t_end;
+};
+
+// Per-solve constants shared by all problems.
+struct BRun {
+    double tol;
+    int32_t max_outer;
+    int32_t count;
+    int32_t nitems, nrb;  // totals of the two work lists
+    int32_t H;            // output rows per wave in the sweep kernel
+    int32_t pad;
+    int* remaining;       // problems not yet finished
+    uint64_t* t0;         // wall clock at the start of the solve
+};
+
+int batch_fuse();  // sweeps fused per sweep-kernel launch
+
+hipError_t launch_batch_start(uint64_t* t0, hipStream_t s);
+hipError_t launch_batch_sweep(Fmt f, const BProb* probs, BState* st, const int* item_prefix,
+                              const double* coef, const BRun& run, int grid_blocks, hipStream_t s);
+hipError_t launch_batch_residual(Fmt f, const BProb* probs, BState* st, const int* rb_prefix,
+                                 double* partials, const BRun& run, int grid_blocks, hipStream_t s);
+
+}  // namespace srj

@@ -1,0 +1,442 @@
+// libsrj batched solves (C ABI): srj_batch_plan / srj_batch_solve / srj_batch_destroy.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/srj.h"
+#include "batch.h"
+#include "kernels.h"
+#include "planner.h"
+
+using namespace srj;
+
+// Set by api.cpp's error reporting helpers.
+extern "C" const char* srj_last_error(void);
+namespace srj {
+srj_status report(srj_status s, const std::string& msg);
+}
+
+namespace {
+
+#define BCHK(expr)                                                                             \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess) return report(SRJ_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int64_t kAlign = 512;
+constexpr int kH = 64;  // output rows per wave in the batch sweep kernel
+
+struct Sched {
+    std::vector<double> w;
+    std::vector<int64_t> q;
+    std::vector<int32_t> seq;
+    int64_t M = 0;
+    std::string err;
+    srj_status st = SRJ_OK;
+};
+
+// Schedule of one problem, as srj_plan builds it.
+void build_one(const srj_grid& g, const srj_schedule& sc, Sched* out)
+{
+    const double km = sc.kappa_min > 0 ? sc.kappa_min : grid_kappa_min(2, g.n);
+    if (sc.P < 1 || sc.P > SRJ_MAX_LEVELS) {
+        out->st = SRJ_EINVAL;
+        out->err = "P must be in [1, 16]";
+        return;
+    }
+    const int P = sc.P;
+    out->w.resize(P);
+    out->q.resize(P);
+    if (sc.omega) {
+        if (!sc.q) {
+            out->st = SRJ_EINVAL;
+            out->err = "explicit weights need counts";
+            return;
+        }
+        for (int i = 0; i < P; ++i) {
+            if (!(sc.omega[i] > 0) || sc.q[i] < 1 || (i > 0 && !(sc.omega[i] < sc.omega[i - 1]))) {
+                out->st = SRJ_EINVAL;
+                out->err = "bad explicit schedule";
+                return;
+            }
+            out->w[i] = sc.omega[i];
+            out->q[i] = sc.q[i];
+        }
+    } else {
+        Optimum o;
+        if (!optimal_schedule(P, km, 2.0, &o, &out->err)) {
+            out->st = SRJ_ESCHEDULE;
+            return;
+        }
+        std::vector<int64_t> qq = floor_counts(o.beta);
+        for (int i = 0; i < P; ++i) {
+            out->w[i] = o.w[i];
+            out->q[i] = qq[i];
+        }
+    }
+    out->M = 0;
+    for (int i = 0; i < P; ++i) out->M += out->q[i];
+    if (sc.ordering == 2) {
+        if (!sc.sequence || sc.M != out->M) {
+            out->st = SRJ_EINVAL;
+            out->err = "explicit sequence must have M entries";
+            return;
+        }
+        std::vector<int64_t> cnt(P, 0);
+        for (int64_t k = 0; k < out->M; ++k) {
+            if (sc.sequence[k] < 0 || sc.sequence[k] >= P) {
+                out->st = SRJ_EINVAL;
+                out->err = "sequence index out of range";
+                return;
+            }
+            cnt[sc.sequence[k]]++;
+        }
+        for (int i = 0; i < P; ++i)
+            if (cnt[i] != out->q[i]) {
+                out->st = SRJ_EINVAL;
+                out->err = "sequence counts differ from q";
+                return;
+            }
+        out->seq.assign(sc.sequence, sc.sequence + out->M);
+    } else {
+        out->seq = order_steps(P, out->w.data(), out->q.data(), km, 2.0, sc.ordering == 1 ? 1 : 0);
+    }
+    const double gq = gamma_q_max(P, out->w.data(), out->q.data(), km, std::max(grid_kappa_max(2, g.n), km * 1.0000001));
+    if (!(gq < 1.0)) {
+        out->st = SRJ_ESCHEDULE;
+        out->err = "integer scheme not convergent";
+    }
+}
+
+}  // namespace
+
+struct srj_batch_s {
+    int count = 0;
+    Fmt fmt = FMT_F32;
+    hipStream_t user_stream = nullptr;
+    hipStream_t stream = nullptr;  // internal, capturable
+    std::vector<srj_grid> grids;
+    std::vector<Geo> geos;
+    std::vector<BProb> probs;      // host copy (device pointers inside)
+    std::vector<int32_t> M;
+    int nitems = 0, nrb = 0, npart = 0;
+    void* pool = nullptr;
+    BProb* probs_d = nullptr;
+    BState* st_d = nullptr;
+    int* item_prefix_d = nullptr;
+    int* rb_prefix_d = nullptr;
+    double* coef_d = nullptr;
+    double* partials_d = nullptr;
+    double* bt2_d = nullptr;  // 2 doubles per problem
+    int* remaining_d = nullptr;
+    uint64_t* t0_d = nullptr;
+    int* remaining_h = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+};
+
+namespace {
+
+void destroy_batch(srj_batch_t b)
+{
+    if (!b) return;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    void* ptrs[] = {b->pool, b->probs_d, b->st_d, b->item_prefix_d, b->rb_prefix_d, b->coef_d, b->partials_d,
+                    b->bt2_d, b->remaining_d, b->t0_d};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    if (b->remaining_h) (void)hipHostFree(b->remaining_h);
+    if (b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}
+
+}  // namespace
+
+extern "C" {
+
+srj_status srj_batch_plan(int32_t count, const srj_grid* grids, const srj_schedule* schedules, void* stream,
+                          srj_batch_t* out)
+{
+    if (!grids || !schedules || !out || count < 1) return report(SRJ_EINVAL, "bad batch arguments");
+    *out = nullptr;
+    const int dt = grids[0].dtype;
+    for (int j = 0; j < count; ++j) {
+        const srj_grid& g = grids[j];
+        if (g.ndim != 2) return report(SRJ_EINVAL, "batched problems are 2D");
+        if (g.n[0] < 1 || g.n[1] < 1 || g.n[0] > (1 << 20) || g.n[1] > (1 << 20))
+            return report(SRJ_EINVAL, "n must be in [1, 2^20]");
+        if (!(g.h > 0)) return report(SRJ_EINVAL, "h must be positive");
+        if (g.dtype != dt || dt < 0 || dt > 2) return report(SRJ_EINVAL, "one storage format per batch");
+    }
+    srj_batch_t b = new (std::nothrow) srj_batch_s();
+    if (!b) return report(SRJ_ENOMEM, "host allocation failed");
+    b->count = count;
+    b->fmt = (Fmt)dt;
+    b->user_stream = (hipStream_t)stream;
+    b->grids.assign(grids, grids + count);
+    // schedules, in parallel host threads
+    std::vector<Sched> sch(count);
+    {
+        const unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+        std::atomic<int> next{0};
+        std::vector<std::thread> th;
+        for (unsigned t = 0; t < nt; ++t)
+            th.emplace_back([&]() {
+                for (int j = next++; j < count; j = next++) build_one(grids[j], schedules[j], &sch[j]);
+            });
+        for (auto& t : th) t.join();
+    }
+    for (int j = 0; j < count; ++j)
+        if (sch[j].st != SRJ_OK) {
+            destroy_batch(b);
+            return report(sch[j].st, "problem " + std::to_string(j) + ": " + sch[j].err);
+        }
+    // layout: one pool; every field of problem j shares the pitch px_j, and interior column 1
+    // of every row starts on a 512-byte boundary
+    const size_t es = fmt_size(b->fmt);
+    std::vector<size_t> off_u0(count), off_u1(count), off_b(count), off_d0(count), off_d1(count), off_r(count);
+    size_t cur = 0;
+    auto carve = [&](size_t elems, size_t esize) {
+        // origin = start + (kAlign/esize - 1) elements, start 512-aligned
+        cur = (cur + kAlign - 1) / kAlign * kAlign;
+        const size_t origin = cur + (kAlign / esize - 1) * esize;
+        cur += (kAlign / esize - 1) * esize + elems * esize;
+        return origin;
+    };
+    b->geos.resize(count);
+    std::vector<int> item_prefix(count + 1, 0), rb_prefix(count + 1, 0);
+    std::vector<double> coef;
+    b->probs.resize(count);
+    const int T = batch_fuse();
+    const int SW = 128 - 2 * T;
+    int npart = 0;
+    for (int j = 0; j < count; ++j) {
+        Geo& g = b->geos[j];
+        g.ndim = 2;
+        g.nx = grids[j].n[0];
+        g.ny = grids[j].n[1];
+        g.nz = 1;
+        g.px = (g.nx + 2 + 63) / 64 * 64;
+        g.py = g.ny + 2;
+        const size_t elems = (size_t)(g.px * g.py);
+        off_u0[j] = carve(elems, 8);
+        off_u1[j] = carve(elems, 8);
+        off_b[j] = carve(elems, 8);
+        off_d0[j] = carve(elems, es);
+        off_d1[j] = carve(elems, es);
+        off_r[j] = carve(elems, es);
+        BProb& P = b->probs[j];
+        std::memset(&P, 0, sizeof(P));
+        P.nx = (int32_t)g.nx;
+        P.ny = (int32_t)g.ny;
+        P.px = g.px;
+        P.M = (int32_t)sch[j].M;
+        P.coff = (int32_t)coef.size();
+        for (int64_t k = 0; k < sch[j].M; ++k) coef.push_back(sch[j].w[sch[j].seq[k]] / 4.0);
+        P.nstrip = (int32_t)((g.nx + SW - 1) / SW);
+        const int nseg = (int)((g.ny + kH - 1) / kH);
+        P.item0 = item_prefix[j];
+        P.nitems = P.nstrip * nseg;
+        item_prefix[j + 1] = item_prefix[j] + P.nitems;
+        P.rb0 = rb_prefix[j];
+        P.nrb = (int32_t)((g.ny + 7) / 8);
+        rb_prefix[j + 1] = rb_prefix[j] + P.nrb;
+        P.pbase = npart;
+        npart += std::max<int>(P.nrb, (int)((g.ny + 7) / 8));
+        b->M.push_back(P.M);
+    }
+    b->nitems = item_prefix[count];
+    b->nrb = rb_prefix[count];
+    b->npart = npart;
+    if (hipMalloc(&b->pool, cur) != hipSuccess) {
+        destroy_batch(b);
+        return report(SRJ_ENOMEM, "batch pool of " + std::to_string(cur) + " bytes");
+    }
+    char* base = (char*)b->pool;
+    for (int j = 0; j < count; ++j) {
+        BProb& P = b->probs[j];
+        P.u64[0] = (double*)(base + off_u0[j]);
+        P.u64[1] = (double*)(base + off_u1[j]);
+        P.b64 = (double*)(base + off_b[j]);
+        P.d[0] = base + off_d0[j];
+        P.d[1] = base + off_d1[j];
+        P.rlo = base + off_r[j];
+    }
+    bool ok = hipMalloc(&b->probs_d, sizeof(BProb) * count) == hipSuccess &&
+              hipMalloc(&b->st_d, sizeof(BState) * count) == hipSuccess &&
+              hipMalloc(&b->item_prefix_d, sizeof(int) * (count + 1)) == hipSuccess &&
+              hipMalloc(&b->rb_prefix_d, sizeof(int) * (count + 1)) == hipSuccess &&
+              hipMalloc(&b->coef_d, sizeof(double) * std::max<size_t>(1, coef.size())) == hipSuccess &&
+              hipMalloc(&b->partials_d, sizeof(double) * 2 * (size_t)npart) == hipSuccess &&
+              hipMalloc(&b->bt2_d, sizeof(double) * 2 * count) == hipSuccess &&
+              hipMalloc(&b->remaining_d, sizeof(int)) == hipSuccess &&
+              hipMalloc(&b->t0_d, sizeof(uint64_t)) == hipSuccess &&
+              hipHostMalloc(&b->remaining_h, sizeof(int), hipHostMallocDefault) == hipSuccess &&
+              hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) == hipSuccess;
+    if (!ok) {
+        destroy_batch(b);
+        return report(SRJ_ENOMEM, "batch scratch allocation failed");
+    }
+    for (int j = 0; j < count; ++j) b->probs[j].bt2 = b->bt2_d + 2 * j;
+    if (hipMemcpy(b->item_prefix_d, item_prefix.data(), sizeof(int) * (count + 1), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->rb_prefix_d, rb_prefix.data(), sizeof(int) * (count + 1), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->coef_d, coef.data(), sizeof(double) * coef.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        destroy_batch(b);
+        return report(SRJ_EHIP, "batch table upload failed");
+    }
+    *out = b;
+    return SRJ_OK;
+}
+
+void srj_batch_destroy(srj_batch_t b)
+{
+    if (b && b->stream) (void)hipStreamSynchronize(b->stream);
+    destroy_batch(b);
+}
+
+srj_status srj_batch_solve(srj_batch_t b, double* const* u, const double* const* f, double tol,
+                           int32_t inner_cycles, int32_t max_outer, srj_solve_info* infos, double* seconds)
+{
+    if (!b || !u || !f) return report(SRJ_EINVAL, "null argument");
+    if (!(tol >= 0) || inner_cycles < 1 || max_outer < 0) return report(SRJ_EINVAL, "bad refinement parameters");
+    for (int j = 0; j < b->count; ++j)
+        if (!u[j] || !f[j]) return report(SRJ_EINVAL, "null problem array");
+    hipStream_t s = b->stream;
+    if (b->user_stream) BCHK(hipStreamSynchronize(b->user_stream));
+    BCHK(hipDeviceSynchronize());
+    // inputs into the pool; ||b~||^2 per problem
+    for (int j = 0; j < b->count; ++j) {
+        const Geo& g = b->geos[j];
+        BProb& P = b->probs[j];
+        P.inner_total = inner_cycles * P.M;
+        const double hh = b->grids[j].h * b->grids[j].h;
+        BCHK(launch_copy_in(FMT_F64, u[j], P.u64[0], g, s));
+        BCHK(launch_copy_in(FMT_F64, u[j], P.u64[1], g, s));
+        BCHK(launch_rhs(FMT_F64, f[j], hh, nullptr, P.b64, g, s));
+        BCHK(launch_zero(b->fmt, P.d[0], g, s));
+        BCHK(launch_zero(b->fmt, P.d[1], g, s));
+        BCHK(launch_zero(b->fmt, P.rlo, g, s));
+        BCHK(launch_residual(FMT_F64, P.u64[0], P.b64, g, 1, b->partials_d + 2 * P.pbase, b->bt2_d + 2 * j, s));
+    }
+    std::vector<double> bt2(2 * b->count);
+    BCHK(hipMemcpyAsync(bt2.data(), b->bt2_d, sizeof(double) * 2 * b->count, hipMemcpyDeviceToHost, s));
+    BCHK(hipStreamSynchronize(s));
+    std::vector<BState> st(b->count);
+    int remaining = 0;
+    for (int j = 0; j < b->count; ++j) {
+        std::memset(&st[j], 0, sizeof(BState));
+        if (!std::isfinite(bt2[2 * j])) {
+            st[j].phase = BP_DIVERGED;
+            st[j].relres = NAN;
+        } else if (bt2[2 * j] == 0.0) {
+            // zero source and boundary: u = 0 is exact
+            st[j].phase = BP_DONE;
+            BCHK(launch_zero(FMT_F64, b->probs[j].u64[0], b->geos[j], s));
+        } else {
+            st[j].phase = BP_RESIDUAL;
+            remaining += 1;
+        }
+    }
+    BCHK(hipMemcpyAsync(b->probs_d, b->probs.data(), sizeof(BProb) * b->count, hipMemcpyHostToDevice, s));
+    BCHK(hipMemcpyAsync(b->st_d, st.data(), sizeof(BState) * b->count, hipMemcpyHostToDevice, s));
+    *b->remaining_h = remaining;
+    BCHK(hipMemcpyAsync(b->remaining_d, b->remaining_h, sizeof(int), hipMemcpyHostToDevice, s));
+    BCHK(hipStreamSynchronize(s));
+
+    BRun run;
+    std::memset(&run, 0, sizeof(run));
+    run.tol = tol;
+    run.max_outer = max_outer;
+    run.count = b->count;
+    run.nitems = b->nitems;
+    run.nrb = b->nrb;
+    run.H = kH;
+    run.remaining = b->remaining_d;
+    run.t0 = b->t0_d;
+    const int gs = std::max(1, std::min((b->nitems + 3) / 4, 2048));
+    const int gr = std::max(1, std::min(b->nrb, 4096));
+    // one graph = G iterations of (sweep, residual)
+    const int G = 16;
+    if (b->exec) {
+        (void)hipGraphExecDestroy(b->exec);
+        b->exec = nullptr;
+    }
+    if (b->graph) {
+        (void)hipGraphDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    BCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    for (int it = 0; it < G; ++it) {
+        hipError_t e1 = launch_batch_sweep(b->fmt, b->probs_d, b->st_d, b->item_prefix_d, b->coef_d, run, gs, s);
+        hipError_t e2 = launch_batch_residual(b->fmt, b->probs_d, b->st_d, b->rb_prefix_d, b->partials_d, run, gr, s);
+        if (e1 != hipSuccess || e2 != hipSuccess) {
+            hipGraph_t g0 = nullptr;
+            (void)hipStreamEndCapture(s, &g0);
+            if (g0) (void)hipGraphDestroy(g0);
+            return report(SRJ_EHIP, "batch launch during capture failed");
+        }
+    }
+    BCHK(hipStreamEndCapture(s, &b->graph));
+    BCHK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    // iterations needed at most: every outer step of the longest problem plus one
+    int64_t max_inner = 0;
+    for (int j = 0; j < b->count; ++j) max_inner = std::max<int64_t>(max_inner, b->probs[j].inner_total);
+    const int T = batch_fuse();
+    const int64_t cap_iters = ((int64_t)max_outer + 1) * ((max_inner + T - 1) / T + 1) + 2;
+    const int64_t cap_replays = cap_iters / G + 2;
+    BCHK(launch_batch_start(b->t0_d, s));
+    int64_t replays = 0;
+    while (remaining > 0 && replays < cap_replays) {
+        BCHK(hipGraphLaunch(b->exec, s));
+        BCHK(hipMemcpyAsync(b->remaining_h, b->remaining_d, sizeof(int), hipMemcpyDeviceToHost, s));
+        BCHK(hipStreamSynchronize(s));
+        remaining = *b->remaining_h;
+        replays += 1;
+    }
+    BCHK(hipMemcpyAsync(st.data(), b->st_d, sizeof(BState) * b->count, hipMemcpyDeviceToHost, s));
+    uint64_t t0 = 0;
+    BCHK(hipMemcpyAsync(&t0, b->t0_d, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    BCHK(hipStreamSynchronize(s));
+    int dev = 0, rate_khz = 0;
+    BCHK(hipGetDevice(&dev));
+    BCHK(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev));
+    srj_status worst = SRJ_OK;
+    for (int j = 0; j < b->count; ++j) {
+        const BProb& P = b->probs[j];
+        srj_status sj;
+        switch (st[j].phase) {
+        case BP_DONE: sj = SRJ_OK; break;
+        case BP_DIVERGED: sj = SRJ_EDIVERGED; break;
+        default: sj = SRJ_ENOCONV; break;
+        }
+        if (sj != SRJ_EDIVERGED) BCHK(launch_copy_out(FMT_F64, P.u64[st[j].ucur], u[j], b->geos[j], s));
+        if (infos) {
+            infos[j].sweeps = (int64_t)st[j].outer * P.inner_total;
+            infos[j].cycles = st[j].outer;
+            infos[j].relres = st[j].relres;
+            infos[j].seconds = (sj == SRJ_OK && st[j].t_end > t0 && rate_khz > 0)
+                                   ? (double)(st[j].t_end - t0) / (rate_khz * 1e3)
+                                   : 0.0;
+            infos[j].status = (int32_t)sj;
+        }
+        if (seconds)
+            seconds[j] = (sj == SRJ_OK && st[j].t_end > t0 && rate_khz > 0)
+                             ? (double)(st[j].t_end - t0) / (rate_khz * 1e3)
+                             : 0.0;
+        if (sj == SRJ_EDIVERGED || (sj == SRJ_ENOCONV && worst == SRJ_OK)) worst = sj;
+    }
+    BCHK(hipStreamSynchronize(s));
+    if (worst != SRJ_OK) return report(worst, "some batched problems did not converge");
+    return SRJ_OK;
+}
+
+}  // extern "C"

@@ -14,7 +14,9 @@
 // and refinement helpers; the temporally blocked 2D sweep is in sweep2d_tb.hip.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
+#include <cstdlib>
 
 #include "formats.h"
 #include "kernels.h"
@@ -104,32 +106,43 @@ __global__ __launch_bounds__(256) void k_sweep2d(const S* __restrict__ u, S* __r
     o[p] = Tr<S>::st(m + c * t);
 }
 
-// One 3D sweep: threads over (x, y), each walking a run of z planes with the z
-// neighbours kept in registers.
-template <class S>
+// One 3D sweep: threads over (x, y) (block of 64 x BY), each walking a run of z planes with
+// the z neighbours and D planes ahead kept in registers.  The z loop is branch-free (clamped
+// plane index) so the loads of the next D planes stay in flight while a plane computes.
+template <class S, int D>
 __global__ __launch_bounds__(256) void k_sweep3d(const S* __restrict__ u, S* __restrict__ o,
                                                  const S* __restrict__ b, int64_t px, int64_t py,
                                                  int nx, int ny, int nz, int zrun, double c64)
 {
     using Cm = typename Tr<S>::C;
     const int j = blockIdx.x * 64 + threadIdx.x + 1;
-    const int i = blockIdx.y * 4 + threadIdx.y + 1;
+    const int i = blockIdx.y * blockDim.y + threadIdx.y + 1;
     if (j > nx || i > ny) return;
     const int k0 = blockIdx.z * zrun + 1;
     const int k1 = min(k0 + zrun, nz + 1);
     const Cm c = (Cm)c64;
     const int64_t pl = px * py;
-    int64_t p = (int64_t)k0 * pl + (int64_t)i * px + j;
-    Cm dn = Tr<S>::ld(u[p - pl]);
-    Cm m = Tr<S>::ld(u[p]);
-    for (int k = k0; k < k1; ++k, p += pl) {
-        Cm up = Tr<S>::ld(u[p + pl]);
-        Cm s = ((Tr<S>::ld(u[p - 1]) + Tr<S>::ld(u[p + 1])) + (Tr<S>::ld(u[p - px]) + Tr<S>::ld(u[p + px]))) +
-               (dn + up);
-        Cm t = (s + Tr<S>::ld(b[p])) - (Cm)6 * m;
-        o[p] = Tr<S>::st(m + c * t);
-        dn = m;
-        m = up;
+    const int64_t col = (int64_t)i * px + j;
+    Cm dn = Tr<S>::ld(u[(int64_t)(k0 - 1) * pl + col]);
+    Cm m = Tr<S>::ld(u[(int64_t)k0 * pl + col]);
+    Cm Q[D];
+#pragma unroll
+    for (int s = 0; s < D; ++s) Q[s] = Tr<S>::ld(u[(int64_t)min(k0 + 1 + s, nz + 1) * pl + col]);
+    for (int kb = k0; kb < k1; kb += D) {
+#pragma unroll
+        for (int s = 0; s < D; ++s) {
+            const int k = kb + s;
+            const int64_t p = (int64_t)min(k, nz) * pl + col;
+            const Cm up = Q[s];
+            const Cm sm = ((Tr<S>::ld(u[p - 1]) + Tr<S>::ld(u[p + 1])) +
+                           (Tr<S>::ld(u[p - px]) + Tr<S>::ld(u[p + px]))) +
+                          (dn + up);
+            const Cm t = (sm + Tr<S>::ld(b[p])) - (Cm)6 * m;
+            if (k < k1) o[p] = Tr<S>::st(m + c * t);
+            dn = m;
+            m = up;
+            Q[s] = Tr<S>::ld(u[(int64_t)min(k + 1 + D, nz + 1) * pl + col]);
+        }
     }
 }
 
@@ -317,6 +330,12 @@ __global__ __launch_bounds__(256) void k_adjoint_out(const double* __restrict__ 
 
 // ------------------------------------------------------------------ launchers
 
+static int env_int(const char* name, int dflt)
+{
+    const char* v = getenv(name);
+    return v ? atoi(v) : dflt;
+}
+
 static dim3 grid1d(int64_t n)
 {
     int64_t b = (n + 255) / 256;
@@ -365,10 +384,21 @@ hipError_t launch_sweep_unfused(Fmt f, const void* in, void* out, const void* b,
         SRJ_DISPATCH(f, hipLaunchKernelGGL(k_sweep2d<S>, grid, dim3(64, 4), 0, s, (const S*)in, (S*)out,
                                            (const S*)b, g.px, (int)g.nx, (int)g.ny, c));
     } else {
-        const int zrun = 8;
-        dim3 grid((unsigned)((g.nx + 63) / 64), (unsigned)((g.ny + 3) / 4), (unsigned)((g.nz + zrun - 1) / zrun));
-        SRJ_DISPATCH(f, hipLaunchKernelGGL(k_sweep3d<S>, grid, dim3(64, 4), 0, s, (const S*)in, (S*)out,
-                                           (const S*)b, g.px, g.py, (int)g.nx, (int)g.ny, (int)g.nz, zrun, c));
+        static const int zrun = env_int("SRJ_3D_ZRUN", 32);
+        static const int by = std::min(4, std::max(1, env_int("SRJ_3D_BY", 4)));
+        static const int pf = env_int("SRJ_3D_PREFETCH", 2);
+        dim3 grid((unsigned)((g.nx + 63) / 64), (unsigned)((g.ny + by - 1) / by), (unsigned)((g.nz + zrun - 1) / zrun));
+        dim3 blk(64, by);
+        if (pf <= 1) {
+            SRJ_DISPATCH(f, hipLaunchKernelGGL((k_sweep3d<S, 1>), grid, blk, 0, s, (const S*)in, (S*)out, (const S*)b,
+                                               g.px, g.py, (int)g.nx, (int)g.ny, (int)g.nz, zrun, c));
+        } else if (pf == 2) {
+            SRJ_DISPATCH(f, hipLaunchKernelGGL((k_sweep3d<S, 2>), grid, blk, 0, s, (const S*)in, (S*)out, (const S*)b,
+                                               g.px, g.py, (int)g.nx, (int)g.ny, (int)g.nz, zrun, c));
+        } else {
+            SRJ_DISPATCH(f, hipLaunchKernelGGL((k_sweep3d<S, 4>), grid, blk, 0, s, (const S*)in, (S*)out, (const S*)b,
+                                               g.px, g.py, (int)g.nx, (int)g.ny, (int)g.nz, zrun, c));
+        }
     }
     return hipGetLastError();
 }

@@ -56,7 +56,7 @@ _lib = None
 EXPORTS = ["srj_plan", "srj_plan_destroy", "srj_plan_describe", "srj_plan_sequence",
            "srj_plan_set_fusion", "srj_solve", "srj_sweeps", "srj_residual", "srj_solve_ir",
            "srj_schedule_optimal", "srj_schedule_order", "srj_status_string", "srj_last_error",
-           "srj_adjoint"]
+           "srj_adjoint", "srj_batch_plan", "srj_batch_solve", "srj_batch_destroy"]
 
 
 def lib():
@@ -78,6 +78,11 @@ def lib():
     L.srj_residual.argtypes = [vp, vp, vp, vp, ctypes.POINTER(dbl)]
     L.srj_solve_ir.argtypes = [vp, vp, vp, dbl, i32, i32, ctypes.POINTER(_Info)]
     L.srj_adjoint.argtypes = [vp, vp, dbl, i64, vp, vp, ctypes.POINTER(_Info)]
+    L.srj_batch_plan.argtypes = [i32, ctypes.POINTER(_Grid), ctypes.POINTER(_Schedule), vp, ctypes.POINTER(vp)]
+    L.srj_batch_solve.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), dbl, i32, i32, ctypes.POINTER(_Info),
+                                  ctypes.POINTER(dbl)]
+    L.srj_batch_destroy.argtypes = [vp]
+    L.srj_batch_destroy.restype = None
     L.srj_schedule_optimal.argtypes = [i32, dbl, dbl, ctypes.POINTER(dbl), ctypes.POINTER(dbl),
                                        ctypes.POINTER(i64), ctypes.POINTER(dbl)]
     L.srj_schedule_order.argtypes = [i32, ctypes.POINTER(dbl), ctypes.POINTER(i64), dbl, dbl, i32,
@@ -88,7 +93,7 @@ def lib():
     L.srj_last_error.restype = ctypes.c_char_p
     for name in ["srj_plan", "srj_plan_describe", "srj_plan_sequence", "srj_plan_set_fusion", "srj_solve",
                  "srj_sweeps", "srj_residual", "srj_solve_ir", "srj_schedule_optimal", "srj_schedule_order",
-                 "srj_adjoint"]:
+                 "srj_adjoint", "srj_batch_plan", "srj_batch_solve", "srj_batch_destroy"]:
         getattr(L, name).restype = i32
     _lib = L
     return L
@@ -244,6 +249,72 @@ def srj_adjoint(plan, grad_u, tol, max_sweeps, df=None, dg=None):
                            _dptr(dg, plan.full_shape) if dg is not None else None, ctypes.byref(info))
     _check(st, (0, 5, 6))
     return _info(info)
+
+
+class Batch:
+    """Owns an srj_batch_t."""
+
+    def __init__(self, handle, shapes):
+        self.handle = handle
+        self.shapes = shapes  # full-grid shapes (ny + 2, nx + 2)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            _lib.srj_batch_destroy(h)
+            self.handle = None
+
+
+def srj_batch_plan(problems, dtype="f32", stream=None):
+    """problems: list of dicts with n = (n_x, n_y), h, and either P or omega/q (optionally
+    sequence, kappa_min, ordering)."""
+    L = lib()
+    cnt = len(problems)
+    grids = (_Grid * cnt)()
+    scheds = (_Schedule * cnt)()
+    keep = []
+    for j, pr in enumerate(problems):
+        g = grids[j]
+        g.ndim = 2
+        g.n[0], g.n[1] = int(pr["n"][0]), int(pr["n"][1])
+        g.h = float(pr["h"])
+        g.dtype = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
+        s = scheds[j]
+        if pr.get("omega") is not None:
+            w = np.ascontiguousarray(pr["omega"], dtype=np.float64)
+            qq = np.ascontiguousarray(pr["q"], dtype=np.int64)
+            keep += [w, qq]
+            s.P = len(w)
+            s.omega = w.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            s.q = qq.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        else:
+            s.P = int(pr["P"])
+        s.kappa_min = float(pr.get("kappa_min", 0.0))
+        s.ordering = int(pr.get("ordering", 0))
+        if pr.get("sequence") is not None:
+            sq = np.ascontiguousarray(pr["sequence"], dtype=np.int32)
+            keep.append(sq)
+            s.sequence = sq.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+            s.M = len(sq)
+            s.ordering = 2
+    out = ctypes.c_void_p()
+    st = stream if stream is not None else _stream_handle()
+    _check(L.srj_batch_plan(cnt, grids, scheds, st, ctypes.byref(out)))
+    return Batch(out, [(int(p["n"][1]) + 2, int(p["n"][0]) + 2) for p in problems])
+
+
+def srj_batch_solve(batch, us, fs, tol, inner_cycles=1, max_outer=1000):
+    """Solve every problem in place; returns (list of info dicts, seconds array)."""
+    cnt = len(batch.shapes)
+    if len(us) != cnt or len(fs) != cnt:
+        raise ValueError("one u and one f per problem")
+    up = (ctypes.c_void_p * cnt)(*[_dptr(u, sh).value for u, sh in zip(us, batch.shapes)])
+    fp = (ctypes.c_void_p * cnt)(*[_dptr(f, sh).value for f, sh in zip(fs, batch.shapes)])
+    infos = (_Info * cnt)()
+    secs = (ctypes.c_double * cnt)()
+    st = lib().srj_batch_solve(batch.handle, up, fp, float(tol), int(inner_cycles), int(max_outer), infos, secs)
+    _check(st, (0, 5, 6))
+    return [_info(i) for i in infos], np.array(secs[:])
 
 
 def srj_schedule_optimal(P, kappa_min, kappa_max=2.0):

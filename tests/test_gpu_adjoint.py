@@ -47,7 +47,7 @@ def test_adjoint_matches_dense_gradient(n, P):
     plan = oracle_plan(n, h, P)
     ft = dev(f).requires_grad_(True)
     gt = dev(g).requires_grad_(True)
-    u = srj_solve_diff(ft, gt, plan, tol=1e-13)
+    u = srj_solve_diff(ft, gt, plan, tol=1e-13, tol_backward=1e-13)
     L = loss_t(u, dev(ut))
     L.backward()
     df_ref, dg_ref = OA.grad_dense(f, g, ut, h)
@@ -73,7 +73,7 @@ def test_adjoint_central_differences():
     plan = srj.srj_plan(n, h, P=5)
     ft = dev(f).requires_grad_(True)
     gt = dev(g).requires_grad_(True)
-    L = loss_t(srj_solve_diff(ft, gt, plan, tol=1e-13), dev(ut))
+    L = loss_t(srj_solve_diff(ft, gt, plan, tol=1e-13, tol_backward=1e-13), dev(ut))
     L.backward()
     df, dg = ft.grad, gt.grad
     rng = np.random.default_rng(2)

@@ -1,0 +1,102 @@
+"""Batched solves: every problem's result is bit-identical to the oracle's FP64 refinement
+around binary32 sweeps with the same schedule, with the same number of outer steps."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import schedule as S
+from oracle import sweeps
+from paper_1511_04292_amd import srj, workloads
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+SIZES = [(5, 5), (17, 17), (32, 32), (45, 30), (64, 64), (77, 100), (130, 129), (200, 200), (257, 90),
+         (1, 9), (300, 301)]
+LEVELS = [2, 3, 4, 5, 6, 2, 3, 4, 5, 6, 4]
+
+
+def oracle_sched(n, P):
+    km = S.kappa_min_dirichlet(n)
+    o = S.optimal(P, km)
+    q = S.q_floor(o["beta"])
+    return o["w"], q, S.order_balanced(o["w"], q, km)
+
+
+def make_problem(n, seed):
+    rng = np.random.default_rng(seed)
+    full = (n[1] + 2, n[0] + 2)
+    u0 = workloads.random_ring(full, rng)
+    f = np.zeros(full)
+    f[1:-1, 1:-1] = rng.standard_normal((n[1], n[0]))
+    return u0, f
+
+
+@pytest.mark.parametrize("fmt", ["f32", "bf16"])
+def test_batch_matches_oracle_per_problem(fmt):
+    probs, data, refs = [], [], []
+    for i, n in enumerate(SIZES):
+        P = LEVELS[i]
+        w, q, seq = oracle_sched(n, P)
+        h = 1.0 / (max(n) + 1)
+        u0, f = make_problem(n, 100 + i)
+        probs.append(dict(n=n, h=h, omega=w, q=q, sequence=seq))
+        data.append((u0, f))
+        refs.append(sweeps.solve_ir(u0, f, h, np.asarray(w)[seq], 1e-10, 1, 400, fmt))
+    b = srj.srj_batch_plan(probs, dtype=fmt)
+    us = [torch.from_numpy(u0).to(DEV) for u0, _ in data]
+    fs = [torch.from_numpy(f).to(DEV) for _, f in data]
+    infos, secs = srj.srj_batch_solve(b, us, fs, 1e-10, 1, 400)
+    torch.cuda.synchronize()
+    for i, (info, ref) in enumerate(zip(infos, refs)):
+        assert ref["status"] == "ok" and info["status"] == "ok", (i, SIZES[i], info, ref["status"])
+        assert info["cycles"] == ref["outer"], (i, info, ref["outer"])
+        assert abs(info["relres"] - ref["relres"]) <= 1e-12 * ref["relres"]
+        assert np.array_equal(us[i].cpu().numpy(), ref["u"]), (i, SIZES[i])
+        assert secs[i] > 0
+
+
+def test_batch_edge_cases():
+    n = (24, 24)
+    h = 1.0 / 25
+    w, q, seq = oracle_sched(n, 3)
+    good_u, good_f = make_problem(n, 1)
+    nan_f = good_f.copy()
+    nan_f[5, 5] = np.nan
+    zero_u = np.zeros_like(good_u)
+    zero_u[3, 3] = 4.0  # interior guess only: zero source and ring make u = 0 exact
+    zero_f = np.zeros_like(good_f)
+    probs = [dict(n=n, h=h, omega=w, q=q, sequence=seq) for _ in range(3)]
+    b = srj.srj_batch_plan(probs, dtype="f32")
+    us = [torch.from_numpy(x).to(DEV) for x in (good_u, good_u.copy(), zero_u)]
+    fs = [torch.from_numpy(x).to(DEV) for x in (good_f, nan_f, zero_f)]
+    infos, secs = srj.srj_batch_solve(b, us, fs, 1e-10, 1, 300)
+    assert infos[0]["status"] == "ok"
+    assert infos[1]["status"] == "ediverged"
+    assert infos[2]["status"] == "ok" and float(us[2].abs().max()) == 0.0
+    # a budget too small leaves a problem unconverged without disturbing the others
+    b2 = srj.srj_batch_plan(probs[:2], dtype="f32")
+    us2 = [torch.from_numpy(good_u).to(DEV), torch.from_numpy(good_u).to(DEV)]
+    fs2 = [torch.from_numpy(good_f).to(DEV), torch.from_numpy(good_f).to(DEV)]
+    infos2, _ = srj.srj_batch_solve(b2, us2, fs2, 1e-10, 1, 2)
+    assert all(i["status"] == "enoconv" and i["cycles"] == 2 for i in infos2)
+
+
+def test_batch_with_planner_schedules_converges():
+    N, P = workloads.batch_sizes(count=24, seed=5, lo=32, hi=300)
+    probs, us, fs = [], [], []
+    for j, (n, p) in enumerate(zip(N, P)):
+        wl = workloads.batch_problem(int(n), seed=1000 + j)
+        probs.append(dict(n=(int(n), int(n)), h=wl["h"], P=int(p)))
+        us.append(torch.from_numpy(wl["u0"]).to(DEV))
+        fs.append(torch.from_numpy(wl["f"]).to(DEV))
+    b = srj.srj_batch_plan(probs, dtype="f32")
+    infos, secs = srj.srj_batch_solve(b, us, fs, 1e-10, 1, 1000)
+    assert all(i["status"] == "ok" and i["relres"] <= 1e-10 for i in infos)
+    # cross-check one problem against the single-grid refinement path on the GPU
+    p0 = srj.srj_plan(probs[0]["n"], probs[0]["h"], P=probs[0]["P"], dtype="f32")
+    wl = workloads.batch_problem(int(N[0]), seed=1000)
+    u = torch.from_numpy(wl["u0"]).to(DEV)
+    info = srj.srj_solve_ir(p0, u, torch.from_numpy(wl["f"]).to(DEV), 1e-10, 1, 1000)
+    assert info["cycles"] == infos[0]["cycles"]
+    assert torch.equal(u, us[0])

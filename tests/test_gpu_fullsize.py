@@ -59,7 +59,7 @@ def test_blobs_4096_solve_stops_where_predicted(blobs):
     assert pred[m_pred] <= tol
     plan = srj.srj_plan(wl["n"], wl["h"], omega=w, q=q, sequence=seq)
     u = torch.from_numpy(wl["u0"]).to(DEV)
-    info = srj.srj_solve(plan, u, torch.from_numpy(wl["f"]).to(DEV), tol, 50 * M)
+    info = srj.srj_solve(plan, u, torch.from_numpy(wl["f"]).to(DEV), tol, 30 * M)
     assert info["status"] == "ok"
     near = abs(pred[m_pred] - tol) < 0.01 * tol or abs(pred[m_pred - 1] - tol) < 0.01 * tol
     assert info["cycles"] == m_pred or (near and abs(info["cycles"] - m_pred) == 1)
@@ -79,3 +79,33 @@ def test_smooth_512cube_window_bitwise():
     ref = sweeps.run(wl["u0"], b, c, n)
     got = u.cpu().numpy()
     assert np.array_equal(got, ref)
+
+
+def test_adjoint_2048_central_differences():
+    from paper_1511_04292_amd.autograd import srj_solve_diff
+
+    wl = workloads.adjoint_2d(2048)
+    plan = srj.srj_plan((2048, 2048), wl["h"], P=9)
+    f = torch.from_numpy(wl["f"]).to(DEV).requires_grad_(True)
+    g = torch.from_numpy(wl["g"]).to(DEV).requires_grad_(True)
+    ut = torch.from_numpy(wl["u_target"]).to(DEV)
+
+    M = int(srj.srj_plan_describe(plan)["M"])
+
+    def loss(ff, gg):
+        u = srj_solve_diff(ff, gg, plan, tol=1e-11, max_sweeps=30 * M)
+        return 0.5 * ((u - ut)[1:-1, 1:-1] ** 2).sum()
+
+    L = loss(f, g)
+    L.backward()
+    rng = np.random.default_rng(2)
+    for _ in range(16):
+        vf = np.zeros_like(wl["f"])
+        vf[1:-1, 1:-1] = rng.standard_normal((2048, 2048))
+        vg = workloads.random_ring(wl["f"].shape, rng)
+        eps = 1e-2
+        vft, vgt = torch.from_numpy(vf).to(DEV), torch.from_numpy(vg).to(DEV)
+        with torch.no_grad():
+            fd = (float(loss(f + eps * vft, g + eps * vgt)) - float(loss(f - eps * vft, g - eps * vgt))) / (2 * eps)
+        an = float((f.grad * vft).sum() + (g.grad * vgt).sum())
+        assert abs(fd - an) <= 1e-5 * abs(an), (fd, an)
