@@ -1,6 +1,6 @@
 // Batched SRJ solves: many independent 2D grids, each with its own schedule, refined in
-// FP64 around sweeps in the batch's storage format, advanced together by two kernels per
-// iteration (see batch.hip).
+// FP64 around sweeps in the batch's storage format, advanced together by one kernel launch
+// per iteration (see batch.hip).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -22,10 +22,10 @@ struct BProb {
     const double* bt2;       // -> ||b~||^2 of this problem
     int32_t M, coff;         // cycle length and offset of its c_k in the coefficient table
     int32_t inner_total;     // sweeps per inner solve (inner_cycles * M)
-    int32_t nstrip;          // strips of the fused sweep kernel
-    int32_t item0, nitems;   // first item and item count in the sweep work list
-    int32_t rb0, nrb;        // first residual block and block count in the residual list
-    int32_t pbase;           // first slot of its partial sums
+    int32_t nstrip;          // column strips of a tile row
+    int32_t ntiles;          // tiles (strips x row segments)
+    int32_t H;               // output rows per tile
+    int32_t pbase;           // first slot of its per-tile partial sums
     int32_t pad;
 };
 
@@ -33,29 +33,32 @@ struct BProb {
 enum { BP_SWEEP = 1, BP_DONE = 2, BP_DIVERGED = 3, BP_RESIDUAL = 4, BP_NOCONV = 5 };
 struct BState {
     int32_t phase, k, ucur, dcur;
-    int32_t outer, cnt_s, cnt_r, pad;
+    int32_t outer, cnt, pad0, pad1;
     double relres;
     uint64_t t_end;
 };
 
-// Per-solve constants shared by all problems.
+// One entry of the work list: a tile of a problem.
+struct BItem {
+    int32_t prob, tile;
+};
+
+// Per-solve constants and shared buffers.
 struct BRun {
     double tol;
     int32_t max_outer;
-    int32_t count;
-    int32_t nitems, nrb;  // totals of the two work lists
-    int32_t H;            // output rows per wave in the sweep kernel
     int32_t pad;
+    const BItem* items;   // work list (tiles of the problems still running)
+    const int* nitems;    // its length, rewritten by the host between graph replays
+    const double* coef;   // c_k of every problem (BProb::coff)
+    double* partials;     // per-tile residual partial sums (2 per tile)
     int* remaining;       // problems not yet finished
-    uint64_t* t0;         // wall clock at the start of the solve
 };
 
-int batch_fuse();  // sweeps fused per sweep-kernel launch
+int batch_fuse();  // sweeps fused per launch
 
 hipError_t launch_batch_start(uint64_t* t0, hipStream_t s);
-hipError_t launch_batch_sweep(Fmt f, const BProb* probs, BState* st, const int* item_prefix,
-                              const double* coef, const BRun& run, int grid_blocks, hipStream_t s);
-hipError_t launch_batch_residual(Fmt f, const BProb* probs, BState* st, const int* rb_prefix,
-                                 double* partials, const BRun& run, int grid_blocks, hipStream_t s);
+hipError_t launch_batch_step(Fmt f, const BProb* probs, BState* st, const BRun& run, int grid_blocks,
+                             hipStream_t s);
 
 }  // namespace srj

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -32,7 +33,25 @@ namespace {
     } while (0)
 
 constexpr int64_t kAlign = 512;
-constexpr int kH = 64;  // output rows per wave in the batch sweep kernel
+
+// Output rows per tile.  Tall tiles waste fewer halo rows (a tile of H output rows computes
+// H + 2T rows); short tiles give a problem more waves and each wave a shorter pipeline.  The
+// solve picks, whenever it rebuilds the work list, the tallest height in [kHmin, hmax] that
+// still gives the running problems at least `tiles_target` tiles, so that launches stay wide
+// while many problems run and become short once few remain.
+constexpr int kHmin = 16;
+
+int env_int(const char* name, int dflt, int lo, int hi)
+{
+    const char* e = std::getenv(name);
+    const int v = e ? std::atoi(e) : dflt;
+    return std::max(lo, std::min(v, hi));
+}
+
+int tiles_of(const Geo& g, int strip_w, int H)
+{
+    return (int)((g.nx + strip_w - 1) / strip_w) * (int)((g.ny + H - 1) / H);
+}
 
 struct Sched {
     std::vector<double> w;
@@ -127,18 +146,20 @@ struct srj_batch_s {
     std::vector<Geo> geos;
     std::vector<BProb> probs;      // host copy (device pointers inside)
     std::vector<int32_t> M;
-    int nitems = 0, nrb = 0, npart = 0;
+    int nitems = 0, npart = 0;
     void* pool = nullptr;
     BProb* probs_d = nullptr;
     BState* st_d = nullptr;
-    int* item_prefix_d = nullptr;
-    int* rb_prefix_d = nullptr;
+    BItem* items_d = nullptr;
+    int* nitems_d = nullptr;
     double* coef_d = nullptr;
     double* partials_d = nullptr;
     double* bt2_d = nullptr;  // 2 doubles per problem
     int* remaining_d = nullptr;
     uint64_t* t0_d = nullptr;
     int* remaining_h = nullptr;
+    int* nitems_h = nullptr;  // pinned staging of the work-list length
+    int items_h_len = 0;
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
 };
@@ -150,11 +171,12 @@ void destroy_batch(srj_batch_t b)
     if (!b) return;
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
-    void* ptrs[] = {b->pool, b->probs_d, b->st_d, b->item_prefix_d, b->rb_prefix_d, b->coef_d, b->partials_d,
+    void* ptrs[] = {b->pool, b->probs_d, b->st_d, b->items_d, b->nitems_d, b->coef_d, b->partials_d,
                     b->bt2_d, b->remaining_d, b->t0_d};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (b->remaining_h) (void)hipHostFree(b->remaining_h);
+    if (b->nitems_h) (void)hipHostFree(b->nitems_h);
     if (b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
 }
@@ -213,7 +235,6 @@ srj_status srj_batch_plan(int32_t count, const srj_grid* grids, const srj_schedu
         return origin;
     };
     b->geos.resize(count);
-    std::vector<int> item_prefix(count + 1, 0), rb_prefix(count + 1, 0);
     std::vector<double> coef;
     b->probs.resize(count);
     const int T = batch_fuse();
@@ -243,19 +264,14 @@ srj_status srj_batch_plan(int32_t count, const srj_grid* grids, const srj_schedu
         P.coff = (int32_t)coef.size();
         for (int64_t k = 0; k < sch[j].M; ++k) coef.push_back(sch[j].w[sch[j].seq[k]] / 4.0);
         P.nstrip = (int32_t)((g.nx + SW - 1) / SW);
-        const int nseg = (int)((g.ny + kH - 1) / kH);
-        P.item0 = item_prefix[j];
-        P.nitems = P.nstrip * nseg;
-        item_prefix[j + 1] = item_prefix[j] + P.nitems;
-        P.rb0 = rb_prefix[j];
-        P.nrb = (int32_t)((g.ny + 7) / 8);
-        rb_prefix[j + 1] = rb_prefix[j] + P.nrb;
+        P.H = kHmin;
+        P.ntiles = tiles_of(g, SW, kHmin);
         P.pbase = npart;
-        npart += std::max<int>(P.nrb, (int)((g.ny + 7) / 8));
+        // room for the tiles at the shortest height and for the start residual's blocks
+        npart += std::max<int>(P.ntiles, residual_blocks(g));
+        b->nitems += P.ntiles;
         b->M.push_back(P.M);
     }
-    b->nitems = item_prefix[count];
-    b->nrb = rb_prefix[count];
     b->npart = npart;
     if (hipMalloc(&b->pool, cur) != hipSuccess) {
         destroy_batch(b);
@@ -273,23 +289,22 @@ srj_status srj_batch_plan(int32_t count, const srj_grid* grids, const srj_schedu
     }
     bool ok = hipMalloc(&b->probs_d, sizeof(BProb) * count) == hipSuccess &&
               hipMalloc(&b->st_d, sizeof(BState) * count) == hipSuccess &&
-              hipMalloc(&b->item_prefix_d, sizeof(int) * (count + 1)) == hipSuccess &&
-              hipMalloc(&b->rb_prefix_d, sizeof(int) * (count + 1)) == hipSuccess &&
+              hipMalloc(&b->items_d, sizeof(BItem) * (size_t)b->nitems) == hipSuccess &&
+              hipMalloc(&b->nitems_d, sizeof(int)) == hipSuccess &&
               hipMalloc(&b->coef_d, sizeof(double) * std::max<size_t>(1, coef.size())) == hipSuccess &&
               hipMalloc(&b->partials_d, sizeof(double) * 2 * (size_t)npart) == hipSuccess &&
               hipMalloc(&b->bt2_d, sizeof(double) * 2 * count) == hipSuccess &&
               hipMalloc(&b->remaining_d, sizeof(int)) == hipSuccess &&
               hipMalloc(&b->t0_d, sizeof(uint64_t)) == hipSuccess &&
               hipHostMalloc(&b->remaining_h, sizeof(int), hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc(&b->nitems_h, sizeof(int), hipHostMallocDefault) == hipSuccess &&
               hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) == hipSuccess;
     if (!ok) {
         destroy_batch(b);
         return report(SRJ_ENOMEM, "batch scratch allocation failed");
     }
     for (int j = 0; j < count; ++j) b->probs[j].bt2 = b->bt2_d + 2 * j;
-    if (hipMemcpy(b->item_prefix_d, item_prefix.data(), sizeof(int) * (count + 1), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(b->rb_prefix_d, rb_prefix.data(), sizeof(int) * (count + 1), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(b->coef_d, coef.data(), sizeof(double) * coef.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    if (hipMemcpy(b->coef_d, coef.data(), sizeof(double) * coef.size(), hipMemcpyHostToDevice) != hipSuccess) {
         destroy_batch(b);
         return report(SRJ_EHIP, "batch table upload failed");
     }
@@ -346,25 +361,65 @@ srj_status srj_batch_solve(srj_batch_t b, double* const* u, const double* const*
             remaining += 1;
         }
     }
-    BCHK(hipMemcpyAsync(b->probs_d, b->probs.data(), sizeof(BProb) * b->count, hipMemcpyHostToDevice, s));
     BCHK(hipMemcpyAsync(b->st_d, st.data(), sizeof(BState) * b->count, hipMemcpyHostToDevice, s));
     *b->remaining_h = remaining;
     BCHK(hipMemcpyAsync(b->remaining_d, b->remaining_h, sizeof(int), hipMemcpyHostToDevice, s));
+    BCHK(hipStreamSynchronize(s));
+
+    // work list: the tiles of every running problem, at the height chosen for them
+    const int T = batch_fuse();
+    const int SW = 128 - 2 * T;
+    const int hmax = env_int("SRJ_BATCH_H", 128, kHmin, 1 << 20);
+    const int tiles_target = env_int("SRJ_BATCH_TILES", 4096, 1, 1 << 30);
+    std::vector<BItem> items;
+    items.reserve(b->nitems);
+    auto running = [](const BState& x) { return x.phase == BP_SWEEP || x.phase == BP_RESIDUAL; };
+    // returns true if some running problem changed its tile height
+    auto build_items = [&](const std::vector<BState>& cur) {
+        int H = kHmin;
+        for (int h = hmax; h >= kHmin; h /= 2) {
+            int64_t n = 0;
+            for (int j = 0; j < b->count; ++j)
+                if (running(cur[j])) n += tiles_of(b->geos[j], SW, h);
+            if (n >= tiles_target) {
+                H = h;
+                break;
+            }
+        }
+        bool changed = false;
+        items.clear();
+        for (int j = 0; j < b->count; ++j) {
+            if (!running(cur[j])) continue;
+            BProb& P = b->probs[j];
+            if (P.H != H) {
+                P.H = H;
+                P.ntiles = tiles_of(b->geos[j], SW, H);
+                changed = true;
+            }
+            for (int t = 0; t < P.ntiles; ++t) items.push_back(BItem{j, t});
+        }
+        b->items_h_len = (int)items.size();
+        return changed;
+    };
+    build_items(st);
+    BCHK(hipMemcpyAsync(b->probs_d, b->probs.data(), sizeof(BProb) * b->count, hipMemcpyHostToDevice, s));
+    if (!items.empty())
+        BCHK(hipMemcpyAsync(b->items_d, items.data(), sizeof(BItem) * items.size(), hipMemcpyHostToDevice, s));
+    *b->nitems_h = b->items_h_len;
+    BCHK(hipMemcpyAsync(b->nitems_d, b->nitems_h, sizeof(int), hipMemcpyHostToDevice, s));
     BCHK(hipStreamSynchronize(s));
 
     BRun run;
     std::memset(&run, 0, sizeof(run));
     run.tol = tol;
     run.max_outer = max_outer;
-    run.count = b->count;
-    run.nitems = b->nitems;
-    run.nrb = b->nrb;
-    run.H = kH;
+    run.items = b->items_d;
+    run.nitems = b->nitems_d;
+    run.coef = b->coef_d;
+    run.partials = b->partials_d;
     run.remaining = b->remaining_d;
-    run.t0 = b->t0_d;
     const int gs = std::max(1, std::min((b->nitems + 3) / 4, 2048));
-    const int gr = std::max(1, std::min(b->nrb, 4096));
-    // one graph = G iterations of (sweep, residual)
+    // one graph = G launches
     const int G = 16;
     if (b->exec) {
         (void)hipGraphExecDestroy(b->exec);
@@ -376,9 +431,7 @@ srj_status srj_batch_solve(srj_batch_t b, double* const* u, const double* const*
     }
     BCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     for (int it = 0; it < G; ++it) {
-        hipError_t e1 = launch_batch_sweep(b->fmt, b->probs_d, b->st_d, b->item_prefix_d, b->coef_d, run, gs, s);
-        hipError_t e2 = launch_batch_residual(b->fmt, b->probs_d, b->st_d, b->rb_prefix_d, b->partials_d, run, gr, s);
-        if (e1 != hipSuccess || e2 != hipSuccess) {
+        if (launch_batch_step(b->fmt, b->probs_d, b->st_d, run, gs, s) != hipSuccess) {
             hipGraph_t g0 = nullptr;
             (void)hipStreamEndCapture(s, &g0);
             if (g0) (void)hipGraphDestroy(g0);
@@ -387,20 +440,33 @@ srj_status srj_batch_solve(srj_batch_t b, double* const* u, const double* const*
     }
     BCHK(hipStreamEndCapture(s, &b->graph));
     BCHK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
-    // iterations needed at most: every outer step of the longest problem plus one
+    // launches needed at most: every outer step of the longest problem (its sweeps and its
+    // residual) plus the first residual
     int64_t max_inner = 0;
     for (int j = 0; j < b->count; ++j) max_inner = std::max<int64_t>(max_inner, b->probs[j].inner_total);
-    const int T = batch_fuse();
-    const int64_t cap_iters = ((int64_t)max_outer + 1) * ((max_inner + T - 1) / T + 1) + 2;
-    const int64_t cap_replays = cap_iters / G + 2;
+    const int64_t cap_launches = ((int64_t)max_outer + 1) * ((max_inner + T - 1) / T + 1) + 2;
+    const int64_t cap_replays = cap_launches / G + 2;
     BCHK(launch_batch_start(b->t0_d, s));
     int64_t replays = 0;
+    int listed = remaining;  // running problems when the work list was last built
     while (remaining > 0 && replays < cap_replays) {
         BCHK(hipGraphLaunch(b->exec, s));
         BCHK(hipMemcpyAsync(b->remaining_h, b->remaining_d, sizeof(int), hipMemcpyDeviceToHost, s));
         BCHK(hipStreamSynchronize(s));
         remaining = *b->remaining_h;
         replays += 1;
+        if (remaining > 0 && 4 * remaining <= 3 * listed) {
+            // drop finished problems from the work list
+            BCHK(hipMemcpyAsync(st.data(), b->st_d, sizeof(BState) * b->count, hipMemcpyDeviceToHost, s));
+            BCHK(hipStreamSynchronize(s));
+            if (build_items(st))
+                BCHK(hipMemcpyAsync(b->probs_d, b->probs.data(), sizeof(BProb) * b->count, hipMemcpyHostToDevice, s));
+            BCHK(hipMemcpyAsync(b->items_d, items.data(), sizeof(BItem) * items.size(), hipMemcpyHostToDevice, s));
+            *b->nitems_h = b->items_h_len;
+            BCHK(hipMemcpyAsync(b->nitems_d, b->nitems_h, sizeof(int), hipMemcpyHostToDevice, s));
+            BCHK(hipStreamSynchronize(s));
+            listed = remaining;
+        }
     }
     BCHK(hipMemcpyAsync(st.data(), b->st_d, sizeof(BState) * b->count, hipMemcpyDeviceToHost, s));
     uint64_t t0 = 0;
