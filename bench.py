@@ -177,7 +177,7 @@ def main():
     avg_launch = sec / launches
     bytes_launch = B_PER_POINT_F64 * pts
     achieved = bytes_launch / avg_launch / 1e9
-    kname = f"k_sweep2d_tb<double,{fuse},2>" if fuse > 0 else "k_sweep2d<double>"
+    kname = f"k_sweep2d_tb<double,{fuse},2,3>" if fuse > 0 else "k_sweep2d<double>"
     wname = f"blobs2d_{n}x{n}_f64"
     traffic = measured_traffic(kname, wname)
 

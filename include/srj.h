@@ -118,8 +118,10 @@ srj_status srj_plan_describe(srj_plan_t plan, srj_plan_desc* out);
 /* Copy the ordered level indices of one cycle (cap >= M) into seq. */
 srj_status srj_plan_sequence(srj_plan_t plan, int32_t* seq, int64_t cap);
 /* Override the number of sweeps fused per launch (0 = unfused reference kernel, at most 8)
- * and, if seg_rows > 0, the output rows each wave of the fused 2D kernel computes.  The
- * results do not depend on either value. */
+ * and the output rows each wave of the fused 2D kernel computes (seg_rows = 0, the
+ * default: chosen per launch so that the grid of waves fills the device's resident wave
+ * slots once, from the kernel's occupancy and the number of compute units).  The results
+ * do not depend on either value. */
 srj_status srj_plan_set_fusion(srj_plan_t plan, int32_t fused_sweeps, int32_t seg_rows);
 
 /* Solve to ||r||_2 / ||b~||_2 <= tol, checked at sweep 0 and at every cycle end (every

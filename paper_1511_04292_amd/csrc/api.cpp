@@ -66,7 +66,7 @@ struct srj_plan_s {
     std::vector<double> cseq;  // c_k = w_seq[k] / (2d)
     double kappa_min = 0, kappa_max = 0, rho = 0, gamma_q = 0, pre = 0, suf = 0;
     int fuse = 8;
-    int seg_rows = 64;  // output rows per wave in the fused 2D kernel
+    int seg_rows = 0;  // output rows per wave in the fused 2D kernel (0: from the occupancy)
 
     // device buffers
     DField A, B, blo, b64f;  // iterate pair, b in the sweep format, FP64 b (low-precision plans)
@@ -406,7 +406,7 @@ srj_status srj_plan_set_fusion(srj_plan_t p, int32_t fused, int32_t seg_rows)
     if (fused > 0 && p->geo.ndim != 2) return fail(SRJ_EINVAL, "fused sweeps are 2D only");
     if (seg_rows < 0 || seg_rows > (1 << 20)) return fail(SRJ_EINVAL, "segment rows must be in [0, 2^20]");
     p->fuse = fused;
-    if (seg_rows > 0) p->seg_rows = seg_rows;
+    p->seg_rows = seg_rows;
     return SRJ_OK;
 }
 

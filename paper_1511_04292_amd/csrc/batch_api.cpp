@@ -15,6 +15,7 @@
 #include "batch.h"
 #include "kernels.h"
 #include "planner.h"
+#include "tb_core.h"
 
 using namespace srj;
 
@@ -391,9 +392,10 @@ srj_status srj_batch_solve(srj_batch_t b, double* const* u, const double* const*
         for (int j = 0; j < b->count; ++j) {
             if (!running(cur[j])) continue;
             BProb& P = b->probs[j];
-            if (P.H != H) {
-                P.H = H;
-                P.ntiles = tiles_of(b->geos[j], SW, H);
+            const int Hj = std::max(kHmin, std::min(H, tb_max_rows(P.px, (int)fmt_size(b->fmt))));
+            if (P.H != Hj) {
+                P.H = Hj;
+                P.ntiles = tiles_of(b->geos[j], SW, Hj);
                 changed = true;
             }
             for (int t = 0; t < P.ntiles; ++t) items.push_back(BItem{j, t});

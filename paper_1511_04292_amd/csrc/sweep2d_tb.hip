@@ -10,6 +10,7 @@
 // overlap by T columns on each side, segments by T rows, the overlap being recomputed).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <cstdlib>
 
@@ -51,6 +52,22 @@ static int env_int(const char* name, int dflt)
     return v ? atoi(v) : dflt;
 }
 
+// Waves of one kernel instance that the device holds at once: blocks per CU (from the
+// kernel's register and LDS use) x 4 waves x CUs.
+template <class S, int T, int C, int D>
+static int tb_resident_waves()
+{
+    static const int waves = [] {
+        int nb = 0, dev = 0, ncu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep2d_tb<S, T, C, D>, 256, 0) != hipSuccess) nb = 1;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            ncu = 1;
+        return std::max(1, nb) * 4 * std::max(1, ncu);
+    }();
+    return waves;
+}
+
 template <class S, int T, int C, int D>
 static void tb2d(const S* in, S* out, const S* b, const Geo& g, const Coefs& co, int H, hipStream_t s)
 {
@@ -59,6 +76,14 @@ static void tb2d(const S* in, S* out, const S* b, const Geo& g, const Coefs& co,
     CoefsT<T> ct;
     for (int l = 0; l < T; ++l) ct.c[l] = co.c[l];
     const int nstrip = (int)((g.nx + SW - 1) / SW);
+    if (H <= 0) {
+        // One round: as many row segments as leave every resident wave slot one tile, so
+        // that all waves start together and the device stays full until they end.  Below
+        // 2T rows a tile would spend most of its steps filling the pipeline.
+        const int per_strip = std::max(1, tb_resident_waves<S, T, C, D>() / nstrip);
+        H = std::max((int)((g.ny + per_strip - 1) / per_strip), std::max(2 * T, 8));
+    }
+    H = std::min(H, tb_max_rows(g.px, (int)sizeof(S)));
     const int nseg = (int)((g.ny + H - 1) / H);
     const int nwaves = nstrip * nseg;
     const int nblk = ((nwaves + 3) / 4 + 7) / 8 * 8;
@@ -81,16 +106,19 @@ static void tb2d_T(const S* in, S* out, const S* b, const Geo& g, const Coefs& c
     }
 }
 
+// Rows in flight per wave: 3 for binary64 (its unrolled loop then matches the 3-row window
+// and the kernel keeps 3 waves per SIMD), 4 for the 4-byte and 2-byte formats.
 template <class S>
 static void tb2d_dispatch(const S* in, S* out, const S* b, const Geo& g, const Coefs& co, int T,
                           int H, hipStream_t s)
 {
     constexpr int C = 2;
-    static const int pf = env_int("SRJ_TB_PREFETCH", 4);
-    if (pf == 1) {
-        tb2d_T<S, C, 1>(in, out, b, g, co, T, H, s);
-    } else if (pf == 2) {
+    static const int knob = env_int("SRJ_TB_PREFETCH", 0);  // tuning knob, 0 = per format
+    const int pf = knob > 0 ? knob : (sizeof(S) == 8 ? 3 : 4);
+    if (pf == 2) {
         tb2d_T<S, C, 2>(in, out, b, g, co, T, H, s);
+    } else if (pf == 3) {
+        tb2d_T<S, C, 3>(in, out, b, g, co, T, H, s);
     } else {
         tb2d_T<S, C, 4>(in, out, b, g, co, T, H, s);
     }
@@ -99,7 +127,7 @@ static void tb2d_dispatch(const S* in, S* out, const S* b, const Geo& g, const C
 hipError_t launch_sweep_fused(Fmt f, const void* in, void* out, const void* b, const Geo& g,
                               const Coefs& co, int T, int H, hipStream_t s)
 {
-    if (g.ndim != 2 || T < 1 || T > kMaxFuse || H < 1) return hipErrorInvalidValue;
+    if (g.ndim != 2 || T < 1 || T > kMaxFuse || H < 0) return hipErrorInvalidValue;  // H = 0: automatic
     SRJ_DISPATCH(f, tb2d_dispatch<S>((const S*)in, (S*)out, (const S*)b, g, co, T, H, s));
     return hipGetLastError();
 }

@@ -11,27 +11,24 @@
 namespace srj {
 
 // Lane shifts through DPP (wave_shr:1 / wave_shl:1): lane i receives lane i-1 (resp. i+1).
-// The wave's edge lanes receive 0; their results are never stored.
-__device__ __forceinline__ float dpp_from_left(float v)
-{
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
-}
-__device__ __forceinline__ float dpp_from_right(float v)
-{
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
-}
+// The wave's edge lanes have no source and receive 0 (bound_ctrl); their results are never
+// stored.
+__device__ __forceinline__ int dpp_shr1(int v) { return __builtin_amdgcn_mov_dpp(v, 0x138, 0xf, 0xf, true); }
+__device__ __forceinline__ int dpp_shl1(int v) { return __builtin_amdgcn_mov_dpp(v, 0x130, 0xf, 0xf, true); }
+__device__ __forceinline__ float dpp_from_left(float v) { return __int_as_float(dpp_shr1(__float_as_int(v))); }
+__device__ __forceinline__ float dpp_from_right(float v) { return __int_as_float(dpp_shl1(__float_as_int(v))); }
 __device__ __forceinline__ double dpp_from_left(double v)
 {
     const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), 0x138, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x138, 0xf, 0xf, false);
+    const int lo = dpp_shr1((int)(b & 0xffffffffll));
+    const int hi = dpp_shr1((int)(b >> 32));
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 __device__ __forceinline__ double dpp_from_right(double v)
 {
     const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), 0x130, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x130, 0xf, 0xf, false);
+    const int lo = dpp_shl1((int)(b & 0xffffffffll));
+    const int hi = dpp_shl1((int)(b >> 32));
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
@@ -45,52 +42,165 @@ __device__ __forceinline__ int vcopy(int x)
     return y;
 }
 
+// Stores of the tile go through a raw buffer resource whose range check drops the stores of
+// masked lanes and rows (their byte offset is pushed past the record count), so the step
+// loop stores without branches and the compiler can keep the row loads of later steps in
+// flight across it.
+typedef unsigned int tb_u32x2 __attribute__((ext_vector_type(2)));
+constexpr int kTbMasked = 0x40000000;  // offset added for a masked row; the record count stays below it
+
+__device__ __forceinline__ void tb_store(double v, __amdgpu_buffer_rsrc_t r, int off)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(tb_u32x2, v), r, off, 0, 0);
+}
+__device__ __forceinline__ void tb_store(float v, __amdgpu_buffer_rsrc_t r, int off)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, off, 0, 0);
+}
+__device__ __forceinline__ void tb_store(bf16_t v, __amdgpu_buffer_rsrc_t r, int off)
+{
+    __builtin_amdgcn_raw_buffer_store_b16(v.v, r, off, 0, 0);
+}
+
+// Largest segment height whose store window (H rows of pitch px plus one strip) keeps the
+// buffer record count below kTbMasked.
+inline int tb_max_rows(int64_t px, int esize)
+{
+    const int64_t lim = ((int64_t)kTbMasked / esize - 256) / px;
+    return (int)(lim < 1 ? 1 : (lim > (1 << 20) ? (1 << 20) : lim));
+}
+
+// Pipeline state of one wave: T time levels of a 3-row window (rows r-l-1 .. r-l+1 of level
+// l-1 held as p2, p1 and the incoming value), the scaled source of the row each level works
+// on (bq[l-1] = b of row r-l), and D rows of u and b in flight.
+template <class Cm, int T, int C, int D>
+struct TbRegs {
+    Cm p1[T][C], p2[T][C], bq[T][C];
+    Cm U[D][C], B[D][C];
+};
+
+// One step of the pipeline: level-0 row r arrives from slot s; levels 1..lmax are computed
+// (lmax < T only while the pipeline fills: level l is first needed at step 2l of the tile);
+// the value of level T for row r - T is stored if that row is an output row of the tile.
+// CLEAN steps know that every computed point is an interior point of the grid and that
+// all T levels apply, and so skip the per-level selects.
+template <class S, int T, int C, int D, bool CLEAN>
+__device__ __forceinline__ void tb_step(TbRegs<typename Tr<S>::C, T, C, D>& R, int s, int lmax, int r,
+                                        const typename Tr<S>::C (&cf)[T], const bool (&upd)[C], int ny,
+                                        int Tact, int y0, int y1, int rowbytes, const int (&lanebase)[C],
+                                        __amdgpu_buffer_rsrc_t rs)
+{
+    using Cm = typename Tr<S>::C;
+    Cm in[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) in[c] = R.U[s][c];
+    const int rv = CLEAN ? 0 : vcopy(r);
+#pragma unroll
+    for (int l = 1; l <= T; ++l) {
+        if (l > lmax + 1) break;
+        Cm out[C];
+        if (l <= lmax) {
+            const Cm wn = dpp_from_left(R.p1[l - 1][C - 1]);
+            const Cm en = dpp_from_right(R.p1[l - 1][0]);
+            bool rowok = true;
+            if (!CLEAN) {
+                const int jv = rv - l;
+                rowok = (jv >= 1) & (jv <= ny) & (l <= Tact);
+            }
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const Cm W = (c == 0) ? wn : R.p1[l - 1][c - 1];
+                const Cm E = (c == C - 1) ? en : R.p1[l - 1][c + 1];
+                const Cm m = R.p1[l - 1][c];
+                const Cm sm = (W + E) + (R.p2[l - 1][c] + in[c]);
+                const Cm t = (sm + R.bq[l - 1][c]) - (Cm)4 * m;
+                Cm v = Tr<S>::ld(Tr<S>::st(m + cf[l - 1] * t));
+                if (CLEAN) {
+                    out[c] = v;
+                } else {
+                    // v is always computed: an empty register constraint keeps the compiler
+                    // from sinking its arithmetic under a branch
+                    asm("" : "+v"(v));
+                    out[c] = (rowok && upd[c]) ? v : m;
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            R.p2[l - 1][c] = R.p1[l - 1][c];
+            R.p1[l - 1][c] = in[c];
+            if (l <= lmax) in[c] = out[c];
+        }
+    }
+    if (lmax == T) {
+        const int j = r - T;
+        const int rowpart = (j >= y0 && j < y1) ? (j - y0) * rowbytes : kTbMasked;
+#pragma unroll
+        for (int c = 0; c < C; ++c) tb_store(Tr<S>::st(in[c]), rs, rowpart + lanebase[c]);
+    }
+#pragma unroll
+    for (int l = T - 1; l > 0; --l)
+#pragma unroll
+        for (int c = 0; c < C; ++c) R.bq[l][c] = R.bq[l - 1][c];
+#pragma unroll
+    for (int c = 0; c < C; ++c) R.bq[0][c] = R.B[s][c];
+}
+
 // One wave computes Tact <= T consecutive sweeps (coefficients cf[0..Tact)) of the tile
 // (strip st, segment sg) of an nx x ny grid: strip st covers columns x0 .. x0 + 64C - 1 with
 // x0 = 1 + st*SW - T (SW = 64C - 2T output columns per strip); segment sg outputs rows
-// y0 .. y1-1.  At step r the wave takes row r (level 0) and computes level l for row r - l,
-// l = 1..T, from level l-1 rows r-l-1, r-l, r-l+1; the value of level T for row r - T is
-// stored if that row belongs to the segment.  Levels above Tact pass values through
-// unchanged.  Ring rows/columns never change; lanes or rows outside the grid read clamped
-// (in-bounds) addresses and are never updated or stored, and only points whose dependence
-// cone lies inside the loaded window are stored.  The step loop is free of branches so
-// that the D row loads in flight (register slots named statically by unrolling the loop D
-// times) overlap D steps of arithmetic.
-template <class S, int T, int C, int D>
-__device__ __forceinline__ void tb_tile(const S* __restrict__ uin, S* __restrict__ uout,
-                                        const S* __restrict__ bb, int64_t px, int nx, int ny,
-                                        const typename Tr<S>::C (&cf)[T], int Tact, int st, int sg,
-                                        int H)
+// y0 .. y1-1 (H rows, fewer in the last segment).  The wave streams rows y0-T .. y1-1+T:
+// at step r it takes row r (level 0) and computes level l for row r - l, l = 1..T, from
+// level l-1 rows r-l-1, r-l, r-l+1; the value of level T for row r - T is stored if that row
+// belongs to the segment.  Levels above Tact pass values through unchanged.  Ring rows and
+// columns never change; rows outside the grid read clamped (in-bounds) addresses and are
+// never updated or stored, and only points whose dependence cone lies inside the loaded
+// window are stored.  The first steps (pipeline fill) compute only the levels whose rows
+// are needed; the rest of the step loop is free of branches so that the D row loads in
+// flight (register slots named statically by unrolling the loop D times) overlap D steps
+// of arithmetic.  H * px * sizeof(S) must not exceed what tb_max_rows allows.
+template <class S, int T, int C, int D, bool CLEAN>
+__device__ __forceinline__ void tb_tile_body(const S* __restrict__ uin, S* __restrict__ uout,
+                                             const S* __restrict__ bb, int64_t px, int nx, int ny,
+                                             const typename Tr<S>::C (&cf)[T], int Tact, int st, int sg, int H)
 {
     using Cm = typename Tr<S>::C;
     constexpr int SW = 64 * C - 2 * T;
+    constexpr int F = (2 * T + D - 1) / D * D;  // fill steps, a whole number of slot rounds
     const int lane = threadIdx.x & 63;
-    const int64_t x0 = 1 + (int64_t)st * SW - T + (int64_t)lane * C;
+    const int64_t xs = 1 + (int64_t)st * SW - T;  // first column of the strip
+    const int64_t x0 = xs + (int64_t)lane * C;
     const int y0 = 1 + sg * H;
     const int y1 = min(y0 + H, ny + 1);
-    const int rb = max(0, y0 - T);
+    const int rb = y0 - T;
     const int rl = y1 - 1 + T;
 
-    bool upd[C], outc[C];
+    bool upd[C];
     int64_t xc[C];
+    int lanebase[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         const int64_t x = x0 + c;
         const int off = lane * C + c;
         upd[c] = (x >= 1 && x <= (int64_t)nx);
-        outc[c] = upd[c] && off >= T && off < 64 * C - T;
+        const bool outc = upd[c] && off >= T && off < 64 * C - T;
+        lanebase[c] = off * (int)sizeof(S) + (outc ? 0 : (int)0x80000000);
         xc[c] = x < 0 ? 0 : (x > (int64_t)nx + 1 ? (int64_t)nx + 1 : x);
     }
+    const int rowbytes = (int)(px * (int64_t)sizeof(S));
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(uout + (int64_t)y0 * px + xs), (short)0, (int)((int64_t)H * rowbytes + 128 * (int)sizeof(S)),
+        0x00020000);
 
-    Cm p1[T][C], p2[T][C], bq[T][C];
+    TbRegs<Cm, T, C, D> R;
 #pragma unroll
     for (int l = 0; l < T; ++l)
 #pragma unroll
-        for (int c = 0; c < C; ++c) p1[l][c] = p2[l][c] = bq[l][c] = (Cm)0;
+        for (int c = 0; c < C; ++c) R.p1[l][c] = R.p2[l][c] = R.bq[l][c] = (Cm)0;
 
-    // in-bounds loads of row r (clamped to the last ring row)
+    // in-bounds loads of row r (clamped to the ring rows)
     auto load_row = [&](int r, Cm* vu, Cm* vb) {
-        const int64_t rowp = (int64_t)min(r, ny + 1) * px;
+        const int64_t rowp = (int64_t)max(0, min(r, ny + 1)) * px;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             vu[c] = Tr<S>::ld(uin[rowp + xc[c]]);
@@ -98,61 +208,47 @@ __device__ __forceinline__ void tb_tile(const S* __restrict__ uin, S* __restrict
         }
     };
 
-    Cm U[D][C], B[D][C];
 #pragma unroll
-    for (int s = 0; s < D; ++s) load_row(rb + s, U[s], B[s]);
+    for (int s = 0; s < D; ++s) load_row(rb + s, R.U[s], R.B[s]);
 
-    const int nsteps = rl - rb + 1;
-    for (int r0 = rb; r0 < rb + nsteps; r0 += D) {
+    // pipeline fill, unrolled: step i needs levels 1 .. i/2
+#pragma unroll
+    for (int i = 0; i < F; ++i) {
+        const int s = i % D;
+        const int lmax = min(T, i / 2);
+        tb_step<S, T, C, D, CLEAN>(R, s, lmax, rb + i, cf, upd, ny, Tact, y0, y1, rowbytes, lanebase, rs);
+        load_row(rb + i + D, R.U[s], R.B[s]);
+        // keep each row load in its step: bunched at the end of the loop body they would be
+        // waited for at the top of the next iteration
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    // steady state: all levels, D steps per iteration (the last may run past rl: its rows
+    // are loaded clamped and never stored)
+    for (int r0 = rb + F; r0 <= rl; r0 += D) {
 #pragma unroll
         for (int s = 0; s < D; ++s) {
-            const int r = r0 + s;
-            const int rv = vcopy(r);
-            Cm in[C];
-#pragma unroll
-            for (int c = 0; c < C; ++c) in[c] = U[s][c];
-#pragma unroll
-            for (int l = 1; l <= T; ++l) {
-                const int jv = rv - l;
-                const bool rowok = (jv >= 1) & (jv <= ny) & (l <= Tact);
-                const Cm wn = dpp_from_left(p1[l - 1][C - 1]);
-                const Cm en = dpp_from_right(p1[l - 1][0]);
-                Cm out[C];
-#pragma unroll
-                for (int c = 0; c < C; ++c) {
-                    const Cm W = (c == 0) ? wn : p1[l - 1][c - 1];
-                    const Cm E = (c == C - 1) ? en : p1[l - 1][c + 1];
-                    const Cm m = p1[l - 1][c];
-                    const Cm sm = (W + E) + (p2[l - 1][c] + in[c]);
-                    const Cm t = (sm + bq[l - 1][c]) - (Cm)4 * m;
-                    Cm v = Tr<S>::ld(Tr<S>::st(m + cf[l - 1] * t));
-                    // v is always computed: an empty register constraint keeps the compiler
-                    // from sinking its arithmetic under a branch
-                    asm("" : "+v"(v));
-                    out[c] = (rowok && upd[c]) ? v : m;
-                }
-#pragma unroll
-                for (int c = 0; c < C; ++c) {
-                    p2[l - 1][c] = p1[l - 1][c];
-                    p1[l - 1][c] = in[c];
-                    in[c] = out[c];
-                }
-            }
-            const int j = r - T;
-            const bool rowout = (j >= y0) & (j < y1);
-            S* po = uout + (int64_t)j * px + x0;
-#pragma unroll
-            for (int c = 0; c < C; ++c)
-                if (rowout && outc[c]) po[c] = Tr<S>::st(in[c]);
-#pragma unroll
-            for (int l = T - 1; l > 0; --l)
-#pragma unroll
-                for (int c = 0; c < C; ++c) bq[l][c] = bq[l - 1][c];
-#pragma unroll
-            for (int c = 0; c < C; ++c) bq[0][c] = B[s][c];
-            load_row(r + D, U[s], B[s]);
+            tb_step<S, T, C, D, CLEAN>(R, s, T, r0 + s, cf, upd, ny, Tact, y0, y1, rowbytes, lanebase, rs);
+            load_row(r0 + s + D, R.U[s], R.B[s]);
+            __builtin_amdgcn_sched_barrier(0);
         }
     }
+}
+
+template <class S, int T, int C, int D>
+__device__ __forceinline__ void tb_tile(const S* __restrict__ uin, S* __restrict__ uout,
+                                        const S* __restrict__ bb, int64_t px, int nx, int ny,
+                                        const typename Tr<S>::C (&cf)[T], int Tact, int st, int sg, int H)
+{
+    constexpr int SW = 64 * C - 2 * T;
+    const int64_t xs = 1 + (int64_t)st * SW - T;
+    const int y0 = 1 + sg * H;
+    const int y1 = min(y0 + H, ny + 1);
+    // every computed point interior: rows y0-T+1 .. y1+T-2 and the strip's columns
+    const bool clean = Tact == T && y0 - T + 1 >= 1 && y1 + T - 2 <= ny && xs >= 1 && xs + 64 * C - 1 <= nx;
+    if (clean)
+        tb_tile_body<S, T, C, D, true>(uin, uout, bb, px, nx, ny, cf, Tact, st, sg, H);
+    else
+        tb_tile_body<S, T, C, D, false>(uin, uout, bb, px, nx, ny, cf, Tact, st, sg, H);
 }
 
 }  // namespace srj
