@@ -27,11 +27,93 @@ HBM_PEAK_GBS = 8000.0
 B_PER_POINT_F64 = 24.0  # read u, read b, write u
 
 
+# Sources the fused 2D sweep is compiled from: counter-derived traffic is used only while
+# they are unchanged.
+FUSED_SOURCES = ("sweep2d_tb.hip", "tb_core.h", "formats.h")
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_1511_04292_amd", "csrc", "sweep2d_tb.hip"), "rb") as fh:
-        h.update(fh.read())
+    for name in FUSED_SOURCES:
+        with open(os.path.join(ROOT, "paper_1511_04292_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def ingest_counters(fetch_dir, write_dir, workload="blobs2d_4096x4096_f64"):
+    """Turn the counter CSVs of two `rocprofv3 --pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs of
+    `bench.py --kernel-only` into HBM bytes per launch: each counter is scaled by what it reads
+    for the calibration kernel (torch's elementwise multiply over 1 GiB in, 1 GiB out).  Writes
+    profiles/traffic.json and returns a markdown table."""
+    import csv
+    import glob
+
+    def per_kernel(d, counter):
+        acc = {}
+        for fn in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(fn)):
+                if r["Counter_Name"] != counter:
+                    continue
+                k = r["Kernel_Name"]
+                acc.setdefault(k, []).append(float(r["Counter_Value"]))
+        return {k: (sum(v) / len(v), len(v)) for k, v in acc.items()}
+
+    fetch = per_kernel(fetch_dir, "FETCH_SIZE")
+    write = per_kernel(write_dir, "WRITE_SIZE")
+    gib_kib = float(1 << 20)
+    cal = [k for k in fetch if "elementwise" in k and "Mul" in k]
+    if not cal:
+        raise SystemExit("no calibration kernel in the counter runs")
+    fscale = gib_kib / fetch[cal[0]][0]
+    wscale = gib_kib / write[cal[0]][0]
+    n = 4096
+    rows, out = [], {}
+    for k, (fk, cnt) in sorted(fetch.items()):
+        if "srj::" not in k:
+            continue
+        wk = write.get(k, (float("nan"), 0))[0]
+        rb = fk * 1024 * fscale
+        wb = wk * 1024 * wscale
+        short = k.split("(")[0].replace("void ", "").replace("srj::", "")
+        rows.append(f"| `{short}` | {cnt} | {fk:.0f} | {wk:.0f} | {rb / 1e6:.1f} + {wb / 1e6:.1f} = {(rb + wb) / 1e6:.1f} |")
+        if short.startswith("k_sweep2d_tb<double, 8, 2,"):
+            d = short.split(",")[-1].strip(" >")
+            out[f"k_sweep2d_tb<double,8,2,{d}>|{workload}"] = {
+                "bytes_per_launch": int(rb + wb), "read_bytes": int(rb), "write_bytes": int(wb),
+                "fetch_scale": round(fscale, 4), "write_scale": round(wscale, 4),
+                "kernel_source_sha256_16": kernel_source_hash(),
+                "kernel_sources": [f"paper_1511_04292_amd/csrc/{x}" for x in FUSED_SOURCES],
+                "algorithmic_bytes_per_launch": 24 * n * n}
+    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
+        json.dump(out, fh, indent=1)
+    head = (f"Calibration: FETCH_SIZE scale {fscale:.4f}, WRITE_SIZE scale {wscale:.4f} "
+            f"(torch multiply over 1 GiB binary64 in, 1 GiB out)\n\n"
+            "| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | scaled HBM MB (read + write) |\n"
+            "|---|---|---|---|---|")
+    return head + "\n" + "\n".join(rows)
+
+
+def summarize_trace(trace_dir):
+    """Per-kernel launch statistics from a `rocprofv3 --kernel-trace` CSV, split by grid size
+    (so launches of the same kernel on different workloads stay apart), as a markdown table."""
+    import csv
+    import glob
+
+    groups = {}
+    for fn in glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True):
+        for r in csv.DictReader(open(fn)):
+            key = (r["Kernel_Name"].split("(")[0].replace("void ", ""),
+                   f'{r["Grid_Size_X"]}x{r["Grid_Size_Y"]}x{r["Grid_Size_Z"]}')
+            groups.setdefault(key, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    total = sum(sum(v) for v in groups.values())
+    lines = ["| kernel | grid (threads) | calls | total ms | average us | min us | max us | % |",
+             "|---|---|---|---|---|---|---|---|"]
+    for (name, grid), v in sorted(groups.items(), key=lambda kv: -sum(kv[1])):
+        if sum(v) < 1e-3 * total:
+            continue
+        lines.append(f"| `{name}` | {grid} | {len(v)} | {sum(v) / 1e3:.2f} | {sum(v) / len(v):.2f} | "
+                     f"{min(v):.1f} | {max(v):.1f} | {100 * sum(v) / total:.2f} |")
+    return "\n".join(lines)
 
 
 def measured_traffic(kernel, workload):
@@ -92,10 +174,21 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--workloads", default="all", choices=["all", "main"],
                     help="'all' also measures the 3D, batched and differentiable workloads")
+    ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="read the counter CSVs of two --kernel-only runs under rocprofv3 --pmc "
+                         "FETCH_SIZE / WRITE_SIZE, write profiles/traffic.json, print a table")
+    ap.add_argument("--summarize-trace", metavar="TRACE_DIR",
+                    help="print per-kernel, per-grid launch statistics of a rocprofv3 --kernel-trace run")
     ap.add_argument("--kernel-only", action="store_true",
                     help="counter-collection run: one 1 GiB read / 1 GiB write calibration kernel, then "
                          "20 fused and 20 unfused sweep launches on the workload; prints no JSON")
     args = ap.parse_args()
+    if args.ingest_counters:
+        print(ingest_counters(*args.ingest_counters))
+        return
+    if args.summarize_trace:
+        print(summarize_trace(args.summarize_trace))
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the SRJ solver here runs on a single MI355X; "

@@ -19,6 +19,7 @@
 #include <cstdlib>
 
 #include "formats.h"
+#include "tb_core.h"
 #include "kernels.h"
 
 namespace srj {
@@ -107,12 +108,15 @@ __global__ __launch_bounds__(256) void k_sweep2d(const S* __restrict__ u, S* __r
 }
 
 // One 3D sweep: threads over (x, y) (block of 64 x BY), each walking a run of z planes with
-// the z neighbours and D planes ahead kept in registers.  The z loop is branch-free (clamped
-// plane index) so the loads of the next D planes stay in flight while a plane computes.
+// the z neighbours and D planes ahead kept in registers.  The y neighbours of a block's rows
+// come from its own loads through L1 except on its first and last row, so taller blocks
+// fetch fewer extra rows from HBM.  The z loop is branch-free (clamped plane index; the
+// stores of planes past the run are dropped by the range check of a buffer resource that
+// covers the run) so the loads of the next D planes stay in flight while a plane computes.
 template <class S, int D>
-__global__ __launch_bounds__(256) void k_sweep3d(const S* __restrict__ u, S* __restrict__ o,
-                                                 const S* __restrict__ b, int64_t px, int64_t py,
-                                                 int nx, int ny, int nz, int zrun, double c64)
+__global__ __launch_bounds__(1024) void k_sweep3d(const S* __restrict__ u, S* __restrict__ o,
+                                                  const S* __restrict__ b, int64_t px, int64_t py,
+                                                  int nx, int ny, int nz, int zrun, double c64)
 {
     using Cm = typename Tr<S>::C;
     const int j = blockIdx.x * 64 + threadIdx.x + 1;
@@ -123,6 +127,8 @@ __global__ __launch_bounds__(256) void k_sweep3d(const S* __restrict__ u, S* __r
     const Cm c = (Cm)c64;
     const int64_t pl = px * py;
     const int64_t col = (int64_t)i * px + j;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(o + (int64_t)k0 * pl), (short)0, (int)((int64_t)(k1 - k0) * pl * (int64_t)sizeof(S)), 0x00020000);
     Cm dn = Tr<S>::ld(u[(int64_t)(k0 - 1) * pl + col]);
     Cm m = Tr<S>::ld(u[(int64_t)k0 * pl + col]);
     Cm Q[D];
@@ -138,7 +144,8 @@ __global__ __launch_bounds__(256) void k_sweep3d(const S* __restrict__ u, S* __r
                            (Tr<S>::ld(u[p - px]) + Tr<S>::ld(u[p + px]))) +
                           (dn + up);
             const Cm t = (sm + Tr<S>::ld(b[p])) - (Cm)6 * m;
-            if (k < k1) o[p] = Tr<S>::st(m + c * t);
+            // planes k >= k1 land at or past the record count and are dropped
+            tb_store(Tr<S>::st(m + c * t), rs, (int)(((int64_t)(k - k0) * pl + col) * (int64_t)sizeof(S)));
             dn = m;
             m = up;
             Q[s] = Tr<S>::ld(u[(int64_t)min(k + 1 + D, nz + 1) * pl + col]);
@@ -384,9 +391,12 @@ hipError_t launch_sweep_unfused(Fmt f, const void* in, void* out, const void* b,
         SRJ_DISPATCH(f, hipLaunchKernelGGL(k_sweep2d<S>, grid, dim3(64, 4), 0, s, (const S*)in, (S*)out,
                                            (const S*)b, g.px, (int)g.nx, (int)g.ny, c));
     } else {
-        static const int zrun = env_int("SRJ_3D_ZRUN", 32);
-        static const int by = std::min(4, std::max(1, env_int("SRJ_3D_BY", 4)));
+        static const int zrun_knob = env_int("SRJ_3D_ZRUN", 32);
+        static const int by = std::min(16, std::max(1, env_int("SRJ_3D_BY", 4)));
         static const int pf = env_int("SRJ_3D_PREFETCH", 2);
+        // the run's byte offsets (plus D planes of overshoot) stay below 2^31
+        const int64_t zmax = ((int64_t)1 << 31) / ((int64_t)fmt_size(f) * g.px * g.py) - 6;
+        const int zrun = (int)std::max<int64_t>(1, std::min<int64_t>(zrun_knob, zmax));
         dim3 grid((unsigned)((g.nx + 63) / 64), (unsigned)((g.ny + by - 1) / by), (unsigned)((g.nz + zrun - 1) / zrun));
         dim3 blk(64, by);
         if (pf <= 1) {
