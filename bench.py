@@ -358,11 +358,16 @@ def bench_3d(torch, srj, workloads, n=512, levels=8, tol=1e-10):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         bpp = {"f64": 24, "f32": 12, "bf16": 6}[fmt]
+        launch_s = sec / launches
+        per_sweep = sec / 32
         r = {"time_to_tol_s": round(dt, 4), "sweeps": int(info["sweeps"]), "cycles_or_outer": int(info["cycles"]),
              "relres": info["relres"], "status": info["status"], "GLUP_s": round(pts * info["sweeps"] / dt / 1e9, 2),
-             "sweep_kernel_us": round(sec / launches * 1e6, 1),
-             "sweep_kernel_GBs": round(bpp * pts / (sec / launches) / 1e9, 1),
-             "sweep_kernel_hbm_frac": round(bpp * pts / (sec / launches) / 1e9 / HBM_PEAK_GBS, 4)}
+             "fused_sweeps": int(srj.srj_plan_describe(plan)["fused_sweeps"]),
+             "launch_us": round(launch_s * 1e6, 1), "per_sweep_us": round(per_sweep * 1e6, 1),
+             # algorithmic bytes of one launch (u, b read once, u written once) over its time
+             "launch_algorithmic_GBs": round(bpp * pts / launch_s / 1e9, 1),
+             # effective sweep rate over the unfused sweep's HBM roofline (8 TB/s / bytes per update)
+             "per_sweep_hbm_roofline_frac": round(pts / per_sweep / (HBM_PEAK_GBS * 1e9 / bpp), 3)}
         if fmt == "f64":
             ref = u
             r["M"] = int(srj.srj_plan_describe(plan)["M"])

@@ -195,7 +195,7 @@ srj_status run_sweeps(srj_plan_t p, DField** cur, DField** nxt, const void* b, i
     int64_t k = k0;
     const int64_t end = k0 + n;
     while (k < end) {
-        if (p->fuse <= 0 || p->geo.ndim != 2) {
+        if (p->fuse <= 0) {
             HIPCHK(launch_sweep_unfused(p->fmt, (*cur)->origin, (*nxt)->origin, b, p->geo,
                                         p->cseq[k % p->M], p->stream));
             k += 1;
@@ -204,8 +204,11 @@ srj_status run_sweeps(srj_plan_t p, DField** cur, DField** nxt, const void* b, i
             int T = (int)std::min<int64_t>({(int64_t)p->fuse, end - k, to_cycle_end});
             Coefs co;
             for (int l = 0; l < T; ++l) co.c[l] = p->cseq[(k + l) % p->M];
-            HIPCHK(launch_sweep_fused(p->fmt, (*cur)->origin, (*nxt)->origin, b, p->geo, co, T, p->seg_rows,
-                                      p->stream));
+            if (p->geo.ndim == 2)
+                HIPCHK(launch_sweep_fused(p->fmt, (*cur)->origin, (*nxt)->origin, b, p->geo, co, T, p->seg_rows,
+                                          p->stream));
+            else
+                HIPCHK(launch_sweep_fused3d(p->fmt, (*cur)->origin, (*nxt)->origin, b, p->geo, co, T, p->stream));
             k += T;
         }
         if (launches) *launches += 1;
@@ -359,7 +362,7 @@ srj_status srj_plan(const srj_grid* grid, const srj_schedule* schedule, void* st
         destroy(p);
         return fail(SRJ_EHIP, "initial fill failed");
     }
-    p->fuse = (g.ndim == 2) ? 8 : 0;
+    p->fuse = (g.ndim == 2) ? kMaxFuse : (fused3d_fits(g, p->fmt) ? kMaxFuse3d : 0);
     *out = p;
     return SRJ_OK;
 }
@@ -403,7 +406,9 @@ srj_status srj_plan_set_fusion(srj_plan_t p, int32_t fused, int32_t seg_rows)
 {
     if (!p) return fail(SRJ_EINVAL, "null plan");
     if (fused < 0 || fused > kMaxFuse) return fail(SRJ_EINVAL, "fusion depth must be in [0, 8]");
-    if (fused > 0 && p->geo.ndim != 2) return fail(SRJ_EINVAL, "fused sweeps are 2D only");
+    if (p->geo.ndim == 3 && fused > kMaxFuse3d) return fail(SRJ_EINVAL, "3D fusion depth must be in [0, 4]");
+    if (p->geo.ndim == 3 && fused > 0 && !fused3d_fits(p->geo, p->fmt))
+        return fail(SRJ_EINVAL, "z planes too large for the fused 3D kernel (1 GiB per plane at most)");
     if (seg_rows < 0 || seg_rows > (1 << 20)) return fail(SRJ_EINVAL, "segment rows must be in [0, 2^20]");
     p->fuse = fused;
     p->seg_rows = seg_rows;

@@ -29,16 +29,12 @@ template <> struct Tr<bf16_t> {
     static __device__ __forceinline__ float ld(bf16_t x) { return __uint_as_float((uint32_t)x.v << 16); }
     static __device__ __forceinline__ bf16_t st(float f)
     {
-        // round to nearest, ties to even; NaN stays a (quiet) NaN.  Written as a select so
-        // the conversion does not branch.
-        const uint32_t x = __float_as_uint(f);
-        const uint32_t rn = (x + 0x7fffu + ((x >> 16) & 1u)) >> 16;
-        const uint32_t qn = (x >> 16) | 0x40u;
+        // round to nearest, ties to even (gfx950 converts in one instruction, subnormals
+        // kept); NaN stays a NaN
         bf16_t r;
-        r.v = (uint16_t)(((x & 0x7fffffffu) > 0x7f800000u) ? qn : rn);
+        r.v = __builtin_bit_cast(uint16_t, (__bf16)f);
         return r;
     }
-    // binary64 -> binary32 (round to nearest) -> bfloat16 (round to nearest even)
     static __device__ __forceinline__ bf16_t from64(double x) { return st((float)x); }
 };
 

@@ -11,7 +11,8 @@ namespace srj {
 
 enum Fmt { FMT_F64 = 0, FMT_F32 = 1, FMT_BF16 = 2 };
 
-constexpr int kMaxFuse = 8;  // largest number of sweeps fused into one launch
+constexpr int kMaxFuse = 8;    // largest number of sweeps fused into one 2D launch
+constexpr int kMaxFuse3d = 4;  // largest number of sweeps fused into one 3D launch
 
 struct Geo {
     int ndim;
@@ -39,6 +40,15 @@ hipError_t launch_sweep_unfused(Fmt f, const void* in, void* out, const void* b,
 // segments of H output rows per wave.
 hipError_t launch_sweep_fused(Fmt f, const void* in, void* out, const void* b, const Geo& g,
                               const Coefs& co, int T, int H, hipStream_t s);
+// T <= kMaxFuse3d sweeps (coefficients co.c[0..T)) of a 3D grid in one launch: x-y tiles of
+// 64 x 32 with T-wide halos, streamed in z.  Needs fused3d_fits(g, f): a padded z plane
+// below 1 GiB (its stores are addressed within one plane).
+inline bool fused3d_fits(const Geo& g, Fmt f)
+{
+    return g.px * g.py * (int64_t)fmt_size(f) < ((int64_t)1 << 30) - 4096;
+}
+hipError_t launch_sweep_fused3d(Fmt f, const void* in, void* out, const void* b, const Geo& g,
+                                const Coefs& co, int T, hipStream_t s);
 // sum r^2 and max |r| of r = b64 - A u (binary64); zero_interior treats u's interior as 0.
 // partials must hold 2 * residual_blocks(g) doubles; result receives {sum, max}.
 int residual_blocks(const Geo& g);

@@ -1,0 +1,239 @@
+// Temporally blocked 3D SRJ sweep for gfx950 (CDNA4, wave64).
+//
+// T consecutive scheduled sweeps (Sec. 2; each step the 7-point form of Sec. 3.1's update
+// with d = 3, evaluated with the association and rounding of the unfused kernel, so the
+// result is bit-identical to T unfused sweeps) are applied in one launch.  A block of 8 waves
+// owns an x-y tile of 64 columns (one per lane) by 32 rows (4 per wave) and streams a run of
+// z planes through it.  At step k the block takes plane k (level 0) and computes level l for
+// plane k - l, l = 1..T, from level l-1 planes k-l-1, k-l and k-l+1: each lane keeps, per
+// level, the two older planes of its 4 points in registers; x neighbours cross lanes by DPP
+// shifts, y neighbours are the lane's own rows except across wave boundaries, where the
+// boundary rows of each level are exchanged through LDS (double-buffered by step parity, one
+// barrier per step).  One HBM read of u and b and one write of u serve T sweeps; tiles overlap
+// by T columns and rows on each side and z runs by T planes, the overlap being recomputed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cstdint>
+#include <cstdlib>
+
+#include "formats.h"
+#include "kernels.h"
+#include "tb_core.h"
+
+namespace srj {
+
+template <int T> struct Coefs3T {
+    double c[T];
+};
+
+constexpr int k3Waves = 8;                  // waves per block
+constexpr int k3Rows = 4;                   // rows per wave
+constexpr int k3TileY = k3Waves * k3Rows;   // tile rows
+
+template <class S, int T, int D>
+__global__ __launch_bounds__(512) void k_sweep3d_tb(const S* __restrict__ uin, S* __restrict__ uout,
+                                                    const S* __restrict__ bb, int64_t px, int64_t py, int nx,
+                                                    int ny, int nz, Coefs3T<T> co, int Tact, int ntx, int nty,
+                                                    int zs)
+{
+    using Cm = typename Tr<S>::C;
+    constexpr int SX = 64 - 2 * T;        // output columns per tile
+    constexpr int SY = k3TileY - 2 * T;   // output rows per tile
+    __shared__ Cm xch[2][T][k3Waves][2][64];
+
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int bid = (int)blockIdx.x;
+    const int tx = bid % ntx, ty = (bid / ntx) % nty, tz = bid / (ntx * nty);
+    const int64_t pl = px * py;
+
+    const int x = 1 + tx * SX - T + lane;
+    const int64_t xcl = x < 0 ? 0 : (x > nx + 1 ? nx + 1 : x);
+    const bool updx = x >= 1 && x <= nx;
+    const bool outx = updx && lane >= T && lane < 64 - T;
+    int yr[k3Rows];
+    bool updy[k3Rows], outy[k3Rows];
+    int64_t colp[k3Rows];
+#pragma unroll
+    for (int r = 0; r < k3Rows; ++r) {
+        const int trow = w * k3Rows + r;
+        yr[r] = 1 + ty * SY - T + trow;
+        updy[r] = yr[r] >= 1 && yr[r] <= ny;
+        outy[r] = updy[r] && trow >= T && trow < k3TileY - T;
+        const int64_t yc = yr[r] < 0 ? 0 : (yr[r] > ny + 1 ? ny + 1 : yr[r]);
+        colp[r] = yc * px + xcl;
+    }
+    const int z0 = 1 + tz * zs;
+    const int z1 = min(z0 + zs, nz + 1);
+    const int kb = z0 - T;
+    const int ke = z1 - 1 + T;
+
+    Cm cf[T];
+#pragma unroll
+    for (int l = 0; l < T; ++l) cf[l] = (Cm)co.c[l];
+
+    // stores go through a buffer resource over the output plane whose range check drops
+    // masked lanes (offset pushed below zero), rows (offset pushed past the record count) and
+    // planes outside the run (record count 0)
+    const int plbytes = (int)(pl * (int64_t)sizeof(S));
+    const int lanebase = outx ? x * (int)sizeof(S) : INT_MIN;
+
+    Cm w1[T][k3Rows], w2[T][k3Rows], bq[T][k3Rows];
+#pragma unroll
+    for (int l = 0; l < T; ++l)
+#pragma unroll
+        for (int r = 0; r < k3Rows; ++r) w1[l][r] = w2[l][r] = bq[l][r] = (Cm)0;
+
+    auto load_plane = [&](int k, Cm* vu, Cm* vb) {
+        const int64_t zp = (int64_t)max(0, min(k, nz + 1)) * pl;
+#pragma unroll
+        for (int r = 0; r < k3Rows; ++r) {
+            vu[r] = Tr<S>::ld(uin[zp + colp[r]]);
+            vb[r] = Tr<S>::ld(bb[zp + colp[r]]);
+        }
+    };
+
+    Cm U[D][k3Rows], B[D][k3Rows];
+#pragma unroll
+    for (int s = 0; s < D; ++s) load_plane(kb + s, U[s], B[s]);
+
+    const int wu = max(w - 1, 0), wd = min(w + 1, k3Waves - 1);
+    for (int k0 = kb; k0 <= ke; k0 += D) {
+#pragma unroll
+        for (int s = 0; s < D; ++s) {
+            const int k = k0 + s;
+            const int cur = k & 1, prev = cur ^ 1;
+            Cm in[k3Rows];
+#pragma unroll
+            for (int r = 0; r < k3Rows; ++r) in[r] = U[s][r];
+            xch[cur][0][w][0][lane] = in[0];
+            xch[cur][0][w][1][lane] = in[k3Rows - 1];
+#pragma unroll
+            for (int l = 1; l <= T; ++l) {
+                // level l on plane p = k - l; its y neighbours across wave boundaries are the
+                // neighbouring waves' rows of plane p at level l-1, published in step k-1
+                const Cm up = xch[prev][l - 1][wu][1][lane];
+                const Cm dn = xch[prev][l - 1][wd][0][lane];
+                const int p = k - l;
+                const bool pok = (p >= 1) & (p <= nz) & (l <= Tact);
+                Cm out[k3Rows];
+#pragma unroll
+                for (int r = 0; r < k3Rows; ++r) {
+                    const Cm m = w1[l - 1][r];
+                    const Cm W = dpp_from_left(m);
+                    const Cm E = dpp_from_right(m);
+                    const Cm Sn = (r == 0) ? up : w1[l - 1][r - 1];
+                    const Cm Nn = (r == k3Rows - 1) ? dn : w1[l - 1][r + 1];
+                    const Cm sm = ((W + E) + (Sn + Nn)) + (w2[l - 1][r] + in[r]);
+                    const Cm t = (sm + bq[l - 1][r]) - (Cm)6 * m;
+                    Cm v = Tr<S>::ld(Tr<S>::st(m + cf[l - 1] * t));
+                    asm("" : "+v"(v));
+                    out[r] = (pok && updx && updy[r]) ? v : m;
+                }
+#pragma unroll
+                for (int r = 0; r < k3Rows; ++r) {
+                    w2[l - 1][r] = w1[l - 1][r];
+                    w1[l - 1][r] = in[r];
+                    in[r] = out[r];
+                }
+                if (l < T) {
+                    xch[cur][l][w][0][lane] = in[0];
+                    xch[cur][l][w][1][lane] = in[k3Rows - 1];
+                }
+            }
+            // level T of plane k - T
+            const int pT = k - T;
+            const bool zout = (pT >= z0) & (pT < z1);
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                (void*)(uout + (int64_t)min(max(pT, 0), nz + 1) * pl), (short)0, zout ? plbytes : 0, 0x00020000);
+#pragma unroll
+            for (int r = 0; r < k3Rows; ++r) {
+                const int rowpart = outy[r] ? (int)((int64_t)yr[r] * px * (int64_t)sizeof(S)) : kTbMasked;
+                tb_store(Tr<S>::st(in[r]), rs, rowpart + lanebase);
+            }
+#pragma unroll
+            for (int l = T - 1; l > 0; --l)
+#pragma unroll
+                for (int r = 0; r < k3Rows; ++r) bq[l][r] = bq[l - 1][r];
+#pragma unroll
+            for (int r = 0; r < k3Rows; ++r) bq[0][r] = B[s][r];
+            __syncthreads();
+            load_plane(k + D, U[s], B[s]);
+        }
+    }
+}
+
+static int env_int3(const char* name, int dflt)
+{
+    const char* v = getenv(name);
+    return v ? atoi(v) : dflt;
+}
+
+template <class S, int T, int D>
+static int tb3_resident_blocks()
+{
+    static const int blocks = [] {
+        int nb = 0, dev = 0, ncu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep3d_tb<S, T, D>, 512, 0) != hipSuccess) nb = 1;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            ncu = 1;
+        return std::max(1, nb) * std::max(1, ncu);
+    }();
+    return blocks;
+}
+
+template <class S, int T, int D>
+static void tb3d(const S* in, S* out, const S* b, const Geo& g, const Coefs& co, int Tact, hipStream_t s)
+{
+    constexpr int SX = 64 - 2 * T, SY = k3TileY - 2 * T;
+    Coefs3T<T> ct;
+    for (int l = 0; l < T; ++l) ct.c[l] = l < Tact ? co.c[l] : 0.0;
+    const int ntx = (int)((g.nx + SX - 1) / SX);
+    const int nty = (int)((g.ny + SY - 1) / SY);
+    // z runs: as many as fill the resident block slots once (at least one), balanced
+    static const int zs_knob = env_int3("SRJ_3DTB_ZRUN", 0);  // tuning knob, 0 = automatic
+    int ntz = std::max(1, tb3_resident_blocks<S, T, D>() / (ntx * nty));
+    int zs = zs_knob > 0 ? zs_knob : (int)((g.nz + ntz - 1) / ntz);
+    zs = std::max(1, std::min(zs, (int)g.nz));
+    ntz = (int)((g.nz + zs - 1) / zs);
+    zs = (int)((g.nz + ntz - 1) / ntz);
+    const int nblk = ntx * nty * ntz;
+    hipLaunchKernelGGL((k_sweep3d_tb<S, T, D>), dim3(nblk), dim3(512), 0, s, in, out, b, g.px, g.py, (int)g.nx,
+                       (int)g.ny, (int)g.nz, ct, Tact, ntx, nty, zs);
+}
+
+template <class S, int D>
+static void tb3d_TD(const S* in, S* out, const S* b, const Geo& g, const Coefs& co, int T, hipStream_t s)
+{
+    switch (T) {
+    case 1: tb3d<S, 1, D>(in, out, b, g, co, 1, s); break;
+    case 2: tb3d<S, 2, D>(in, out, b, g, co, 2, s); break;
+    case 3: tb3d<S, 3, D>(in, out, b, g, co, 3, s); break;
+    default: tb3d<S, 4, D>(in, out, b, g, co, 4, s); break;
+    }
+}
+
+// Planes in flight per wave: 2 (the default) or 1.
+template <class S>
+static void tb3d_T(const S* in, S* out, const S* b, const Geo& g, const Coefs& co, int T, hipStream_t s)
+{
+    static const int knob = env_int3("SRJ_3DTB_PREFETCH", 0);  // tuning knob, 0 = default (2)
+    const int pf = knob > 0 ? knob : 2;
+    if (pf >= 2)
+        tb3d_TD<S, 2>(in, out, b, g, co, T, s);
+    else
+        tb3d_TD<S, 1>(in, out, b, g, co, T, s);
+}
+
+hipError_t launch_sweep_fused3d(Fmt f, const void* in, void* out, const void* b, const Geo& g,
+                                const Coefs& co, int T, hipStream_t s)
+{
+    if (g.ndim != 3 || T < 1 || T > kMaxFuse3d) return hipErrorInvalidValue;
+    SRJ_DISPATCH(f, tb3d_T<S>((const S*)in, (S*)out, (const S*)b, g, co, T, s));
+    return hipGetLastError();
+}
+
+}  // namespace srj

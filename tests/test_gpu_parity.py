@@ -127,6 +127,23 @@ def test_fused_segment_heights_bitwise(T, H):
     assert np.array_equal(host(ug), ref)
 
 
+@pytest.mark.parametrize("T", [1, 2, 3, 4])
+@pytest.mark.parametrize("n", [(70, 45, 33), (5, 7, 3), (130, 40, 9), (1, 1, 1), (64, 1, 20), (57, 37, 70)])
+def test_fused3d_sweeps_bitwise(T, n):
+    """3D x-y tiles streamed in z, T sweeps per launch: bit-identical to the oracle's sweeps
+    (tiles and z runs ragged, cycle ends crossed, last launch shorter)."""
+    h = 1.0 / (max(n) + 1)
+    u, f = rand_case(n, 5)
+    w, q, seq = shared_schedule()
+    nsweeps = 2 * len(seq) + 3
+    p = explicit_plan(n, h, w, q, seq, fuse=T)
+    ug = dev(u)
+    srj.srj_sweeps(p, ug, dev(f), 1, nsweeps)
+    c = sweeps.coefficients(np.array(w)[seq], 3)
+    ref = sweeps.run(u, sweeps.rhs(f, h), c, nsweeps, k0=1)
+    assert np.array_equal(host(ug), ref)
+
+
 def test_fused_equals_unfused_on_gpu():
     n = (517, 389)
     h = 1.0 / 518
