@@ -211,8 +211,14 @@ def main():
     t0 = time.perf_counter()
     plan = srj.srj_plan(wl["n"], wl["h"], P=args.levels)
     t_plan = time.perf_counter() - t0
-    if args.fuse is not None:
-        srj.srj_plan_set_fusion(plan, args.fuse)
+    if args.fuse is not None or args.kernel_only:
+        # counter runs measure the default launch shape only
+        if args.fuse is not None:
+            srj.srj_plan_set_fusion(plan, args.fuse)
+        tuned = {"fused_sweeps": args.fuse if args.fuse is not None else 8, "seg_rows": 0, "tuned": False}
+    else:
+        t0 = time.perf_counter()
+        tuned = dict(srj.srj_plan_tune(plan), tuned=True, seconds=round(time.perf_counter() - t0, 3))
     desc = srj.srj_plan_describe(plan)
     M = int(desc["M"])
     pts = n * n
@@ -272,7 +278,9 @@ def main():
     achieved = bytes_launch / avg_launch / 1e9
     kname = f"k_sweep2d_tb<double,{fuse},2,3>" if fuse > 0 else "k_sweep2d<double>"
     wname = f"blobs2d_{n}x{n}_f64"
-    traffic = measured_traffic(kname, wname)
+    # counters were taken on the default launch shape (8 sweeps, segment height from the
+    # occupancy); another tuned shape has no committed traffic
+    traffic = measured_traffic(kname, wname) if (fuse == 8 and int(tuned["seg_rows"]) == 0) else None
 
     # unfused reference sweep on the same grid, for the per-sweep HBM figure
     srj.srj_plan_set_fusion(plan, 0)
@@ -298,7 +306,9 @@ def main():
         "data": "synthetic (seeded Gaussian-blob source, U(-1,1) Dirichlet ring)",
         "config": {"workload": f"2D Poisson {n}x{n} interior, 5-point, Dirichlet, SRJ P={args.levels} "
                                f"(M={M}), FP64, tol {args.tol:g}",
-                   "n": n, "levels": args.levels, "M": M, "tol": args.tol, "fused_sweeps": fuse},
+                   "n": n, "levels": args.levels, "M": M, "tol": args.tol, "fused_sweeps": fuse,
+                   "seg_rows": int(tuned["seg_rows"])},
+        "launch_tuning": tuned,
         "time_to_tol_s": round(dt, 4),
         "sweeps": sweeps_done,
         "cycles": int(info["cycles"]),
@@ -345,6 +355,7 @@ def bench_3d(torch, srj, workloads, n=512, levels=8, tol=1e-10):
     ref = None
     for fmt in ("f64", "f32", "bf16"):
         plan = srj.srj_plan((n, n, n), 1.0 / (n + 1), P=levels, dtype=fmt)
+        tuned = srj.srj_plan_tune(plan)
         u = u0.clone()
         sec, launches = srj.srj_sweeps(plan, u, f, 0, 32)
         u = u0.clone()
@@ -363,6 +374,7 @@ def bench_3d(torch, srj, workloads, n=512, levels=8, tol=1e-10):
         r = {"time_to_tol_s": round(dt, 4), "sweeps": int(info["sweeps"]), "cycles_or_outer": int(info["cycles"]),
              "relres": info["relres"], "status": info["status"], "GLUP_s": round(pts * info["sweeps"] / dt / 1e9, 2),
              "fused_sweeps": int(srj.srj_plan_describe(plan)["fused_sweeps"]),
+             "launch_tuning": tuned,
              "launch_us": round(launch_s * 1e6, 1), "per_sweep_us": round(per_sweep * 1e6, 1),
              # algorithmic bytes of one launch (u, b read once, u written once) over its time
              "launch_algorithmic_GBs": round(bpp * pts / launch_s / 1e9, 1),
@@ -393,6 +405,7 @@ def bench_batch(torch, srj, workloads, count=1024, tol=1e-10):
         fs.append(torch.from_numpy(wl["f"]).to("cuda:0"))
     t0 = time.perf_counter()
     b = srj.srj_batch_plan(probs, dtype="f32")
+    tuned = srj.srj_batch_tune(b)
     t_plan = time.perf_counter() - t0
     us = [u.clone() for u in u0s]
     torch.cuda.synchronize()
@@ -403,7 +416,7 @@ def bench_batch(torch, srj, workloads, count=1024, tol=1e-10):
     lup = sum(int(nn) * int(nn) * i["sweeps"] for nn, i in zip(N, infos))
     return {"workload": f"{count} 2D Poisson problems, N log-uniform [32, 1024], P in 3..8, f ~ N(0,1), "
                         f"FP32 sweeps in FP64 refinement, tol {tol:g}",
-            "wall_s": round(dt, 3), "plan_s": round(t_plan, 2), "converged": sum(i["status"] == "ok" for i in infos),
+            "wall_s": round(dt, 3), "plan_s": round(t_plan, 2), "launch_tuning": tuned, "converged": sum(i["status"] == "ok" for i in infos),
             "total_points": int(sum(int(nn) ** 2 for nn in N)), "total_LUP": int(lup),
             "GLUP_s": round(lup / dt / 1e9, 2), "solves_per_s": round(count / dt, 2),
             "p50_problem_s": round(float(np.percentile(secs, 50)), 4),
@@ -420,6 +433,7 @@ def bench_adjoint(torch, srj, workloads, n=2048, levels=9, tol=1e-10):
     g = torch.from_numpy(wl["g"]).to("cuda:0").requires_grad_(True)
     ut = torch.from_numpy(wl["u_target"]).to("cuda:0")
     plan = srj.srj_plan((n, n), wl["h"], P=levels)
+    tuned = srj.srj_plan_tune(plan)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     u = srj_solve_diff(f, g, plan, tol=tol, tol_backward=1e-9)
@@ -432,7 +446,7 @@ def bench_adjoint(torch, srj, workloads, n=2048, levels=9, tol=1e-10):
     return {"workload": f"2D {n}^2, f blobs and U(-1,1) ring as parameters, L = 1/2 ||u - u_target||^2, "
                         f"SRJ P={levels} forward to {tol:g}, adjoint to 1e-9 (binary64 floor of a smooth "
                         f"right-hand side is about 2e-10 here)",
-            "forward_s": round(t1 - t0, 4), "backward_s": round(t2 - t1, 4),
+            "forward_s": round(t1 - t0, 4), "backward_s": round(t2 - t1, 4), "launch_tuning": tuned,
             "loss": float(loss.detach())}
 
 

@@ -168,11 +168,12 @@ srj_status srj_adjoint(srj_plan_t plan, const double* grad_u, double tol, int64_
 /* Batched solves: many independent 2D grids (sizes, spacings and schedules may all
  * differ; one storage format per batch), each solved by the same FP64 refinement as
  * srj_solve_ir with its own schedule (Sec. 2-4 per problem), all advanced together on
- * the device: one kernel applies the scheduled sweeps to every problem that is sweeping,
- * another forms u + d and the binary64 residual of every problem that finished an inner
- * solve and decides it.  The iterations are replayed from a captured HIP graph on an
+ * the device.  One kernel launch per iteration goes over the tiles of every running
+ * problem: tiles of a sweeping problem get up to 8 scheduled sweeps, tiles of a problem
+ * that finished an inner solve get u + d and its binary64 residual, and the last tile of a
+ * problem decides it.  The iterations are replayed from a captured HIP graph on an
  * internal stream (the plan's stream is synchronised first).  Problems never wait on one
- * another; finished problems drop out. */
+ * another; finished problems drop out of the work list. */
 typedef struct srj_batch_s* srj_batch_t;
 /* grids[count], schedules[count] as for srj_plan (ndim must be 2, one dtype for all).  The
  * batch owns all device buffers (about 3 FP64 + 3 sweep-format fields per problem). */
@@ -186,6 +187,29 @@ srj_status srj_batch_solve(srj_batch_t batch, double* const* u, const double* co
                            int32_t inner_cycles, int32_t max_outer, srj_solve_info* infos,
                            double* seconds);
 void srj_batch_destroy(srj_batch_t batch);
+
+/* Autotuning of the launch shape (no paper counterpart: the paper's sweeps are scalar
+ * loops).  The tuner times candidate configurations on the device, on the plan's or
+ * batch's own scratch fields (no user data is read or written), keeps the fastest (the
+ * configuration in place unless another is at least 3% faster), and returns what it
+ * measured.  Results of later solves are bit-identical whatever is
+ * chosen; only their speed changes.  Synchronises the plan's stream; takes milliseconds
+ * to about a second for the largest grids.
+ *   srj_plan_tune: 2D plans time fusion depths {8, 6, 4} x segment heights {automatic,
+ *     24, 32, 48, 64, 96, 128}; 3D plans fusion depths {4, 3, 2, 1, 0}.  Sets the plan's
+ *     fusion (as srj_plan_set_fusion would).
+ *   srj_batch_tune: times the batch's sweep launch with every problem sweeping, for
+ *     largest tile heights {32, 64, 128, 256}, and keeps the fastest as the height the
+ *     batch starts from (it still shortens tiles as problems finish). */
+typedef struct {
+    int32_t fused_sweeps;        /* chosen sweeps per launch (batch: 8) */
+    int32_t seg_rows;            /* chosen segment / largest tile height (0 = automatic) */
+    int32_t candidates;          /* configurations timed */
+    double us_per_sweep;         /* device time per sweep of the whole grid / batch, chosen */
+    double us_per_sweep_before;  /* the same for the configuration in place before tuning */
+} srj_tune_info;
+srj_status srj_plan_tune(srj_plan_t plan, srj_tune_info* info);
+srj_status srj_batch_tune(srj_batch_t batch, srj_tune_info* info);
 
 /* Host-only schedule computations (no device needed). */
 /* Optimal P-level weights/fractions on [kappa_min, kappa_max] (Sec. 3) and counts

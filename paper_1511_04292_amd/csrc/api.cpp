@@ -473,6 +473,80 @@ srj_status srj_sweeps(srj_plan_t p, double* u, const double* f, int64_t k0, int6
     return SRJ_OK;
 }
 
+srj_status srj_plan_tune(srj_plan_t p, srj_tune_info* info)
+{
+    if (!p) return fail(SRJ_EINVAL, "null plan");
+    struct Cand {
+        int T, H;
+    };
+    std::vector<Cand> cands;
+    cands.push_back({p->fuse, p->seg_rows});  // the configuration in place, timed first
+    if (p->geo.ndim == 2) {
+        for (int T : {8, 6, 4})
+            for (int H : {0, 24, 32, 48, 64, 96, 128}) cands.push_back({T, H});
+    } else {
+        if (fused3d_fits(p->geo, p->fmt))
+            for (int T : {4, 3, 2, 1}) cands.push_back({T, 0});
+        cands.push_back({0, 0});
+    }
+    HIPCHK(launch_zero(p->fmt, p->A.origin, p->geo, p->stream));
+    HIPCHK(launch_zero(p->fmt, p->B.origin, p->geo, p->stream));
+    // device time per sweep of a configuration: 24 sweeps (whole launches at every depth),
+    // repeated until the timed run lasts about a millisecond
+    auto time_one = [&](const Cand& c, double* us) -> srj_status {
+        p->fuse = c.T;
+        p->seg_rows = c.H;
+        DField *cur = &p->A, *nxt = &p->B;
+        srj_status st = run_sweeps(p, &cur, &nxt, p->blo.origin, 0, 24);  // warm-up
+        if (st != SRJ_OK) return st;
+        int64_t n = 24;
+        for (int rep = 0; rep < 4; ++rep) {
+            HIPCHK(hipEventRecord(p->ev0, p->stream));
+            st = run_sweeps(p, &cur, &nxt, p->blo.origin, 0, n);
+            if (st != SRJ_OK) return st;
+            HIPCHK(hipEventRecord(p->ev1, p->stream));
+            HIPCHK(hipEventSynchronize(p->ev1));
+            float ms = 0;
+            HIPCHK(hipEventElapsedTime(&ms, p->ev0, p->ev1));
+            *us = ms * 1e3 / (double)n;
+            if (ms >= 1.0f || n >= 24 * 64) break;
+            n = std::min<int64_t>(24 * 64, n * (int64_t)std::ceil(1.2 / std::max(ms, 0.01f)));
+            n = (n + 23) / 24 * 24;
+        }
+        return SRJ_OK;
+    };
+    double before = 0, best = 0;
+    Cand pick = cands[0];
+    for (size_t i = 0; i < cands.size(); ++i) {
+        double us = 0;
+        srj_status st = time_one(cands[i], &us);
+        if (st != SRJ_OK) {
+            p->fuse = cands[0].T;
+            p->seg_rows = cands[0].H;
+            return st;
+        }
+        if (i == 0) before = us;
+        // the configuration in place stays unless another one is clearly faster (3%), so
+        // timing noise does not flip between near-equal shapes
+        const double score = (i == 0) ? us : us * 1.03;
+        if (i == 0 || score < best) {
+            best = score;
+            pick = cands[i];
+        }
+    }
+    best = (pick.T == cands[0].T && pick.H == cands[0].H) ? before : best / 1.03;
+    p->fuse = pick.T;
+    p->seg_rows = pick.H;
+    if (info) {
+        info->fused_sweeps = pick.T;
+        info->seg_rows = pick.H;
+        info->candidates = (int32_t)cands.size();
+        info->us_per_sweep = best;
+        info->us_per_sweep_before = before;
+    }
+    return SRJ_OK;
+}
+
 srj_status srj_solve(srj_plan_t p, double* u, const double* f, double tol, int64_t max_sweeps,
                      srj_solve_info* info)
 {

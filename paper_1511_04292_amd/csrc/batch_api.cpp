@@ -161,6 +161,7 @@ struct srj_batch_s {
     int* remaining_h = nullptr;
     int* nitems_h = nullptr;  // pinned staging of the work-list length
     int items_h_len = 0;
+    int hmax = 128;           // largest tile height (srj_batch_tune may change it)
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
 };
@@ -204,6 +205,7 @@ srj_status srj_batch_plan(int32_t count, const srj_grid* grids, const srj_schedu
     if (!b) return report(SRJ_ENOMEM, "host allocation failed");
     b->count = count;
     b->fmt = (Fmt)dt;
+    b->hmax = env_int("SRJ_BATCH_H", 128, kHmin, 1 << 20);
     b->user_stream = (hipStream_t)stream;
     b->grids.assign(grids, grids + count);
     // schedules, in parallel host threads
@@ -319,6 +321,103 @@ void srj_batch_destroy(srj_batch_t b)
     destroy_batch(b);
 }
 
+srj_status srj_batch_tune(srj_batch_t b, srj_tune_info* info)
+{
+    if (!b) return report(SRJ_EINVAL, "null batch");
+    hipStream_t s = b->stream;
+    if (b->user_stream) BCHK(hipStreamSynchronize(b->user_stream));
+    const int T = batch_fuse();
+    const int SW = 128 - 2 * T;
+    // every problem sweeping from zero corrections, never reaching the end of an inner solve
+    std::vector<BState> st(b->count);
+    double pts = 0;
+    for (int j = 0; j < b->count; ++j) {
+        std::memset(&st[j], 0, sizeof(BState));
+        st[j].phase = BP_SWEEP;
+        BProb& P = b->probs[j];
+        P.inner_total = 1 << 30;
+        BCHK(launch_zero(b->fmt, P.d[0], b->geos[j], s));
+        BCHK(launch_zero(b->fmt, P.d[1], b->geos[j], s));
+        BCHK(launch_zero(b->fmt, P.rlo, b->geos[j], s));
+        pts += (double)b->geos[j].nx * (double)b->geos[j].ny;
+    }
+    BCHK(hipMemcpyAsync(b->st_d, st.data(), sizeof(BState) * b->count, hipMemcpyHostToDevice, s));
+    BRun run;
+    std::memset(&run, 0, sizeof(run));
+    run.tol = 0;
+    run.max_outer = 0;
+    run.items = b->items_d;
+    run.nitems = b->nitems_d;
+    run.coef = b->coef_d;
+    run.partials = b->partials_d;
+    run.remaining = b->remaining_d;
+    const int gs = std::max(1, std::min((b->nitems + 3) / 4, 2048));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    BCHK(hipEventCreate(&e0));
+    BCHK(hipEventCreate(&e1));
+    const int cands[] = {b->hmax, 32, 64, 128, 256};
+    double before = 0, best = 0;
+    int pick = b->hmax, ncand = 0;
+    srj_status result = SRJ_OK;
+    for (int c = 0; c < 5 && result == SRJ_OK; ++c) {
+        const int H = cands[c];
+        if (c > 0 && H == cands[0]) continue;
+        std::vector<BItem> items;
+        for (int j = 0; j < b->count; ++j) {
+            BProb& P = b->probs[j];
+            P.H = std::max(kHmin, std::min(H, tb_max_rows(P.px, (int)fmt_size(b->fmt))));
+            P.ntiles = tiles_of(b->geos[j], SW, P.H);
+            for (int t = 0; t < P.ntiles; ++t) items.push_back(BItem{j, t});
+        }
+        *b->nitems_h = (int)items.size();
+        if (hipMemcpyAsync(b->probs_d, b->probs.data(), sizeof(BProb) * b->count, hipMemcpyHostToDevice, s) !=
+                hipSuccess ||
+            hipMemcpyAsync(b->items_d, items.data(), sizeof(BItem) * items.size(), hipMemcpyHostToDevice, s) !=
+                hipSuccess ||
+            hipMemcpyAsync(b->nitems_d, b->nitems_h, sizeof(int), hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            result = report(SRJ_EHIP, "batch tuning upload failed");
+            break;
+        }
+        // 2 warm-up launches, then 6 timed (48 sweeps of every problem)
+        bool ok = true;
+        for (int it = 0; it < 8 && ok; ++it) {
+            if (it == 2) ok = hipEventRecord(e0, s) == hipSuccess;
+            ok = ok && launch_batch_step(b->fmt, b->probs_d, b->st_d, run, gs, s) == hipSuccess;
+        }
+        float ms = 0;
+        ok = ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+             hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+        if (!ok) {
+            result = report(SRJ_EHIP, "batch tuning launch failed");
+            break;
+        }
+        const double us = ms * 1e3 / (6.0 * T);
+        ncand += 1;
+        // keep the height in place unless another one is clearly faster (3%)
+        const double score = (c == 0) ? us : us * 1.03;
+        if (c == 0) before = us;
+        if (c == 0 || score < best) {
+            best = score;
+            pick = H;
+        }
+    }
+    if (pick != cands[0]) best /= 1.03;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (result != SRJ_OK) return result;
+    b->hmax = pick;
+    if (info) {
+        info->fused_sweeps = T;
+        info->seg_rows = pick;
+        info->candidates = ncand;
+        info->us_per_sweep = best;
+        info->us_per_sweep_before = before;
+    }
+    (void)pts;
+    return SRJ_OK;
+}
+
 srj_status srj_batch_solve(srj_batch_t b, double* const* u, const double* const* f, double tol,
                            int32_t inner_cycles, int32_t max_outer, srj_solve_info* infos, double* seconds)
 {
@@ -370,7 +469,7 @@ srj_status srj_batch_solve(srj_batch_t b, double* const* u, const double* const*
     // work list: the tiles of every running problem, at the height chosen for them
     const int T = batch_fuse();
     const int SW = 128 - 2 * T;
-    const int hmax = env_int("SRJ_BATCH_H", 128, kHmin, 1 << 20);
+    const int hmax = b->hmax;
     const int tiles_target = env_int("SRJ_BATCH_TILES", 4096, 1, 1 << 30);
     std::vector<BItem> items;
     items.reserve(b->nitems);

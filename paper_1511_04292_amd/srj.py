@@ -51,12 +51,18 @@ class _Info(ctypes.Structure):
                 ("seconds", ctypes.c_double), ("status", ctypes.c_int32)]
 
 
+class _Tune(ctypes.Structure):
+    _fields_ = [("fused_sweeps", ctypes.c_int32), ("seg_rows", ctypes.c_int32), ("candidates", ctypes.c_int32),
+                ("us_per_sweep", ctypes.c_double), ("us_per_sweep_before", ctypes.c_double)]
+
+
 _lib = None
 
 EXPORTS = ["srj_plan", "srj_plan_destroy", "srj_plan_describe", "srj_plan_sequence",
            "srj_plan_set_fusion", "srj_solve", "srj_sweeps", "srj_residual", "srj_solve_ir",
            "srj_schedule_optimal", "srj_schedule_order", "srj_status_string", "srj_last_error",
-           "srj_adjoint", "srj_batch_plan", "srj_batch_solve", "srj_batch_destroy"]
+           "srj_adjoint", "srj_batch_plan", "srj_batch_solve", "srj_batch_destroy", "srj_plan_tune",
+           "srj_batch_tune"]
 
 
 def lib():
@@ -83,6 +89,8 @@ def lib():
                                   ctypes.POINTER(dbl)]
     L.srj_batch_destroy.argtypes = [vp]
     L.srj_batch_destroy.restype = None
+    L.srj_plan_tune.argtypes = [vp, ctypes.POINTER(_Tune)]
+    L.srj_batch_tune.argtypes = [vp, ctypes.POINTER(_Tune)]
     L.srj_schedule_optimal.argtypes = [i32, dbl, dbl, ctypes.POINTER(dbl), ctypes.POINTER(dbl),
                                        ctypes.POINTER(i64), ctypes.POINTER(dbl)]
     L.srj_schedule_order.argtypes = [i32, ctypes.POINTER(dbl), ctypes.POINTER(i64), dbl, dbl, i32,
@@ -93,7 +101,7 @@ def lib():
     L.srj_last_error.restype = ctypes.c_char_p
     for name in ["srj_plan", "srj_plan_describe", "srj_plan_sequence", "srj_plan_set_fusion", "srj_solve",
                  "srj_sweeps", "srj_residual", "srj_solve_ir", "srj_schedule_optimal", "srj_schedule_order",
-                 "srj_adjoint", "srj_batch_plan", "srj_batch_solve", "srj_batch_destroy"]:
+                 "srj_adjoint", "srj_batch_plan", "srj_batch_solve", "srj_plan_tune", "srj_batch_tune"]:
         getattr(L, name).restype = i32
     _lib = L
     return L
@@ -339,3 +347,22 @@ def srj_schedule_order(omega, q, kappa_min, kappa_max=2.0, ordering=0):
                                     float(kappa_max), int(ordering),
                                     seq.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
     return seq
+
+
+def _tune_dict(t):
+    return dict(fused_sweeps=t.fused_sweeps, seg_rows=t.seg_rows, candidates=t.candidates,
+                us_per_sweep=t.us_per_sweep, us_per_sweep_before=t.us_per_sweep_before)
+
+
+def srj_plan_tune(plan):
+    """Time candidate launch shapes on the plan's scratch fields and keep the fastest."""
+    t = _Tune()
+    _check(lib().srj_plan_tune(plan.handle, ctypes.byref(t)))
+    return _tune_dict(t)
+
+
+def srj_batch_tune(batch):
+    """Time candidate largest tile heights of the batch's sweep launch and keep the fastest."""
+    t = _Tune()
+    _check(lib().srj_batch_tune(batch.handle, ctypes.byref(t)))
+    return _tune_dict(t)
