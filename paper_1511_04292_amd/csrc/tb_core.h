@@ -81,20 +81,24 @@ struct TbRegs {
 
 // One step of the pipeline: level-0 row r arrives from slot s; levels 1..lmax are computed
 // (lmax < T only while the pipeline fills: level l is first needed at step 2l of the tile);
-// the value of level T for row r - T is stored if that row is an output row of the tile.
+// the value of level T for row r - dir*T is stored if that row is an output row of the tile.
+// dir = +1 streams rows downwards (level l works on row r - l), -1 upwards (row r + l); the
+// window then holds the rows in the other order and (S + N) is formed as (N + S), which is
+// the same IEEE sum.
 // CLEAN steps know that every computed point is an interior point of the grid and that
 // all T levels apply, and so skip the per-level selects.
 template <class S, int T, int C, int D, bool CLEAN>
 __device__ __forceinline__ void tb_step(TbRegs<typename Tr<S>::C, T, C, D>& R, int s, int lmax, int r,
                                         const typename Tr<S>::C (&cf)[T], const bool (&upd)[C], int ny,
                                         int Tact, int y0, int y1, int rowbytes, const int (&lanebase)[C],
-                                        __amdgpu_buffer_rsrc_t rs)
+                                        __amdgpu_buffer_rsrc_t rs, int dir)
 {
     using Cm = typename Tr<S>::C;
     Cm in[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) in[c] = R.U[s][c];
     const int rv = CLEAN ? 0 : vcopy(r);
+    const int dv = CLEAN ? 0 : vcopy(dir);
 #pragma unroll
     for (int l = 1; l <= T; ++l) {
         if (l > lmax + 1) break;
@@ -104,7 +108,7 @@ __device__ __forceinline__ void tb_step(TbRegs<typename Tr<S>::C, T, C, D>& R, i
             const Cm en = dpp_from_right(R.p1[l - 1][0]);
             bool rowok = true;
             if (!CLEAN) {
-                const int jv = rv - l;
+                const int jv = rv - dv * l;
                 rowok = (jv >= 1) & (jv <= ny) & (l <= Tact);
             }
 #pragma unroll
@@ -133,7 +137,7 @@ __device__ __forceinline__ void tb_step(TbRegs<typename Tr<S>::C, T, C, D>& R, i
         }
     }
     if (lmax == T) {
-        const int j = r - T;
+        const int j = r - dir * T;
         const int rowpart = (j >= y0 && j < y1) ? (j - y0) * rowbytes : kTbMasked;
 #pragma unroll
         for (int c = 0; c < C; ++c) tb_store(Tr<S>::st(in[c]), rs, rowpart + lanebase[c]);
@@ -174,6 +178,13 @@ __device__ __forceinline__ void tb_tile_body(const S* __restrict__ uin, S* __res
     const int y1 = min(y0 + H, ny + 1);
     const int rb = y0 - T;
     const int rl = y1 - 1 + T;
+    // odd segments stream upwards, so that the halo rows two neighbouring segments share
+    // are read by both at the same time (both at their start or both at their end) and the
+    // second read can come from L2; (S + N) equals (N + S) exactly, so the direction does
+    // not change any result
+    const int dir = (sg & 1) ? -1 : 1;
+    const int r_first = dir > 0 ? rb : rl;
+    const int nsteps = rl - rb + 1;
 
     bool upd[C];
     int64_t xc[C];
@@ -209,26 +220,28 @@ __device__ __forceinline__ void tb_tile_body(const S* __restrict__ uin, S* __res
     };
 
 #pragma unroll
-    for (int s = 0; s < D; ++s) load_row(rb + s, R.U[s], R.B[s]);
+    for (int s = 0; s < D; ++s) load_row(r_first + dir * s, R.U[s], R.B[s]);
 
     // pipeline fill, unrolled: step i needs levels 1 .. i/2
 #pragma unroll
     for (int i = 0; i < F; ++i) {
         const int s = i % D;
         const int lmax = min(T, i / 2);
-        tb_step<S, T, C, D, CLEAN>(R, s, lmax, rb + i, cf, upd, ny, Tact, y0, y1, rowbytes, lanebase, rs);
-        load_row(rb + i + D, R.U[s], R.B[s]);
+        tb_step<S, T, C, D, CLEAN>(R, s, lmax, r_first + dir * i, cf, upd, ny, Tact, y0, y1, rowbytes, lanebase, rs,
+                                   dir);
+        load_row(r_first + dir * (i + D), R.U[s], R.B[s]);
         // keep each row load in its step: bunched at the end of the loop body they would be
         // waited for at the top of the next iteration
         __builtin_amdgcn_sched_barrier(0);
     }
     // steady state: all levels, D steps per iteration (the last may run past rl: its rows
     // are loaded clamped and never stored)
-    for (int r0 = rb + F; r0 <= rl; r0 += D) {
+    for (int i0 = F; i0 < nsteps; i0 += D) {
 #pragma unroll
         for (int s = 0; s < D; ++s) {
-            tb_step<S, T, C, D, CLEAN>(R, s, T, r0 + s, cf, upd, ny, Tact, y0, y1, rowbytes, lanebase, rs);
-            load_row(r0 + s + D, R.U[s], R.B[s]);
+            const int r = r_first + dir * (i0 + s);
+            tb_step<S, T, C, D, CLEAN>(R, s, T, r, cf, upd, ny, Tact, y0, y1, rowbytes, lanebase, rs, dir);
+            load_row(r + dir * D, R.U[s], R.B[s]);
             __builtin_amdgcn_sched_barrier(0);
         }
     }

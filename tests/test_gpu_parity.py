@@ -274,6 +274,48 @@ def test_ir_matches_oracle(fmt):
     assert np.array_equal(host(ug), ref["u"])
 
 
+@pytest.mark.parametrize("fmt", ["f32", "bf16"])
+@pytest.mark.parametrize("fuse", [0, 2, 4])
+def test_lowprec_sweeps_3d_bitwise(fmt, fuse):
+    n = (70, 37, 29)
+    h = 1.0 / 71
+    u, f = rand_case(n, 18)
+    w, q, seq = big_first()
+    nsw = 9
+    p = explicit_plan(n, h, w, q, seq, dtype=fmt, fuse=fuse)
+    ug = dev(u)
+    srj.srj_sweeps(p, ug, dev(f), 0, nsw)
+    c32 = sweeps.lo_coefficients(np.array(w)[seq], 3)
+    x = sweeps.lo_cast(u, fmt)
+    b = sweeps.lo_cast(sweeps.rhs(f, h), fmt)
+    for s in range(nsw):
+        x = sweeps.sweep_lo(x, b, c32[s % len(seq)], fmt)
+    ref = sweeps.lo_widen(x, fmt)
+    got = host(ug)
+    inner = (slice(1, -1), slice(1, -1), slice(1, -1))
+    assert np.array_equal(got[inner], ref[inner])
+
+
+@pytest.mark.parametrize("fmt", ["f32", "bf16"])
+def test_ir_3d_matches_oracle(fmt):
+    n = (21, 18, 15)
+    h = 1.0 / 22
+    rng = np.random.default_rng(31)
+    full = tuple(x + 2 for x in reversed(n))
+    u0 = workloads.random_ring(full, rng)
+    f = rng.standard_normal(full)
+    w, q, seq = oracle_schedule(4, n)
+    wseq = np.array(w)[seq]
+    ref = sweeps.solve_ir(u0, f, h, wseq, 1e-10, 1, 60, fmt)
+    p = explicit_plan(n, h, w, q, seq, dtype=fmt)
+    ug = dev(u0)
+    info = srj.srj_solve_ir(p, ug, dev(f), 1e-10, 1, 60)
+    assert ref["status"] == "ok" and info["status"] == "ok"
+    assert info["cycles"] == ref["outer"]
+    assert abs(info["relres"] - ref["relres"]) <= 1e-12 * ref["relres"]
+    assert np.array_equal(host(ug), ref["u"])
+
+
 # ------------------------------------------------------------------ error paths
 
 def test_errors():
