@@ -36,7 +36,7 @@ template <class S, int T, int D>
 __global__ __launch_bounds__(512) void k_sweep3d_tb(const S* __restrict__ uin, S* __restrict__ uout,
                                                     const S* __restrict__ bb, int64_t px, int64_t py, int nx,
                                                     int ny, int nz, Coefs3T<T> co, int Tact, int ntx, int nty,
-                                                    int zs)
+                                                    int ntz, int zs)
 {
     using Cm = typename Tr<S>::C;
     constexpr int SX = 64 - 2 * T;        // output columns per tile
@@ -45,7 +45,11 @@ __global__ __launch_bounds__(512) void k_sweep3d_tb(const S* __restrict__ uin, S
 
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int bid = (int)blockIdx.x;
+    // consecutive block indices go to different XCDs; remap them so that each XCD works a
+    // contiguous band of tiles and neighbouring tiles share their halo reads in one L2
+    const int nblk = (int)gridDim.x;  // a multiple of 8 (padded by the launcher)
+    const int bid = (int)(blockIdx.x & 7) * (nblk >> 3) + (int)(blockIdx.x >> 3);
+    if (bid >= ntx * nty * ntz) return;  // padding block: the whole block leaves
     const int tx = bid % ntx, ty = (bid / ntx) % nty, tz = bid / (ntx * nty);
     const int64_t pl = px * py;
 
@@ -200,9 +204,9 @@ static void tb3d(const S* in, S* out, const S* b, const Geo& g, const Coefs& co,
     zs = std::max(1, std::min(zs, (int)g.nz));
     ntz = (int)((g.nz + zs - 1) / zs);
     zs = (int)((g.nz + ntz - 1) / ntz);
-    const int nblk = ntx * nty * ntz;
+    const int nblk = (ntx * nty * ntz + 7) / 8 * 8;
     hipLaunchKernelGGL((k_sweep3d_tb<S, T, D>), dim3(nblk), dim3(512), 0, s, in, out, b, g.px, g.py, (int)g.nx,
-                       (int)g.ny, (int)g.nz, ct, Tact, ntx, nty, zs);
+                       (int)g.ny, (int)g.nz, ct, Tact, ntx, nty, ntz, zs);
 }
 
 template <class S, int D>
