@@ -341,3 +341,17 @@ def test_errors():
     ug[3, 3] = 7.0
     info = srj.srj_solve(p, ug, dev(z), 1e-10, 10)
     assert info["status"] == "ok" and info["sweeps"] == 0 and float(ug.abs().max()) == 0.0
+    # fusion depths: at most 8 in 2D, 4 in 3D; segment heights non-negative
+    with pytest.raises(srj.SrjError) as e:
+        srj.srj_plan_set_fusion(p, 9)
+    assert e.value.status == 1
+    with pytest.raises(srj.SrjError) as e:
+        srj.srj_plan_set_fusion(p, 8, -1)
+    assert e.value.status == 1
+    p3 = srj.srj_plan((6, 5, 4), 1.0 / 7, omega=[1.0], q=[1])
+    assert srj.srj_plan_describe(p3)["fused_sweeps"] == 4
+    with pytest.raises(srj.SrjError) as e:
+        srj.srj_plan_set_fusion(p3, 5)
+    assert e.value.status == 1
+    srj.srj_plan_set_fusion(p3, 0)
+    assert srj.srj_plan_describe(p3)["fused_sweeps"] == 0
