@@ -276,6 +276,7 @@ srj_status srj_batch_plan(int32_t count, const srj_grid* grids, const srj_schedu
         b->M.push_back(P.M);
     }
     b->npart = npart;
+    cur += kAlign;  // slack after the last field: tiles may read one element past a ring
     if (hipMalloc(&b->pool, cur) != hipSuccess) {
         destroy_batch(b);
         return report(SRJ_ENOMEM, "batch pool of " + std::to_string(cur) + " bytes");

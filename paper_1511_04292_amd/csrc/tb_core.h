@@ -62,6 +62,29 @@ __device__ __forceinline__ void tb_store(bf16_t v, __amdgpu_buffer_rsrc_t r, int
     __builtin_amdgcn_raw_buffer_store_b16(v.v, r, off, 0, 0);
 }
 
+// Two neighbouring elements x, x+1 of a row in one load (x odd: the pair is aligned to its
+// size, since interior column 1 of every row is).
+typedef double tb_d2 __attribute__((ext_vector_type(2)));
+typedef float tb_f2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void tb_ld_pair(const double* p, double& a, double& b)
+{
+    const tb_d2 v = *reinterpret_cast<const tb_d2*>(p);
+    a = v.x;
+    b = v.y;
+}
+__device__ __forceinline__ void tb_ld_pair(const float* p, float& a, float& b)
+{
+    const tb_f2 v = *reinterpret_cast<const tb_f2*>(p);
+    a = v.x;
+    b = v.y;
+}
+__device__ __forceinline__ void tb_ld_pair(const bf16_t* p, float& a, float& b)
+{
+    const uint32_t w = *reinterpret_cast<const uint32_t*>(p);
+    a = __uint_as_float(w << 16);
+    b = __uint_as_float(w & 0xffff0000u);
+}
+
 // Largest segment height whose store window (H rows of pitch px plus one strip) keeps the
 // buffer record count below kTbMasked.
 inline int tb_max_rows(int64_t px, int esize)
@@ -209,13 +232,30 @@ __device__ __forceinline__ void tb_tile_body(const S* __restrict__ uin, S* __res
 #pragma unroll
         for (int c = 0; c < C; ++c) R.p1[l][c] = R.p2[l][c] = R.bq[l][c] = (Cm)0;
 
+    // With two columns per lane and T even, a lane's columns x0, x0+1 start at an odd x and
+    // are loaded as one pair.  Pairs left of the ring start at -1 and pairs right of it at
+    // the last odd x <= nx+1: one element beyond the ring column on either side, inside the
+    // field's allocation.  Such lanes then hold values that are not the ring's, but they are
+    // never updated or stored, and the ring lanes they feed keep their values.
+    constexpr bool kPairs = (C == 2) && (T % 2 == 0);
+    int64_t xpair = x0;
+    if (kPairs) {
+        const int64_t xlast = ((nx + 1) & 1) ? (int64_t)nx + 1 : (int64_t)nx;
+        xpair = x0 < -1 ? -1 : (x0 > xlast ? xlast : x0);
+    }
+
     // in-bounds loads of row r (clamped to the ring rows)
     auto load_row = [&](int r, Cm* vu, Cm* vb) {
         const int64_t rowp = (int64_t)max(0, min(r, ny + 1)) * px;
+        if constexpr (kPairs) {
+            tb_ld_pair(uin + rowp + xpair, vu[0], vu[1]);
+            tb_ld_pair(bb + rowp + xpair, vb[0], vb[1]);
+        } else {
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-            vu[c] = Tr<S>::ld(uin[rowp + xc[c]]);
-            vb[c] = Tr<S>::ld(bb[rowp + xc[c]]);
+            for (int c = 0; c < C; ++c) {
+                vu[c] = Tr<S>::ld(uin[rowp + xc[c]]);
+                vb[c] = Tr<S>::ld(bb[rowp + xc[c]]);
+            }
         }
     };
 
