@@ -108,9 +108,14 @@ struct TbRegs {
 // dir = +1 streams rows downwards (level l works on row r - l), -1 upwards (row r + l); the
 // window then holds the rows in the other order and (S + N) is formed as (N + S), which is
 // the same IEEE sum.
-// CLEAN steps know that every computed point is an interior point of the grid and that
-// all T levels apply, and so skip the per-level selects.
-template <class S, int T, int C, int D, bool CLEAN>
+// MODE says what the step must check:
+//   TB_CLEAN: every computed point is an interior point of the grid and all T levels apply,
+//             so no selects;
+//   TB_COLS:  every computed row is an interior row and all T levels apply; columns outside
+//             the grid (the ring and beyond, fixed per lane) keep their values;
+//   TB_FULL:  rows, columns and levels above Tact are all checked.
+enum { TB_CLEAN = 0, TB_COLS = 1, TB_FULL = 2 };
+template <class S, int T, int C, int D, int MODE>
 __device__ __forceinline__ void tb_step(TbRegs<typename Tr<S>::C, T, C, D>& R, int s, int lmax, int r,
                                         const typename Tr<S>::C (&cf)[T], const bool (&upd)[C], int ny,
                                         int Tact, int y0, int y1, int rowbytes, const int (&lanebase)[C],
@@ -120,8 +125,8 @@ __device__ __forceinline__ void tb_step(TbRegs<typename Tr<S>::C, T, C, D>& R, i
     Cm in[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) in[c] = R.U[s][c];
-    const int rv = CLEAN ? 0 : vcopy(r);
-    const int dv = CLEAN ? 0 : vcopy(dir);
+    const int rv = MODE == TB_FULL ? vcopy(r) : 0;
+    const int dv = MODE == TB_FULL ? vcopy(dir) : 0;
 #pragma unroll
     for (int l = 1; l <= T; ++l) {
         if (l > lmax + 1) break;
@@ -130,7 +135,7 @@ __device__ __forceinline__ void tb_step(TbRegs<typename Tr<S>::C, T, C, D>& R, i
             const Cm wn = dpp_from_left(R.p1[l - 1][C - 1]);
             const Cm en = dpp_from_right(R.p1[l - 1][0]);
             bool rowok = true;
-            if (!CLEAN) {
+            if (MODE == TB_FULL) {
                 const int jv = rv - dv * l;
                 rowok = (jv >= 1) & (jv <= ny) & (l <= Tact);
             }
@@ -142,7 +147,7 @@ __device__ __forceinline__ void tb_step(TbRegs<typename Tr<S>::C, T, C, D>& R, i
                 const Cm sm = (W + E) + (R.p2[l - 1][c] + in[c]);
                 const Cm t = (sm + R.bq[l - 1][c]) - (Cm)4 * m;
                 Cm v = Tr<S>::ld(Tr<S>::st(m + cf[l - 1] * t));
-                if (CLEAN) {
+                if (MODE == TB_CLEAN) {
                     out[c] = v;
                 } else {
                     // v is always computed: an empty register constraint keeps the compiler
@@ -186,10 +191,11 @@ __device__ __forceinline__ void tb_step(TbRegs<typename Tr<S>::C, T, C, D>& R, i
 // are needed; the rest of the step loop is free of branches so that the D row loads in
 // flight (register slots named statically by unrolling the loop D times) overlap D steps
 // of arithmetic.  H * px * sizeof(S) must not exceed what tb_max_rows allows.
-template <class S, int T, int C, int D, bool CLEAN>
+template <class S, int T, int C, int D, int FILL, int STEADY>
 __device__ __forceinline__ void tb_tile_body(const S* __restrict__ uin, S* __restrict__ uout,
                                              const S* __restrict__ bb, int64_t px, int nx, int ny,
-                                             const typename Tr<S>::C (&cf)[T], int Tact, int st, int sg, int H)
+                                             const typename Tr<S>::C (&cf)[T], int Tact, int st, int sg, int H,
+                                             int dir)
 {
     using Cm = typename Tr<S>::C;
     constexpr int SW = 64 * C - 2 * T;
@@ -201,11 +207,6 @@ __device__ __forceinline__ void tb_tile_body(const S* __restrict__ uin, S* __res
     const int y1 = min(y0 + H, ny + 1);
     const int rb = y0 - T;
     const int rl = y1 - 1 + T;
-    // odd segments stream upwards, so that the halo rows two neighbouring segments share
-    // are read by both at the same time (both at their start or both at their end) and the
-    // second read can come from L2; (S + N) equals (N + S) exactly, so the direction does
-    // not change any result
-    const int dir = (sg & 1) ? -1 : 1;
     const int r_first = dir > 0 ? rb : rl;
     const int nsteps = rl - rb + 1;
 
@@ -267,8 +268,8 @@ __device__ __forceinline__ void tb_tile_body(const S* __restrict__ uin, S* __res
     for (int i = 0; i < F; ++i) {
         const int s = i % D;
         const int lmax = min(T, i / 2);
-        tb_step<S, T, C, D, CLEAN>(R, s, lmax, r_first + dir * i, cf, upd, ny, Tact, y0, y1, rowbytes, lanebase, rs,
-                                   dir);
+        tb_step<S, T, C, D, FILL>(R, s, lmax, r_first + dir * i, cf, upd, ny, Tact, y0, y1, rowbytes, lanebase, rs,
+                                  dir);
         load_row(r_first + dir * (i + D), R.U[s], R.B[s]);
         // keep each row load in its step: bunched at the end of the loop body they would be
         // waited for at the top of the next iteration
@@ -280,14 +281,18 @@ __device__ __forceinline__ void tb_tile_body(const S* __restrict__ uin, S* __res
 #pragma unroll
         for (int s = 0; s < D; ++s) {
             const int r = r_first + dir * (i0 + s);
-            tb_step<S, T, C, D, CLEAN>(R, s, T, r, cf, upd, ny, Tact, y0, y1, rowbytes, lanebase, rs, dir);
+            tb_step<S, T, C, D, STEADY>(R, s, T, r, cf, upd, ny, Tact, y0, y1, rowbytes, lanebase, rs, dir);
             load_row(r + dir * D, R.U[s], R.B[s]);
             __builtin_amdgcn_sched_barrier(0);
         }
     }
 }
 
-template <class S, int T, int C, int D>
+// EDGES: whether tiles on the grid's edges get their own variants (fill checked, steady
+// state checking columns only).  Each variant adds to the kernel's register count, which is
+// the maximum over all of them; callers whose kernel is already near a waves-per-SIMD step
+// use two variants only.
+template <class S, int T, int C, int D, bool EDGES = true>
 __device__ __forceinline__ void tb_tile(const S* __restrict__ uin, S* __restrict__ uout,
                                         const S* __restrict__ bb, int64_t px, int nx, int ny,
                                         const typename Tr<S>::C (&cf)[T], int Tact, int st, int sg, int H)
@@ -296,12 +301,40 @@ __device__ __forceinline__ void tb_tile(const S* __restrict__ uin, S* __restrict
     const int64_t xs = 1 + (int64_t)st * SW - T;
     const int y0 = 1 + sg * H;
     const int y1 = min(y0 + H, ny + 1);
-    // every computed point interior: rows y0-T+1 .. y1+T-2 and the strip's columns
-    const bool clean = Tact == T && y0 - T + 1 >= 1 && y1 + T - 2 <= ny && xs >= 1 && xs + 64 * C - 1 <= nx;
-    if (clean)
-        tb_tile_body<S, T, C, D, true>(uin, uout, bb, px, nx, ny, cf, Tact, st, sg, H);
-    else
-        tb_tile_body<S, T, C, D, false>(uin, uout, bb, px, nx, ny, cf, Tact, st, sg, H);
+    // computed rows are y0-T+1 .. y1+T-2, computed columns the strip's
+    const bool top = y0 - T + 1 < 1;
+    const bool bottom = y1 + T - 2 > ny;
+    const bool cols = xs < 1 || xs + 64 * C - 1 > nx;
+    // Odd segments stream upwards, so that the halo rows two neighbouring segments share are
+    // read by both at the same time (both at their start or both at their end) and the second
+    // read can come from L2; (S + N) equals (N + S) exactly, so the direction changes no
+    // result.  A tile that reaches the top ring streams down and one that reaches the bottom
+    // ring streams up: its rows outside the grid then all come in the pipeline fill, and only
+    // the fill checks rows.
+    int dir = (sg & 1) ? -1 : 1;
+    if (top) dir = 1;
+    if (bottom) dir = -1;
+    if constexpr (!EDGES || sizeof(S) == 8) {
+        // binary64 keeps two variants: more would raise the kernel's register count past
+        // three waves per SIMD
+        if (Tact < T || top || bottom || cols)
+            tb_tile_body<S, T, C, D, TB_FULL, TB_FULL>(uin, uout, bb, px, nx, ny, cf, Tact, st, sg, H, dir);
+        else
+            tb_tile_body<S, T, C, D, TB_CLEAN, TB_CLEAN>(uin, uout, bb, px, nx, ny, cf, Tact, st, sg, H, dir);
+        return;
+    }
+    if (Tact < T || (top && bottom)) {
+        tb_tile_body<S, T, C, D, TB_FULL, TB_FULL>(uin, uout, bb, px, nx, ny, cf, Tact, st, sg, H, dir);
+    } else if (top || bottom) {
+        if (cols)
+            tb_tile_body<S, T, C, D, TB_FULL, TB_COLS>(uin, uout, bb, px, nx, ny, cf, Tact, st, sg, H, dir);
+        else
+            tb_tile_body<S, T, C, D, TB_FULL, TB_CLEAN>(uin, uout, bb, px, nx, ny, cf, Tact, st, sg, H, dir);
+    } else if (cols) {
+        tb_tile_body<S, T, C, D, TB_COLS, TB_COLS>(uin, uout, bb, px, nx, ny, cf, Tact, st, sg, H, dir);
+    } else {
+        tb_tile_body<S, T, C, D, TB_CLEAN, TB_CLEAN>(uin, uout, bb, px, nx, ny, cf, Tact, st, sg, H, dir);
+    }
 }
 
 }  // namespace srj
