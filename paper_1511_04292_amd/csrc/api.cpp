@@ -67,6 +67,7 @@ struct srj_plan_s {
     double kappa_min = 0, kappa_max = 0, rho = 0, gamma_q = 0, pre = 0, suf = 0;
     int fuse = 8;
     int seg_rows = 0;  // output rows per wave in the fused 2D kernel (0: from the occupancy)
+    uint32_t fused_launches = 0;  // 2D launches so far: their parity alternates the stream direction
 
     // device buffers
     DField A, B, blo, b64f;  // iterate pair, b in the sweep format, FP64 b (low-precision plans)
@@ -206,7 +207,7 @@ srj_status run_sweeps(srj_plan_t p, DField** cur, DField** nxt, const void* b, i
             for (int l = 0; l < T; ++l) co.c[l] = p->cseq[(k + l) % p->M];
             if (p->geo.ndim == 2)
                 HIPCHK(launch_sweep_fused(p->fmt, (*cur)->origin, (*nxt)->origin, b, p->geo, co, T, p->seg_rows,
-                                          p->stream));
+                                          (int)(p->fused_launches++ & 1u), p->stream));
             else
                 HIPCHK(launch_sweep_fused3d(p->fmt, (*cur)->origin, (*nxt)->origin, b, p->geo, co, T, p->stream));
             k += T;

@@ -116,9 +116,11 @@ __global__ __launch_bounds__(256) void k_batch_step(const BProb* __restrict__ pr
             Cm cf[T];
 #pragma unroll
             for (int l = 0; l < T; ++l) cf[l] = (l < Tj) ? (Cm)run.coef[P.coff + (k + l) % P.M] : (Cm)0;
-            // two tile variants only: the batch kernel also holds the residual path
+            // two tile variants only: the batch kernel also holds the residual path; the
+            // stream direction alternates with the problem's launches, as in the single-grid
+            // kernel
             tb_tile<S, T, C, D, false>((const S*)P.d[dcur], (S*)P.d[1 - dcur], (const S*)P.rlo, P.px, P.nx, P.ny, cf,
-                                       Tj, sx, sg, P.H);
+                                       Tj, sx, sg, P.H, (k / T) & 1);
         } else {
             double s, m;
             residual_tile<S, T, C>(P, ucur, dcur, sx, sg, s, m);

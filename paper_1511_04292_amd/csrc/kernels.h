@@ -37,9 +37,10 @@ hipError_t launch_rhs(Fmt f, const double* user_f, double hh, void* blo, double*
 hipError_t launch_sweep_unfused(Fmt f, const void* in, void* out, const void* b, const Geo& g,
                                 double c, hipStream_t s);
 // T consecutive 2D sweeps in -> out in one launch with coefficients co.c[0..T), row
-// segments of H output rows per wave.
+// segments of H output rows per wave.  flip (0 or 1) reverses the direction every segment
+// streams in; callers alternate it from launch to launch (it changes no result).
 hipError_t launch_sweep_fused(Fmt f, const void* in, void* out, const void* b, const Geo& g,
-                              const Coefs& co, int T, int H, hipStream_t s);
+                              const Coefs& co, int T, int H, int flip, hipStream_t s);
 // T <= kMaxFuse3d sweeps (coefficients co.c[0..T)) of a 3D grid in one launch: x-y tiles of
 // 64 x 32 with T-wide halos, streamed in z.  Needs fused3d_fits(g, f): a padded z plane
 // below 1 GiB (its stores are addressed within one plane).

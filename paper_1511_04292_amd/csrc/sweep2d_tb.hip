@@ -32,7 +32,7 @@ template <class S, int T, int C, int D>
 __global__ __launch_bounds__(256) void k_sweep2d_tb(const S* __restrict__ uin, S* __restrict__ uout,
                                                     const S* __restrict__ bb, int64_t px, int nx,
                                                     int ny, CoefsT<T> co, int nstrip, int nwaves,
-                                                    int H, int remap)
+                                                    int H, int remap, int flip)
 {
     using Cm = typename Tr<S>::C;
     const int nblk = (int)gridDim.x;  // a multiple of 8 (padded by the launcher)
@@ -43,7 +43,7 @@ __global__ __launch_bounds__(256) void k_sweep2d_tb(const S* __restrict__ uin, S
     Cm cf[T];
 #pragma unroll
     for (int l = 0; l < T; ++l) cf[l] = (Cm)co.c[l];
-    tb_tile<S, T, C, D>(uin, uout, bb, px, nx, ny, cf, T, wid % nstrip, wid / nstrip, H);
+    tb_tile<S, T, C, D>(uin, uout, bb, px, nx, ny, cf, T, wid % nstrip, wid / nstrip, H, flip);
 }
 
 static int env_int(const char* name, int dflt)
@@ -69,7 +69,8 @@ static int tb_resident_waves()
 }
 
 template <class S, int T, int C, int D>
-static void tb2d(const S* in, S* out, const S* b, const Geo& g, const Coefs& co, int H, hipStream_t s)
+static void tb2d(const S* in, S* out, const S* b, const Geo& g, const Coefs& co, int H, int flip,
+                 hipStream_t s)
 {
     constexpr int SW = 64 * C - 2 * T;
     static const int remap = env_int("SRJ_TB_XCD_REMAP", 1);  // tuning knob, default on
@@ -88,21 +89,22 @@ static void tb2d(const S* in, S* out, const S* b, const Geo& g, const Coefs& co,
     const int nwaves = nstrip * nseg;
     const int nblk = ((nwaves + 3) / 4 + 7) / 8 * 8;
     hipLaunchKernelGGL((k_sweep2d_tb<S, T, C, D>), dim3(nblk), dim3(256), 0, s, in, out, b, g.px,
-                       (int)g.nx, (int)g.ny, ct, nstrip, nwaves, H, remap);
+                       (int)g.nx, (int)g.ny, ct, nstrip, nwaves, H, remap, flip);
 }
 
 template <class S, int C, int D>
-static void tb2d_T(const S* in, S* out, const S* b, const Geo& g, const Coefs& co, int T, int H, hipStream_t s)
+static void tb2d_T(const S* in, S* out, const S* b, const Geo& g, const Coefs& co, int T, int H, int flip,
+                   hipStream_t s)
 {
     switch (T) {
-    case 1: tb2d<S, 1, C, D>(in, out, b, g, co, H, s); break;
-    case 2: tb2d<S, 2, C, D>(in, out, b, g, co, H, s); break;
-    case 3: tb2d<S, 3, C, D>(in, out, b, g, co, H, s); break;
-    case 4: tb2d<S, 4, C, D>(in, out, b, g, co, H, s); break;
-    case 5: tb2d<S, 5, C, D>(in, out, b, g, co, H, s); break;
-    case 6: tb2d<S, 6, C, D>(in, out, b, g, co, H, s); break;
-    case 7: tb2d<S, 7, C, D>(in, out, b, g, co, H, s); break;
-    default: tb2d<S, 8, C, D>(in, out, b, g, co, H, s); break;
+    case 1: tb2d<S, 1, C, D>(in, out, b, g, co, H, flip, s); break;
+    case 2: tb2d<S, 2, C, D>(in, out, b, g, co, H, flip, s); break;
+    case 3: tb2d<S, 3, C, D>(in, out, b, g, co, H, flip, s); break;
+    case 4: tb2d<S, 4, C, D>(in, out, b, g, co, H, flip, s); break;
+    case 5: tb2d<S, 5, C, D>(in, out, b, g, co, H, flip, s); break;
+    case 6: tb2d<S, 6, C, D>(in, out, b, g, co, H, flip, s); break;
+    case 7: tb2d<S, 7, C, D>(in, out, b, g, co, H, flip, s); break;
+    default: tb2d<S, 8, C, D>(in, out, b, g, co, H, flip, s); break;
     }
 }
 
@@ -110,25 +112,27 @@ static void tb2d_T(const S* in, S* out, const S* b, const Geo& g, const Coefs& c
 // and the kernel keeps 3 waves per SIMD), 4 for the 4-byte and 2-byte formats.
 template <class S>
 static void tb2d_dispatch(const S* in, S* out, const S* b, const Geo& g, const Coefs& co, int T,
-                          int H, hipStream_t s)
+                          int H, int flip, hipStream_t s)
 {
     constexpr int C = 2;
     static const int knob = env_int("SRJ_TB_PREFETCH", 0);  // tuning knob, 0 = per format
     const int pf = knob > 0 ? knob : (sizeof(S) == 8 ? 3 : 4);
     if (pf == 2) {
-        tb2d_T<S, C, 2>(in, out, b, g, co, T, H, s);
+        tb2d_T<S, C, 2>(in, out, b, g, co, T, H, flip, s);
     } else if (pf == 3) {
-        tb2d_T<S, C, 3>(in, out, b, g, co, T, H, s);
+        tb2d_T<S, C, 3>(in, out, b, g, co, T, H, flip, s);
     } else {
-        tb2d_T<S, C, 4>(in, out, b, g, co, T, H, s);
+        tb2d_T<S, C, 4>(in, out, b, g, co, T, H, flip, s);
     }
 }
 
 hipError_t launch_sweep_fused(Fmt f, const void* in, void* out, const void* b, const Geo& g,
-                              const Coefs& co, int T, int H, hipStream_t s)
+                              const Coefs& co, int T, int H, int flip, hipStream_t s)
 {
     if (g.ndim != 2 || T < 1 || T > kMaxFuse || H < 0) return hipErrorInvalidValue;  // H = 0: automatic
-    SRJ_DISPATCH(f, tb2d_dispatch<S>((const S*)in, (S*)out, (const S*)b, g, co, T, H, s));
+    static const int flips = env_int("SRJ_TB_FLIP", 1);  // tuning knob, default on
+    flip = flips ? (flip & 1) : 0;
+    SRJ_DISPATCH(f, tb2d_dispatch<S>((const S*)in, (S*)out, (const S*)b, g, co, T, H, flip, s));
     return hipGetLastError();
 }
 

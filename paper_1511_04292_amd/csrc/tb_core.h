@@ -295,7 +295,8 @@ __device__ __forceinline__ void tb_tile_body(const S* __restrict__ uin, S* __res
 template <class S, int T, int C, int D, bool EDGES = true>
 __device__ __forceinline__ void tb_tile(const S* __restrict__ uin, S* __restrict__ uout,
                                         const S* __restrict__ bb, int64_t px, int nx, int ny,
-                                        const typename Tr<S>::C (&cf)[T], int Tact, int st, int sg, int H)
+                                        const typename Tr<S>::C (&cf)[T], int Tact, int st, int sg, int H,
+                                        int flip = 0)
 {
     constexpr int SW = 64 * C - 2 * T;
     const int64_t xs = 1 + (int64_t)st * SW - T;
@@ -305,13 +306,15 @@ __device__ __forceinline__ void tb_tile(const S* __restrict__ uin, S* __restrict
     const bool top = y0 - T + 1 < 1;
     const bool bottom = y1 + T - 2 > ny;
     const bool cols = xs < 1 || xs + 64 * C - 1 > nx;
-    // Odd segments stream upwards, so that the halo rows two neighbouring segments share are
-    // read by both at the same time (both at their start or both at their end) and the second
-    // read can come from L2; (S + N) equals (N + S) exactly, so the direction changes no
-    // result.  A tile that reaches the top ring streams down and one that reaches the bottom
-    // ring streams up: its rows outside the grid then all come in the pipeline fill, and only
-    // the fill checks rows.
-    int dir = (sg & 1) ? -1 : 1;
+    // Segments of one parity stream upwards, so that the halo rows two neighbouring segments
+    // share are read by both at the same time (both at their start or both at their end) and
+    // the second read can come from L2; (S + N) equals (N + S) exactly, so the direction
+    // changes no result.  flip swaps the parities: launched alternately, each launch starts
+    // every segment on the rows the previous launch touched last, which the device's
+    // memory-side cache is then most likely to still hold.  A tile that reaches the top ring
+    // streams down and one that reaches the bottom ring streams up: its rows outside the grid
+    // then all come in the pipeline fill, and only the fill checks rows.
+    int dir = ((sg + flip) & 1) ? -1 : 1;
     if (top) dir = 1;
     if (bottom) dir = -1;
     if constexpr (!EDGES || sizeof(S) == 8) {
