@@ -2,11 +2,11 @@
 //
 // T consecutive scheduled sweeps (Sec. 2; each step the 7-point form of Sec. 3.1's update
 // with d = 3, evaluated with the association and rounding of the unfused kernel, so the
-// result is bit-identical to T unfused sweeps) are applied in one launch.  A block of 8 waves
-// owns an x-y tile of 64 columns (one per lane) by 32 rows (4 per wave) and streams a run of
+// result is bit-identical to T unfused sweeps) are applied in one launch.  A block of 16 waves
+// owns an x-y tile of 64 columns (one per lane) by 32 rows (2 per wave) and streams a run of
 // z planes through it.  At step k the block takes plane k (level 0) and computes level l for
 // plane k - l, l = 1..T, from level l-1 planes k-l-1, k-l and k-l+1: each lane keeps, per
-// level, the two older planes of its 4 points in registers; x neighbours cross lanes by DPP
+// level, the two older planes of its 2 points in registers; x neighbours cross lanes by DPP
 // shifts, y neighbours are the lane's own rows except across wave boundaries, where the
 // boundary rows of each level are exchanged through LDS (double-buffered by step parity, one
 // barrier per step).  One HBM read of u and b and one write of u serve T sweeps; tiles overlap
@@ -28,12 +28,13 @@ template <int T> struct Coefs3T {
     double c[T];
 };
 
-constexpr int k3Waves = 8;                  // waves per block
-constexpr int k3Rows = 4;                   // rows per wave
+constexpr int k3Waves = 16;                 // waves per block
+constexpr int k3Rows = 2;                   // rows per wave
 constexpr int k3TileY = k3Waves * k3Rows;   // tile rows
+constexpr int k3Threads = 64 * k3Waves;
 
 template <class S, int T, int D>
-__global__ __launch_bounds__(512) void k_sweep3d_tb(const S* __restrict__ uin, S* __restrict__ uout,
+__global__ __launch_bounds__(k3Threads) void k_sweep3d_tb(const S* __restrict__ uin, S* __restrict__ uout,
                                                     const S* __restrict__ bb, int64_t px, int64_t py, int nx,
                                                     int ny, int nz, Coefs3T<T> co, int Tact, int ntx, int nty,
                                                     int ntz, int zs)
@@ -180,7 +181,7 @@ static int tb3_resident_blocks()
 {
     static const int blocks = [] {
         int nb = 0, dev = 0, ncu = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep3d_tb<S, T, D>, 512, 0) != hipSuccess) nb = 1;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep3d_tb<S, T, D>, k3Threads, 0) != hipSuccess) nb = 1;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
             ncu = 1;
@@ -205,7 +206,7 @@ static void tb3d(const S* in, S* out, const S* b, const Geo& g, const Coefs& co,
     ntz = (int)((g.nz + zs - 1) / zs);
     zs = (int)((g.nz + ntz - 1) / ntz);
     const int nblk = (ntx * nty * ntz + 7) / 8 * 8;
-    hipLaunchKernelGGL((k_sweep3d_tb<S, T, D>), dim3(nblk), dim3(512), 0, s, in, out, b, g.px, g.py, (int)g.nx,
+    hipLaunchKernelGGL((k_sweep3d_tb<S, T, D>), dim3(nblk), dim3(k3Threads), 0, s, in, out, b, g.px, g.py, (int)g.nx,
                        (int)g.ny, (int)g.nz, ct, Tact, ntx, nty, ntz, zs);
 }
 
