@@ -76,9 +76,9 @@ def ingest_counters(fetch_dir, write_dir, workload="blobs2d_4096x4096_f64"):
         wb = wk * 1024 * wscale
         short = k.split("(")[0].replace("void ", "").replace("srj::", "")
         rows.append(f"| `{short}` | {cnt} | {fk:.0f} | {wk:.0f} | {rb / 1e6:.1f} + {wb / 1e6:.1f} = {(rb + wb) / 1e6:.1f} |")
-        if short.startswith("k_sweep2d_tb<double, 8, 2,"):
-            d = short.split(",")[-1].strip(" >")
-            out[f"k_sweep2d_tb<double,8,2,{d}>|{workload}"] = {
+        if short.startswith("k_sweep2d_tb<double,"):
+            key = short.replace(" ", "")
+            out[f"{key}|{workload}"] = {
                 "bytes_per_launch": int(rb + wb), "read_bytes": int(rb), "write_bytes": int(wb),
                 "fetch_scale": round(fscale, 4), "write_scale": round(wscale, 4),
                 "kernel_source_sha256_16": kernel_source_hash(),
@@ -215,7 +215,7 @@ def main():
         # counter runs measure the default launch shape only
         if args.fuse is not None:
             srj.srj_plan_set_fusion(plan, args.fuse)
-        tuned = {"fused_sweeps": args.fuse if args.fuse is not None else 8, "seg_rows": 0, "tuned": False}
+        tuned = {"fused_sweeps": int(srj.srj_plan_describe(plan)["fused_sweeps"]), "seg_rows": 0, "tuned": False}
     else:
         t0 = time.perf_counter()
         tuned = dict(srj.srj_plan_tune(plan), tuned=True, seconds=round(time.perf_counter() - t0, 3))
@@ -278,9 +278,10 @@ def main():
     achieved = bytes_launch / avg_launch / 1e9
     kname = f"k_sweep2d_tb<double,{fuse},2,3>" if fuse > 0 else "k_sweep2d<double>"
     wname = f"blobs2d_{n}x{n}_f64"
-    # counters were taken on the default launch shape (8 sweeps, segment height from the
-    # occupancy); another tuned shape has no committed traffic
-    traffic = measured_traffic(kname, wname) if (fuse == 8 and int(tuned["seg_rows"]) == 0) else None
+    # counters were taken on the default launch shape (the default depth, segment height
+    # from the occupancy); the record is keyed by kernel (and so depth), another segment
+    # height has no committed traffic
+    traffic = measured_traffic(kname, wname) if int(tuned["seg_rows"]) == 0 else None
 
     # unfused reference sweep on the same grid, for the per-sweep HBM figure
     srj.srj_plan_set_fusion(plan, 0)

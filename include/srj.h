@@ -14,7 +14,8 @@
  * With b = (h*h) f, one step with weight w (c = w / (2d)) is
  *     u' = u + c * ( (sum of the 2d neighbours + b) - 2d u ),
  * evaluated with the fixed association ((W+E)+(S+N))[+(D+U)], then + b, then - 2d u,
- * then u + c*t, with no fused multiply-add.  The residual r = b - A u (A = 2d I minus
+ * then u + c*t, each operation rounded on its own (in 2D the kernels form "- 4u" with a
+ * fused multiply-add, which is the same value since 4u is exact).  The residual r = b - A u (A = 2d I minus
  * the neighbour sum, units of h^2) is the t of that step; relres = ||r||_2 / ||b~||_2,
  * b~ being the residual of the state with a zero interior (source plus boundary terms).
  *
@@ -117,7 +118,8 @@ void srj_plan_destroy(srj_plan_t plan);
 srj_status srj_plan_describe(srj_plan_t plan, srj_plan_desc* out);
 /* Copy the ordered level indices of one cycle (cap >= M) into seq. */
 srj_status srj_plan_sequence(srj_plan_t plan, int32_t* seq, int64_t cap);
-/* Override the number of sweeps fused per launch (0 = unfused reference kernel, at most 8)
+/* Override the number of sweeps fused per launch (0 = unfused reference kernel; at most
+ * 10 in 2D, 4 in 3D; the default is the largest)
  * and the output rows each wave of the fused 2D kernel computes (seg_rows = 0, the
  * default: chosen per launch so that the grid of waves fills the device's resident wave
  * slots once, from the kernel's occupancy and the number of compute units).  The results
@@ -195,7 +197,7 @@ void srj_batch_destroy(srj_batch_t batch);
  * measured.  Results of later solves are bit-identical whatever is
  * chosen; only their speed changes.  Synchronises the plan's stream; takes milliseconds
  * to about a second for the largest grids.
- *   srj_plan_tune: 2D plans time fusion depths {8, 6, 4} x segment heights {automatic,
+ *   srj_plan_tune: 2D plans time fusion depths {10, 8, 6, 4} x segment heights {automatic,
  *     24, 32, 48, 64, 96, 128}; 3D plans fusion depths {4, 3, 2, 1, 0}.  Sets the plan's
  *     fusion (as srj_plan_set_fusion would).
  *   srj_batch_tune: times the batch's sweep launch with every problem sweeping, for

@@ -406,7 +406,7 @@ srj_status srj_plan_sequence(srj_plan_t p, int32_t* seq, int64_t cap)
 srj_status srj_plan_set_fusion(srj_plan_t p, int32_t fused, int32_t seg_rows)
 {
     if (!p) return fail(SRJ_EINVAL, "null plan");
-    if (fused < 0 || fused > kMaxFuse) return fail(SRJ_EINVAL, "fusion depth must be in [0, 8]");
+    if (fused < 0 || fused > kMaxFuse) return fail(SRJ_EINVAL, "fusion depth must be in [0, 10]");
     if (p->geo.ndim == 3 && fused > kMaxFuse3d) return fail(SRJ_EINVAL, "3D fusion depth must be in [0, 4]");
     if (p->geo.ndim == 3 && fused > 0 && !fused3d_fits(p->geo, p->fmt))
         return fail(SRJ_EINVAL, "z planes too large for the fused 3D kernel (1 GiB per plane at most)");
@@ -483,7 +483,7 @@ srj_status srj_plan_tune(srj_plan_t p, srj_tune_info* info)
     std::vector<Cand> cands;
     cands.push_back({p->fuse, p->seg_rows});  // the configuration in place, timed first
     if (p->geo.ndim == 2) {
-        for (int T : {8, 6, 4})
+        for (int T : {10, 8, 6, 4})
             for (int H : {0, 24, 32, 48, 64, 96, 128}) cands.push_back({T, H});
     } else {
         if (fused3d_fits(p->geo, p->fmt))

@@ -104,26 +104,23 @@ static void tb2d_T(const S* in, S* out, const S* b, const Geo& g, const Coefs& c
     case 5: tb2d<S, 5, C, D>(in, out, b, g, co, H, flip, s); break;
     case 6: tb2d<S, 6, C, D>(in, out, b, g, co, H, flip, s); break;
     case 7: tb2d<S, 7, C, D>(in, out, b, g, co, H, flip, s); break;
-    default: tb2d<S, 8, C, D>(in, out, b, g, co, H, flip, s); break;
+    case 8: tb2d<S, 8, C, D>(in, out, b, g, co, H, flip, s); break;
+    case 9: tb2d<S, 9, C, D>(in, out, b, g, co, H, flip, s); break;
+    default: tb2d<S, 10, C, D>(in, out, b, g, co, H, flip, s); break;
     }
 }
 
 // Rows in flight per wave: 3 for binary64 (its unrolled loop then matches the 3-row window
-// and the kernel keeps 3 waves per SIMD), 4 for the 4-byte and 2-byte formats.
+// and the kernel keeps 3 waves per SIMD at 8 sweeps), 4 for the 4-byte and 2-byte formats.
 template <class S>
 static void tb2d_dispatch(const S* in, S* out, const S* b, const Geo& g, const Coefs& co, int T,
                           int H, int flip, hipStream_t s)
 {
     constexpr int C = 2;
-    static const int knob = env_int("SRJ_TB_PREFETCH", 0);  // tuning knob, 0 = per format
-    const int pf = knob > 0 ? knob : (sizeof(S) == 8 ? 3 : 4);
-    if (pf == 2) {
-        tb2d_T<S, C, 2>(in, out, b, g, co, T, H, flip, s);
-    } else if (pf == 3) {
+    if constexpr (sizeof(S) == 8)
         tb2d_T<S, C, 3>(in, out, b, g, co, T, H, flip, s);
-    } else {
+    else
         tb2d_T<S, C, 4>(in, out, b, g, co, T, H, flip, s);
-    }
 }
 
 hipError_t launch_sweep_fused(Fmt f, const void* in, void* out, const void* b, const Geo& g,

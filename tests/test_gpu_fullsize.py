@@ -38,7 +38,7 @@ def test_blobs_4096_window_bitwise(blobs):
     w, q, seq = oracle_schedule(10, wl["n"])
     M = int(np.sum(q))
     plan = srj.srj_plan(wl["n"], wl["h"], omega=w, q=q, sequence=seq)
-    assert srj.srj_plan_describe(plan)["fused_sweeps"] == 8
+    assert srj.srj_plan_describe(plan)["fused_sweeps"] == 10
     c = sweeps.coefficients(np.asarray(w)[seq], 2)
     b = sweeps.rhs(wl["f"], wl["h"])
     for k0, n in ((0, 64), (M - 21, 43)):  # the second window crosses the cycle end

@@ -97,7 +97,7 @@ def test_single_sweep_3d_bitwise(n):
 
 # ------------------------------------------------------- temporally blocked sweeps
 
-@pytest.mark.parametrize("T", [1, 2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("T", [1, 2, 3, 4, 5, 6, 7, 8, 9, 10])
 @pytest.mark.parametrize("n", [(300, 200), (129, 150), (2, 2), (1, 70), (250, 1)])
 def test_fused_sweeps_bitwise(T, n):
     h = 1.0 / (max(n) + 1)
@@ -150,12 +150,12 @@ def test_fused_equals_unfused_on_gpu():
     u, f = rand_case(n, 4)
     w, q, seq = oracle_schedule(5, n)
     outs = []
-    for T in (0, 8):
+    for T in (0, 8, 10):
         p = explicit_plan(n, h, w, q, seq, fuse=T)
         ug = dev(u)
         srj.srj_sweeps(p, ug, dev(f), 0, 2 * int(np.sum(q)) + 3)
         outs.append(host(ug))
-    assert np.array_equal(outs[0], outs[1])
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
 
 
 # ------------------------------------------------------------------ residuals
@@ -341,9 +341,10 @@ def test_errors():
     ug[3, 3] = 7.0
     info = srj.srj_solve(p, ug, dev(z), 1e-10, 10)
     assert info["status"] == "ok" and info["sweeps"] == 0 and float(ug.abs().max()) == 0.0
-    # fusion depths: at most 8 in 2D, 4 in 3D; segment heights non-negative
+    # fusion depths: at most 10 in 2D (the default), 4 in 3D; segment heights non-negative
+    assert srj.srj_plan_describe(p)["fused_sweeps"] == 10
     with pytest.raises(srj.SrjError) as e:
-        srj.srj_plan_set_fusion(p, 9)
+        srj.srj_plan_set_fusion(p, 11)
     assert e.value.status == 1
     with pytest.raises(srj.SrjError) as e:
         srj.srj_plan_set_fusion(p, 8, -1)
