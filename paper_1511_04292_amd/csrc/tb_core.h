@@ -323,9 +323,9 @@ __device__ __forceinline__ void tb_tile(const S* __restrict__ uin, S* __restrict
     int dir = ((sg + flip) & 1) ? -1 : 1;
     if (top) dir = 1;
     if (bottom) dir = -1;
-    if constexpr (!EDGES || sizeof(S) == 8) {
-        // binary64 keeps two variants: more would raise the kernel's register count past
-        // three waves per SIMD
+    if constexpr (!EDGES || (sizeof(S) == 8 && T < 10)) {
+        // binary64 below 10 levels keeps two variants: more would raise the kernel's register
+        // count past three waves per SIMD at 8 levels (at 10 it holds two waves either way)
         if (Tact < T || top || bottom || cols)
             tb_tile_body<S, T, C, D, TB_FULL, TB_FULL>(uin, uout, bb, px, nx, ny, cf, Tact, st, sg, H, dir);
         else
