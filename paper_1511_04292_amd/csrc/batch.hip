@@ -28,7 +28,8 @@ namespace srj {
 
 constexpr int kBatchT = 8;  // sweeps fused per launch
 constexpr int kBatchC = 2;  // columns per lane
-constexpr int kBatchD = 4;  // rows in flight per wave
+constexpr int kBatchD = 3;  // rows in flight per wave (the kernel then keeps 3 waves per SIMD
+                             // with the edge-tile variants)
 
 int batch_fuse() { return kBatchT; }
 
@@ -116,10 +117,9 @@ __global__ __launch_bounds__(256) void k_batch_step(const BProb* __restrict__ pr
             Cm cf[T];
 #pragma unroll
             for (int l = 0; l < T; ++l) cf[l] = (l < Tj) ? (Cm)run.coef[P.coff + (k + l) % P.M] : (Cm)0;
-            // two tile variants only: the batch kernel also holds the residual path; the
-            // stream direction alternates with the problem's launches, as in the single-grid
-            // kernel
-            tb_tile<S, T, C, D, false>((const S*)P.d[dcur], (S*)P.d[1 - dcur], (const S*)P.rlo, P.px, P.nx, P.ny, cf,
+            // the stream direction alternates with the problem's launches, as in the
+            // single-grid kernel
+            tb_tile<S, T, C, D, true>((const S*)P.d[dcur], (S*)P.d[1 - dcur], (const S*)P.rlo, P.px, P.nx, P.ny, cf,
                                        Tj, sx, sg, P.H, (k / T) & 1);
         } else {
             double s, m;

@@ -28,11 +28,12 @@ template <int T> struct CoefsT {
 
 // Blocks are optionally remapped so that each of the 8 XCDs works on a contiguous band of
 // tiles, keeping the overlapping halo reads of neighbouring waves in one L2.
+// The 4- and 2-byte formats are held to 3 waves per SIMD (168 VGPRs): at 10 levels the
+// compiler would otherwise take 185 and leave 2; binary64 is left to the compiler.
 template <class S, int T, int C, int D>
-__global__ __launch_bounds__(256) void k_sweep2d_tb(const S* __restrict__ uin, S* __restrict__ uout,
-                                                    const S* __restrict__ bb, int64_t px, int nx,
-                                                    int ny, CoefsT<T> co, int nstrip, int nwaves,
-                                                    int H, int remap, int flip)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(S) == 8 ? 1 : 3)))
+void k_sweep2d_tb(const S* __restrict__ uin, S* __restrict__ uout, const S* __restrict__ bb, int64_t px, int nx,
+                  int ny, CoefsT<T> co, int nstrip, int nwaves, int H, int remap, int flip)
 {
     using Cm = typename Tr<S>::C;
     const int nblk = (int)gridDim.x;  // a multiple of 8 (padded by the launcher)
