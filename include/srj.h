@@ -171,7 +171,7 @@ srj_status srj_adjoint(srj_plan_t plan, const double* grad_u, double tol, int64_
  * differ; one storage format per batch), each solved by the same FP64 refinement as
  * srj_solve_ir with its own schedule (Sec. 2-4 per problem), all advanced together on
  * the device.  One kernel launch per iteration goes over the tiles of every running
- * problem: tiles of a sweeping problem get up to 8 scheduled sweeps, tiles of a problem
+ * problem: tiles of a sweeping problem get up to 10 scheduled sweeps, tiles of a problem
  * that finished an inner solve get u + d and its binary64 residual, and the last tile of a
  * problem decides it.  The iterations are replayed from a captured HIP graph on an
  * internal stream (the plan's stream is synchronised first).  Problems never wait on one
@@ -204,7 +204,7 @@ void srj_batch_destroy(srj_batch_t batch);
  *     largest tile heights {32, 64, 128, 256}, and keeps the fastest as the height the
  *     batch starts from (it still shortens tiles as problems finish). */
 typedef struct {
-    int32_t fused_sweeps;        /* chosen sweeps per launch (batch: 8) */
+    int32_t fused_sweeps;        /* chosen sweeps per launch (batch: 10) */
     int32_t seg_rows;            /* chosen segment / largest tile height (0 = automatic) */
     int32_t candidates;          /* configurations timed */
     double us_per_sweep;         /* device time per sweep of the whole grid / batch, chosen */

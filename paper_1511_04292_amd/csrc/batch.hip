@@ -26,7 +26,7 @@
 
 namespace srj {
 
-constexpr int kBatchT = 8;  // sweeps fused per launch
+constexpr int kBatchT = 10; // sweeps fused per launch
 constexpr int kBatchC = 2;  // columns per lane
 constexpr int kBatchD = 3;  // rows in flight per wave (the kernel then keeps 3 waves per SIMD
                              // with the edge-tile variants)
@@ -91,8 +91,10 @@ __device__ __forceinline__ void residual_tile(const BProb& P, int ucur, int dcur
     }
 }
 
+// As in the single-grid kernel, the 4- and 2-byte formats are held to 3 waves per SIMD.
 template <class S, int T, int C, int D>
-__global__ __launch_bounds__(256) void k_batch_step(const BProb* __restrict__ probs, BState* st, BRun run)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(S) == 8 ? 1 : 3)))
+void k_batch_step(const BProb* __restrict__ probs, BState* st, BRun run)
 {
     using Cm = typename Tr<S>::C;
     const int lane = threadIdx.x & 63;

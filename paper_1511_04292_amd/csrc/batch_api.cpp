@@ -380,7 +380,7 @@ srj_status srj_batch_tune(srj_batch_t b, srj_tune_info* info)
             result = report(SRJ_EHIP, "batch tuning upload failed");
             break;
         }
-        // 2 warm-up launches, then 6 timed (48 sweeps of every problem)
+        // 2 warm-up launches, then 6 timed (60 sweeps of every problem)
         bool ok = true;
         for (int it = 0; it < 8 && ok; ++it) {
             if (it == 2) ok = hipEventRecord(e0, s) == hipSuccess;

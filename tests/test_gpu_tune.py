@@ -61,7 +61,7 @@ def test_batch_tune_then_solve_bitwise():
         refs.append(sweeps.solve_ir(u0, f, h, np.asarray(w)[seq], 1e-10, 1, 400, "f32"))
     b = srj.srj_batch_plan(probs, dtype="f32")
     t = srj.srj_batch_tune(b)
-    assert t["fused_sweeps"] == 8 and t["seg_rows"] in (32, 64, 128, 256) and t["candidates"] >= 4
+    assert t["fused_sweeps"] == 10 and t["seg_rows"] in (32, 64, 128, 256) and t["candidates"] >= 4
     assert 0 < t["us_per_sweep"] <= t["us_per_sweep_before"]
     for rep in range(2):  # the tuned batch solves, twice, from the same inputs
         us = [torch.from_numpy(u0).to(DEV) for u0, _ in data]
