@@ -112,7 +112,7 @@ def test_fused_sweeps_bitwise(T, n):
     assert np.array_equal(host(ug), ref)
 
 
-@pytest.mark.parametrize("T,H", [(8, 8), (8, 13), (3, 100), (5, 1), (8, 512)])
+@pytest.mark.parametrize("T,H", [(8, 8), (8, 13), (3, 100), (5, 1), (8, 512), (10, 10), (10, 77), (9, 5), (10, 203)])
 def test_fused_segment_heights_bitwise(T, H):
     n = (300, 203)
     h = 1.0 / 301
@@ -125,6 +125,25 @@ def test_fused_segment_heights_bitwise(T, H):
     c = sweeps.coefficients(np.array(w)[seq], 2)
     ref = sweeps.run(u, sweeps.rhs(f, h), c, nsweeps)
     assert np.array_equal(host(ug), ref)
+
+
+def test_fused_stream_direction_alternates_without_changing_results():
+    """The plan alternates the stream direction of its segments from launch to launch; calls
+    that start on either parity give the oracle's iterate bit for bit."""
+    n = (257, 190)
+    h = 1.0 / 258
+    u, f = rand_case(n, 12)
+    w, q, seq = shared_schedule()
+    c = sweeps.coefficients(np.array(w)[seq], 2)
+    b = sweeps.rhs(f, h)
+    for first in (10, 20, 7):  # one, two or one partial launch before the second call
+        p = explicit_plan(n, h, w, q, seq, fuse=10, seg_rows=40)
+        ug = dev(u)
+        fg = dev(f)
+        srj.srj_sweeps(p, ug, fg, 0, first)
+        srj.srj_sweeps(p, ug, fg, first, 33)
+        ref = sweeps.run(u, b, c, first + 33)
+        assert np.array_equal(host(ug), ref), first
 
 
 @pytest.mark.parametrize("T", [1, 2, 3, 4])
