@@ -123,7 +123,7 @@ __global__ __launch_bounds__(k3Threads) void k_sweep3d_tb(const S* __restrict__ 
                 const Cm dn = xch[prev][l - 1][wd][0][lane];
                 const int p = k - l;
                 const bool pok = (p >= 1) & (p <= nz) & (l <= Tact);
-                Cm out[k3Rows];
+                Cm out[k3Rows], vs[k3Rows];
 #pragma unroll
                 for (int r = 0; r < k3Rows; ++r) {
                     const Cm m = w1[l - 1][r];
@@ -133,9 +133,14 @@ __global__ __launch_bounds__(k3Threads) void k_sweep3d_tb(const S* __restrict__ 
                     const Cm Nn = (r == k3Rows - 1) ? dn : w1[l - 1][r + 1];
                     const Cm sm = ((W + E) + (Sn + Nn)) + (w2[l - 1][r] + in[r]);
                     const Cm t = (sm + bq[l - 1][r]) - (Cm)6 * m;
-                    Cm v = Tr<S>::ld(Tr<S>::st(m + cf[l - 1] * t));
+                    vs[r] = m + cf[l - 1] * t;
+                }
+                tb_round<S>(vs);
+#pragma unroll
+                for (int r = 0; r < k3Rows; ++r) {
+                    Cm v = vs[r];
                     asm("" : "+v"(v));
-                    out[r] = (pok && updx && updy[r]) ? v : m;
+                    out[r] = (pok && updx && updy[r]) ? v : w1[l - 1][r];
                 }
 #pragma unroll
                 for (int r = 0; r < k3Rows; ++r) {

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "formats.h"
 
@@ -91,6 +92,26 @@ __device__ __forceinline__ void tb_ld_pair(const bf16_t* p, float& a, float& b)
 __device__ __forceinline__ double tb_sub4(double x, double m) { return __builtin_fma(-4.0, m, x); }
 __device__ __forceinline__ float tb_sub4(float x, float m) { return __builtin_fmaf(-4.0f, m, x); }
 
+// Each value rounded to the storage format and back (the level's result as a sweep stores
+// it).  BF16 rounds two values with one conversion instruction; the others are exact.
+typedef __bf16 tb_bf2 __attribute__((ext_vector_type(2)));
+template <class S, int N>
+__device__ __forceinline__ void tb_round(typename Tr<S>::C (&v)[N])
+{
+    if constexpr (std::is_same<S, bf16_t>::value && N % 2 == 0) {
+#pragma unroll
+        for (int i = 0; i < N; i += 2) {
+            const tb_f2 x = {v[i], v[i + 1]};
+            const uint32_t w = __builtin_bit_cast(uint32_t, __builtin_convertvector(x, tb_bf2));
+            v[i] = __uint_as_float(w << 16);
+            v[i + 1] = __uint_as_float(w & 0xffff0000u);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < N; ++i) v[i] = Tr<S>::ld(Tr<S>::st(v[i]));
+    }
+}
+
 // Largest segment height whose store window (H rows of pitch px plus one strip) keeps the
 // buffer record count below kTbMasked.
 inline int tb_max_rows(int64_t px, int esize)
@@ -145,6 +166,7 @@ __device__ __forceinline__ void tb_step(TbRegs<typename Tr<S>::C, T, C, D>& R, i
                 const int jv = rv - dv * l;
                 rowok = (jv >= 1) & (jv <= ny) & (l <= Tact);
             }
+            Cm vs[C];
 #pragma unroll
             for (int c = 0; c < C; ++c) {
                 const Cm W = (c == 0) ? wn : R.p1[l - 1][c - 1];
@@ -152,7 +174,13 @@ __device__ __forceinline__ void tb_step(TbRegs<typename Tr<S>::C, T, C, D>& R, i
                 const Cm m = R.p1[l - 1][c];
                 const Cm sm = (W + E) + (R.p2[l - 1][c] + in[c]);
                 const Cm t = tb_sub4(sm + R.bq[l - 1][c], m);
-                Cm v = Tr<S>::ld(Tr<S>::st(m + cf[l - 1] * t));
+                vs[c] = m + cf[l - 1] * t;
+            }
+            tb_round<S>(vs);
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const Cm m = R.p1[l - 1][c];
+                Cm v = vs[c];
                 if (MODE == TB_CLEAN) {
                     out[c] = v;
                 } else {
