@@ -24,6 +24,17 @@
 
 namespace srj {
 
+constexpr int k3_lcm(int a, int b)
+{
+    int x = a, y = b;
+    while (y) {
+        const int t = x % y;
+        x = y;
+        y = t;
+    }
+    return a / x * b;
+}
+
 template <int T> struct Coefs3T {
     double c[T];
 };
@@ -105,10 +116,16 @@ __global__ __launch_bounds__(k3Threads) void k_sweep3d_tb(const S* __restrict__ 
     for (int s = 0; s < D; ++s) load_plane(kb + s, U[s], B[s]);
 
     const int wu = max(w - 1, 0), wd = min(w + 1, k3Waves - 1);
-    for (int k0 = kb; k0 <= ke; k0 += D) {
+    // K steps per loop iteration, K a multiple of D (the load slots), 2 (the two older planes
+    // per level) and T (the delay line of b): every register then plays the same role at both
+    // ends of the loop body and the back edge needs no copies.  The last iteration may run up
+    // to K - 1 planes past ke: they are loaded clamped and never stored.
+    constexpr int K = k3_lcm(k3_lcm(D, 2), T);
+    for (int k0 = kb; k0 <= ke; k0 += K) {
 #pragma unroll
-        for (int s = 0; s < D; ++s) {
-            const int k = k0 + s;
+        for (int q = 0; q < K; ++q) {
+            const int s = q % D;
+            const int k = k0 + q;
             const int cur = k & 1, prev = cur ^ 1;
             Cm in[k3Rows];
 #pragma unroll
