@@ -121,7 +121,7 @@ void k_batch_step(const BProb* __restrict__ probs, BState* st, BRun run)
             for (int l = 0; l < T; ++l) cf[l] = (l < Tj) ? (Cm)run.coef[P.coff + (k + l) % P.M] : (Cm)0;
             // the stream direction alternates with the problem's launches, as in the
             // single-grid kernel
-            tb_tile<S, T, C, D, true>((const S*)P.d[dcur], (S*)P.d[1 - dcur], (const S*)P.rlo, P.px, P.nx, P.ny, cf,
+            tb_tile<S, T, C, D, true, false>((const S*)P.d[dcur], (S*)P.d[1 - dcur], (const S*)P.rlo, P.px, P.nx, P.ny, cf,
                                        Tj, sx, sg, P.H, (k / T) & 1);
         } else {
             double s, m;

@@ -112,6 +112,17 @@ __device__ __forceinline__ void tb_round(typename Tr<S>::C (&v)[N])
     }
 }
 
+constexpr int tb_lcm(int a, int b)
+{
+    int x = a, y = b;
+    while (y) {
+        const int t = x % y;
+        x = y;
+        y = t;
+    }
+    return a / x * b;
+}
+
 // Largest segment height whose store window (H rows of pitch px plus one strip) keeps the
 // buffer record count below kTbMasked.
 inline int tb_max_rows(int64_t px, int esize)
@@ -225,7 +236,7 @@ __device__ __forceinline__ void tb_step(TbRegs<typename Tr<S>::C, T, C, D>& R, i
 // are needed; the rest of the step loop is free of branches so that the D row loads in
 // flight (register slots named statically by unrolling the loop D times) overlap D steps
 // of arithmetic.  H * px * sizeof(S) must not exceed what tb_max_rows allows.
-template <class S, int T, int C, int D, int FILL, int STEADY>
+template <class S, int T, int C, int D, int FILL, int STEADY, bool WIDE>
 __device__ __forceinline__ void tb_tile_body(const S* __restrict__ uin, S* __restrict__ uout,
                                              const S* __restrict__ bb, int64_t px, int nx, int ny,
                                              const typename Tr<S>::C (&cf)[T], int Tact, int st, int sg, int H,
@@ -309,9 +320,26 @@ __device__ __forceinline__ void tb_tile_body(const S* __restrict__ uin, S* __res
         // waited for at the top of the next iteration
         __builtin_amdgcn_sched_barrier(0);
     }
-    // steady state: all levels, D steps per iteration (the last may run past rl: its rows
-    // are loaded clamped and never stored)
-    for (int i0 = F; i0 < nsteps; i0 += D) {
+    // steady state: all levels.  Binary64 at 10 levels (WIDE) runs K = lcm(D, 2) steps per
+    // iteration, so that the load slots and the two-row window rotate by renaming (b's delay
+    // line still needs copies at the back edge), then D steps per iteration for the rest;
+    // the other cases run D steps per iteration, which measured faster for them.  The last
+    // iteration may run past rl: its rows are loaded clamped and never stored.
+    constexpr int K = (WIDE && sizeof(S) == 8 && T >= 10) ? tb_lcm(D, 2) : D;
+    int i0 = F;
+    if constexpr (K != D) {
+        for (; i0 + K <= nsteps; i0 += K) {
+#pragma unroll
+            for (int q = 0; q < K; ++q) {
+                const int r = r_first + dir * (i0 + q);
+                tb_step<S, T, C, D, STEADY>(R, q % D, T, r, cf, upd, ny, Tact, y0, y1, rowbytes, lanebase, rs,
+                                            dir);
+                load_row(r + dir * D, R.U[q % D], R.B[q % D]);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    }
+    for (; i0 < nsteps; i0 += D) {
 #pragma unroll
         for (int s = 0; s < D; ++s) {
             const int r = r_first + dir * (i0 + s);
@@ -325,8 +353,10 @@ __device__ __forceinline__ void tb_tile_body(const S* __restrict__ uin, S* __res
 // EDGES: whether tiles on the grid's edges get their own variants (fill checked, steady
 // state checking columns only).  Each variant adds to the kernel's register count, which is
 // the maximum over all of them; callers whose kernel is already near a waves-per-SIMD step
-// use two variants only.
-template <class S, int T, int C, int D, bool EDGES = true>
+// use two variants only.  WIDE: whether binary64 at 10 levels may unroll its steady loop
+// over lcm(D, 2) steps (the batch kernel, which also holds the residual path, may not: it
+// would fall to one wave per SIMD).
+template <class S, int T, int C, int D, bool EDGES = true, bool WIDE = true>
 __device__ __forceinline__ void tb_tile(const S* __restrict__ uin, S* __restrict__ uout,
                                         const S* __restrict__ bb, int64_t px, int nx, int ny,
                                         const typename Tr<S>::C (&cf)[T], int Tact, int st, int sg, int H,
@@ -355,22 +385,22 @@ __device__ __forceinline__ void tb_tile(const S* __restrict__ uin, S* __restrict
         // binary64 below 10 levels keeps two variants: more would raise the kernel's register
         // count past three waves per SIMD at 8 levels (at 10 it holds two waves either way)
         if (Tact < T || top || bottom || cols)
-            tb_tile_body<S, T, C, D, TB_FULL, TB_FULL>(uin, uout, bb, px, nx, ny, cf, Tact, st, sg, H, dir);
+            tb_tile_body<S, T, C, D, TB_FULL, TB_FULL, WIDE>(uin, uout, bb, px, nx, ny, cf, Tact, st, sg, H, dir);
         else
-            tb_tile_body<S, T, C, D, TB_CLEAN, TB_CLEAN>(uin, uout, bb, px, nx, ny, cf, Tact, st, sg, H, dir);
+            tb_tile_body<S, T, C, D, TB_CLEAN, TB_CLEAN, WIDE>(uin, uout, bb, px, nx, ny, cf, Tact, st, sg, H, dir);
         return;
     }
     if (Tact < T || (top && bottom)) {
-        tb_tile_body<S, T, C, D, TB_FULL, TB_FULL>(uin, uout, bb, px, nx, ny, cf, Tact, st, sg, H, dir);
+        tb_tile_body<S, T, C, D, TB_FULL, TB_FULL, WIDE>(uin, uout, bb, px, nx, ny, cf, Tact, st, sg, H, dir);
     } else if (top || bottom) {
         if (cols)
-            tb_tile_body<S, T, C, D, TB_FULL, TB_COLS>(uin, uout, bb, px, nx, ny, cf, Tact, st, sg, H, dir);
+            tb_tile_body<S, T, C, D, TB_FULL, TB_COLS, WIDE>(uin, uout, bb, px, nx, ny, cf, Tact, st, sg, H, dir);
         else
-            tb_tile_body<S, T, C, D, TB_FULL, TB_CLEAN>(uin, uout, bb, px, nx, ny, cf, Tact, st, sg, H, dir);
+            tb_tile_body<S, T, C, D, TB_FULL, TB_CLEAN, WIDE>(uin, uout, bb, px, nx, ny, cf, Tact, st, sg, H, dir);
     } else if (cols) {
-        tb_tile_body<S, T, C, D, TB_COLS, TB_COLS>(uin, uout, bb, px, nx, ny, cf, Tact, st, sg, H, dir);
+        tb_tile_body<S, T, C, D, TB_COLS, TB_COLS, WIDE>(uin, uout, bb, px, nx, ny, cf, Tact, st, sg, H, dir);
     } else {
-        tb_tile_body<S, T, C, D, TB_CLEAN, TB_CLEAN>(uin, uout, bb, px, nx, ny, cf, Tact, st, sg, H, dir);
+        tb_tile_body<S, T, C, D, TB_CLEAN, TB_CLEAN, WIDE>(uin, uout, bb, px, nx, ny, cf, Tact, st, sg, H, dir);
     }
 }
 
