@@ -119,7 +119,7 @@ srj_status srj_plan_describe(srj_plan_t plan, srj_plan_desc* out);
 /* Copy the ordered level indices of one cycle (cap >= M) into seq. */
 srj_status srj_plan_sequence(srj_plan_t plan, int32_t* seq, int64_t cap);
 /* Override the number of sweeps fused per launch (0 = unfused reference kernel; at most
- * 10 in 2D, 4 in 3D; the default is the largest)
+ * 10 in 2D, 5 in 3D; the default is the largest, except 4 for binary64 in 3D)
  * and the output rows each wave of the fused 2D kernel computes (seg_rows = 0, the
  * default: chosen per launch so that the grid of waves fills the device's resident wave
  * slots once, from the kernel's occupancy and the number of compute units).  The results
@@ -198,7 +198,7 @@ void srj_batch_destroy(srj_batch_t batch);
  * chosen; only their speed changes.  Synchronises the plan's stream; takes milliseconds
  * to about a second for the largest grids.
  *   srj_plan_tune: 2D plans time fusion depths {10, 8, 6, 4} x segment heights {automatic,
- *     24, 32, 48, 64, 96, 128}; 3D plans fusion depths {4, 3, 2, 1, 0}.  Sets the plan's
+ *     24, 32, 48, 64, 96, 128}; 3D plans fusion depths {5, 4, 3, 2, 1, 0}.  Sets the plan's
  *     fusion (as srj_plan_set_fusion would).
  *   srj_batch_tune: times the batch's sweep launch with every problem sweeping, for
  *     largest tile heights {32, 64, 128, 256}, and keeps the fastest as the height the

@@ -363,7 +363,10 @@ srj_status srj_plan(const srj_grid* grid, const srj_schedule* schedule, void* st
         destroy(p);
         return fail(SRJ_EHIP, "initial fill failed");
     }
-    p->fuse = (g.ndim == 2) ? kMaxFuse : (fused3d_fits(g, p->fmt) ? kMaxFuse3d : 0);
+    // 3D: 5 sweeps per launch for the 4- and 2-byte formats, 4 for binary64 (at 5 its
+    // registers spill and the launch is slower per sweep)
+    p->fuse = (g.ndim == 2) ? kMaxFuse
+                            : (fused3d_fits(g, p->fmt) ? (p->fmt == FMT_F64 ? kMaxFuse3d - 1 : kMaxFuse3d) : 0);
     *out = p;
     return SRJ_OK;
 }
@@ -407,7 +410,7 @@ srj_status srj_plan_set_fusion(srj_plan_t p, int32_t fused, int32_t seg_rows)
 {
     if (!p) return fail(SRJ_EINVAL, "null plan");
     if (fused < 0 || fused > kMaxFuse) return fail(SRJ_EINVAL, "fusion depth must be in [0, 10]");
-    if (p->geo.ndim == 3 && fused > kMaxFuse3d) return fail(SRJ_EINVAL, "3D fusion depth must be in [0, 4]");
+    if (p->geo.ndim == 3 && fused > kMaxFuse3d) return fail(SRJ_EINVAL, "3D fusion depth must be in [0, 5]");
     if (p->geo.ndim == 3 && fused > 0 && !fused3d_fits(p->geo, p->fmt))
         return fail(SRJ_EINVAL, "z planes too large for the fused 3D kernel (1 GiB per plane at most)");
     if (seg_rows < 0 || seg_rows > (1 << 20)) return fail(SRJ_EINVAL, "segment rows must be in [0, 2^20]");
@@ -487,7 +490,7 @@ srj_status srj_plan_tune(srj_plan_t p, srj_tune_info* info)
             for (int H : {0, 24, 32, 48, 64, 96, 128}) cands.push_back({T, H});
     } else {
         if (fused3d_fits(p->geo, p->fmt))
-            for (int T : {4, 3, 2, 1}) cands.push_back({T, 0});
+            for (int T : {5, 4, 3, 2, 1}) cands.push_back({T, 0});
         cands.push_back({0, 0});
     }
     HIPCHK(launch_zero(p->fmt, p->A.origin, p->geo, p->stream));

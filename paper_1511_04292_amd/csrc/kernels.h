@@ -12,7 +12,7 @@ namespace srj {
 enum Fmt { FMT_F64 = 0, FMT_F32 = 1, FMT_BF16 = 2 };
 
 constexpr int kMaxFuse = 10;   // largest number of sweeps fused into one 2D launch
-constexpr int kMaxFuse3d = 4;  // largest number of sweeps fused into one 3D launch
+constexpr int kMaxFuse3d = 5;  // largest number of sweeps fused into one 3D launch
 
 struct Geo {
     int ndim;

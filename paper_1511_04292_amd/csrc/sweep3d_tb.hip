@@ -239,7 +239,8 @@ static void tb3d_TD(const S* in, S* out, const S* b, const Geo& g, const Coefs& 
     case 1: tb3d<S, 1, D>(in, out, b, g, co, 1, s); break;
     case 2: tb3d<S, 2, D>(in, out, b, g, co, 2, s); break;
     case 3: tb3d<S, 3, D>(in, out, b, g, co, 3, s); break;
-    default: tb3d<S, 4, D>(in, out, b, g, co, 4, s); break;
+    case 4: tb3d<S, 4, D>(in, out, b, g, co, 4, s); break;
+    default: tb3d<S, 5, D>(in, out, b, g, co, 5, s); break;
     }
 }
 

@@ -146,7 +146,7 @@ def test_fused_stream_direction_alternates_without_changing_results():
         assert np.array_equal(host(ug), ref), first
 
 
-@pytest.mark.parametrize("T", [1, 2, 3, 4])
+@pytest.mark.parametrize("T", [1, 2, 3, 4, 5])
 @pytest.mark.parametrize("n", [(70, 45, 33), (5, 7, 3), (130, 40, 9), (1, 1, 1), (64, 1, 20), (57, 37, 70)])
 def test_fused3d_sweeps_bitwise(T, n):
     """3D x-y tiles streamed in z, T sweeps per launch: bit-identical to the oracle's sweeps
@@ -360,7 +360,8 @@ def test_errors():
     ug[3, 3] = 7.0
     info = srj.srj_solve(p, ug, dev(z), 1e-10, 10)
     assert info["status"] == "ok" and info["sweeps"] == 0 and float(ug.abs().max()) == 0.0
-    # fusion depths: at most 10 in 2D (the default), 4 in 3D; segment heights non-negative
+    # fusion depths: at most 10 in 2D (the default), 5 in 3D (4 by default in binary64);
+    # segment heights non-negative
     assert srj.srj_plan_describe(p)["fused_sweeps"] == 10
     with pytest.raises(srj.SrjError) as e:
         srj.srj_plan_set_fusion(p, 11)
@@ -371,7 +372,7 @@ def test_errors():
     p3 = srj.srj_plan((6, 5, 4), 1.0 / 7, omega=[1.0], q=[1])
     assert srj.srj_plan_describe(p3)["fused_sweeps"] == 4
     with pytest.raises(srj.SrjError) as e:
-        srj.srj_plan_set_fusion(p3, 5)
+        srj.srj_plan_set_fusion(p3, 6)
     assert e.value.status == 1
     srj.srj_plan_set_fusion(p3, 0)
     assert srj.srj_plan_describe(p3)["fused_sweeps"] == 0

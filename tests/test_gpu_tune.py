@@ -35,7 +35,7 @@ def test_plan_tune_then_solve_bitwise(n, P):
     plan = srj.srj_plan(n, h, omega=w, q=q, sequence=seq)
     before = srj.srj_plan_describe(plan)["fused_sweeps"]
     t = srj.srj_plan_tune(plan)
-    assert t["candidates"] == (29 if len(n) == 2 else 6)
+    assert t["candidates"] == (29 if len(n) == 2 else 7)
     assert 0 < t["us_per_sweep"] <= t["us_per_sweep_before"]
     assert srj.srj_plan_describe(plan)["fused_sweeps"] == t["fused_sweeps"]
     assert before == (10 if len(n) == 2 else 4)
