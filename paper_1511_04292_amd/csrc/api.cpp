@@ -495,15 +495,17 @@ srj_status srj_plan_tune(srj_plan_t p, srj_tune_info* info)
     }
     HIPCHK(launch_zero(p->fmt, p->A.origin, p->geo, p->stream));
     HIPCHK(launch_zero(p->fmt, p->B.origin, p->geo, p->stream));
-    // device time per sweep of a configuration: 24 sweeps (whole launches at every depth),
-    // repeated until the timed run lasts about a millisecond
+    // device time per sweep of a configuration: a unit of sweeps that is a whole number of
+    // launches at every candidate depth (lcm of {10, 8, 6, 4} in 2D, of {5, 4, 3, 2, 1} in
+    // 3D), repeated until the timed run lasts about a millisecond
+    const int64_t unit = (p->geo.ndim == 2) ? 120 : 60;
     auto time_one = [&](const Cand& c, double* us) -> srj_status {
         p->fuse = c.T;
         p->seg_rows = c.H;
         DField *cur = &p->A, *nxt = &p->B;
-        srj_status st = run_sweeps(p, &cur, &nxt, p->blo.origin, 0, 24);  // warm-up
+        srj_status st = run_sweeps(p, &cur, &nxt, p->blo.origin, 0, unit);  // warm-up
         if (st != SRJ_OK) return st;
-        int64_t n = 24;
+        int64_t n = unit;
         for (int rep = 0; rep < 4; ++rep) {
             HIPCHK(hipEventRecord(p->ev0, p->stream));
             st = run_sweeps(p, &cur, &nxt, p->blo.origin, 0, n);
@@ -513,9 +515,9 @@ srj_status srj_plan_tune(srj_plan_t p, srj_tune_info* info)
             float ms = 0;
             HIPCHK(hipEventElapsedTime(&ms, p->ev0, p->ev1));
             *us = ms * 1e3 / (double)n;
-            if (ms >= 1.0f || n >= 24 * 64) break;
-            n = std::min<int64_t>(24 * 64, n * (int64_t)std::ceil(1.2 / std::max(ms, 0.01f)));
-            n = (n + 23) / 24 * 24;
+            if (ms >= 1.0f || n >= unit * 64) break;
+            n = std::min<int64_t>(unit * 64, n * (int64_t)std::ceil(1.2 / std::max(ms, 0.01f)));
+            n = (n + unit - 1) / unit * unit;
         }
         return SRJ_OK;
     };
