@@ -257,7 +257,7 @@ def test_product_planner_plan_solves_cfg_small():
 # ----------------------------------------------------------- reduced precision
 
 @pytest.mark.parametrize("fmt", ["f32", "bf16"])
-@pytest.mark.parametrize("fuse", [0, 5, 8])
+@pytest.mark.parametrize("fuse", [0, 5, 8, 10])
 def test_lowprec_sweeps_bitwise(fmt, fuse):
     n = (200, 131)
     h = 1.0 / 201
@@ -294,7 +294,7 @@ def test_ir_matches_oracle(fmt):
 
 
 @pytest.mark.parametrize("fmt", ["f32", "bf16"])
-@pytest.mark.parametrize("fuse", [0, 2, 4])
+@pytest.mark.parametrize("fuse", [0, 2, 4, 5])
 def test_lowprec_sweeps_3d_bitwise(fmt, fuse):
     n = (70, 37, 29)
     h = 1.0 / 71
