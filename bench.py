@@ -131,9 +131,10 @@ def measured_traffic(kernel, workload):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(wl, levels, sweeps_to_tol, seconds_target=15.0):
+def cpu_baseline(wl, levels, sweeps_to_tol, seconds_target=15.0, single_seconds=5.0):
     """The oracle (plain C loops, OpenMP over rows) timed on the host: its own schedule for
-    the same grid, a bounded number of sweeps of the full workload."""
+    the same grid, a bounded number of sweeps of the full workload, on all threads and on one
+    thread; and the 64^2 case (SRJ P = 2 and plain Jacobi) run to full convergence."""
     from oracle import _clib, sweeps
     from oracle import schedule as S
 
@@ -143,22 +144,52 @@ def cpu_baseline(wl, levels, sweeps_to_tol, seconds_target=15.0):
     seq_w = S.weight_sequence(o["w"], S.order_balanced(o["w"], q, km))
     b = sweeps.rhs(wl["f"], wl["h"])
     c = sweeps.coefficients(seq_w, len(wl["n"]))
-    u = wl["u0"].copy()
-    u = sweeps.run(u, b, c, 1)  # first touch
-    t0 = time.perf_counter()
-    u = sweeps.run(u, b, c, 3, k0=1)
-    t1 = (time.perf_counter() - t0) / 3
-    nsw = max(1, int(seconds_target / max(t1, 1e-6)))
-    t0 = time.perf_counter()
-    u = sweeps.run(u, b, c, nsw, k0=4)
-    dt = time.perf_counter() - t0
     pts = math.prod(wl["n"])
+
+    def timed(target):
+        u = wl["u0"].copy()
+        u = sweeps.run(u, b, c, 1)  # first touch
+        t0 = time.perf_counter()
+        u = sweeps.run(u, b, c, 3, k0=1)
+        t1 = (time.perf_counter() - t0) / 3
+        nsw = max(1, int(target / max(t1, 1e-6)))
+        t0 = time.perf_counter()
+        sweeps.run(u, b, c, nsw, k0=4)
+        return nsw, time.perf_counter() - t0
+
+    threads = _clib.max_threads()
+    nsw, dt = timed(seconds_target)
     rate = pts * nsw / dt
-    return {"value": round(rate / 1e9, 4), "unit": "GLUP/s", "cores": _clib.max_threads(),
-            "kind": "oracle",
-            "sample": f"{nsw} scheduled FP64 sweeps of the full {'x'.join(map(str, wl['n']))} grid "
-                      f"({dt:.1f} s timed); time-to-tolerance extrapolated to {sweeps_to_tol} sweeps: "
-                      f"{sweeps_to_tol * pts / rate:.0f} s"}
+    prev = _clib.set_threads(1)
+    try:
+        nsw1, dt1 = timed(single_seconds)
+    finally:
+        _clib.set_threads(prev)
+    rate1 = pts * nsw1 / dt1
+    out = {"value": round(rate / 1e9, 4), "unit": "GLUP/s", "cores": threads, "kind": "oracle",
+           "sample": f"{nsw} scheduled FP64 sweeps of the full {'x'.join(map(str, wl['n']))} grid "
+                     f"({dt:.1f} s timed, {threads} threads); time-to-tolerance extrapolated to "
+                     f"{sweeps_to_tol} sweeps: {sweeps_to_tol * pts / rate:.0f} s",
+           "single_thread": {"value": round(rate1 / 1e9, 4), "unit": "GLUP/s", "cores": 1,
+                             "sample": f"{nsw1} sweeps of the same grid ({dt1:.1f} s timed); "
+                                       f"time-to-tolerance extrapolated: {sweeps_to_tol * pts / rate1:.0f} s"}}
+    # 64^2: SRJ P = 2 (the oracle's schedule for the grid) and Jacobi to relres 1e-10
+    from paper_1511_04292_amd import workloads
+
+    w1 = workloads.small_2d(64, seed=0)
+    km1 = S.kappa_min_dirichlet(w1["n"])
+    o1 = S.optimal(2, km1)
+    q1 = S.q_floor(o1["beta"])
+    wseq1 = S.weight_sequence(o1["w"], S.order_balanced(o1["w"], q1, km1))
+    small = {}
+    for name, ws in (("srj_P2", wseq1), ("jacobi", [1.0])):
+        t0 = time.perf_counter()
+        r = sweeps.solve(w1["u0"], w1["f"], w1["h"], ws, 1e-10, 10 ** 7)
+        small[name] = {"seconds": round(time.perf_counter() - t0, 3), "sweeps": int(r["sweeps"]),
+                       "relres": r["relres"], "status": r["status"]}
+    small["measured_acceleration"] = round(small["jacobi"]["sweeps"] / max(1, small["srj_P2"]["sweeps"]), 3)
+    out["small_2d_64"] = small
+    return out
 
 
 def main():
@@ -336,7 +367,8 @@ def main():
         del plan, u, u0, f
         torch.cuda.empty_cache()
         other = {}
-        for name, fn in (("smooth3d_512", bench_3d), ("batch_1024", bench_batch), ("adjoint_2048", bench_adjoint)):
+        for name, fn in (("small_2d_64", bench_small_2d), ("smooth3d_512", bench_3d), ("batch_1024", bench_batch),
+                         ("adjoint_2048", bench_adjoint), ("huge_2d_32768", bench_huge_2d)):
             print(f"bench: {name} ...", file=sys.stderr, flush=True)
             other[name] = fn(torch, srj, workloads)
             torch.cuda.empty_cache()
@@ -344,11 +376,51 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def exact_dirichlet(u_ring, f, h):
+    """Exact solution of the discrete Dirichlet problem A u = h^2 f + (ring terms): the
+    5-/7-point Laplacian is diagonalised by the type-I DST along every axis, with eigenvalues
+    sum_i 4 sin^2(k_i pi / (2 (n_i + 1))).  Host binary64 (scipy), all threads."""
+    import numpy as np
+    import scipy.fft
+
+    nd = f.ndim
+    inner = tuple(slice(1, -1) for _ in range(nd))
+    rhs = (float(h) * float(h)) * f[inner]
+    g = np.array(u_ring, copy=True)
+    g[inner] = 0.0
+    for ax in range(nd):
+        lo = [slice(1, -1)] * nd
+        hi = [slice(1, -1)] * nd
+        lo[ax] = slice(0, -2)
+        hi[ax] = slice(2, None)
+        rhs = rhs + g[tuple(lo)] + g[tuple(hi)]
+    lam = np.zeros(rhs.shape)
+    for ax, m in enumerate(rhs.shape):
+        k = np.arange(1, m + 1, dtype=np.float64)
+        shp = [1] * nd
+        shp[ax] = m
+        lam = lam + (4.0 * np.sin(k * np.pi / (2.0 * (m + 1))) ** 2).reshape(shp)
+    t = scipy.fft.dstn(rhs, type=1, norm="ortho", workers=-1)
+    del rhs
+    t /= lam
+    del lam
+    u = np.array(u_ring, copy=True)
+    u[inner] = scipy.fft.dstn(t, type=1, norm="ortho", workers=-1)
+    return u
+
+
 def bench_3d(torch, srj, workloads, n=512, levels=8, tol=1e-10):
-    """512^3 Poisson, P = 8: FP64 SRJ, and FP64 refinement around FP32 and BF16-storage sweeps."""
+    """512^3 Poisson, P = 8: FP64 SRJ, and FP64 refinement around FP32 and BF16-storage sweeps.
+    Each result is compared with the exact discrete solution (DST-I, host binary64)."""
+    import numpy as np
+
     wl = workloads.smooth_3d(n, seed=0)
     u0 = torch.from_numpy(wl["u0"]).to("cuda:0")
     f = torch.from_numpy(wl["f"]).to("cuda:0")
+    t0 = time.perf_counter()
+    ustar = exact_dirichlet(wl["u0"], wl["f"], wl["h"])
+    t_exact = time.perf_counter() - t0
+    ustar_max = float(np.max(np.abs(ustar)))
     del wl
     pts = n ** 3
     res = {"workload": f"3D Poisson {n}^3 interior, 7-point, zero Dirichlet ring, f = U(-1,1) smoothed once, "
@@ -381,15 +453,88 @@ def bench_3d(torch, srj, workloads, n=512, levels=8, tol=1e-10):
              "launch_algorithmic_GBs": round(bpp * pts / launch_s / 1e9, 1),
              # effective sweep rate over the unfused sweep's HBM roofline (8 TB/s / bytes per update)
              "per_sweep_hbm_roofline_frac": round(pts / per_sweep / (HBM_PEAK_GBS * 1e9 / bpp), 3)}
+        # max |u - u*| / max |u*| against the exact discrete solution
+        r["err_vs_exact"] = float(np.max(np.abs(u.cpu().numpy() - ustar))) / ustar_max
         if fmt == "f64":
             ref = u
             r["M"] = int(srj.srj_plan_describe(plan)["M"])
         else:
-            r["max_abs_err_vs_f64_rel"] = float((u - ref).abs().max() / ref.abs().max())
+            r["max_abs_err_vs_f64_gpu_rel"] = float((u - ref).abs().max() / ref.abs().max())
             del u
         res[fmt if fmt == "f64" else f"{fmt}_refined"] = r
         del plan
+    res["exact_reference"] = (f"u* from the type-I DST of the discrete problem on the host "
+                              f"({t_exact:.1f} s); err_vs_exact = max|u - u*| / max|u*|")
     return res
+
+
+def bench_small_2d(torch, srj, workloads, n=64, tol=1e-10):
+    """64^2 Poisson (manufactured sin-sin source plus N(0, 1e-3^2) noise, zero ring): SRJ with
+    the P = 2 schedule the product planner builds for the grid, against plain Jacobi (one
+    weight 1, checked after every sweep), both to relres 1e-10 on the GPU.  The measured
+    acceleration (Jacobi sweeps / SRJ sweeps) is reported beside the schedule's rho (Eq. rho)
+    and the rate ratio log(Gamma_q) / log(1 - kappa_min) of the slowest mode."""
+    wl = workloads.small_2d(n, seed=0)
+    u0 = torch.from_numpy(wl["u0"]).to("cuda:0")
+    f = torch.from_numpy(wl["f"]).to("cuda:0")
+    out = {"workload": f"2D Poisson {n}x{n}, zero ring, f = 2 pi^2 sin sin + N(0, 1e-3^2), tol {tol:g}"}
+    plans = {"srj_P2": srj.srj_plan(wl["n"], wl["h"], P=2),
+             "jacobi": srj.srj_plan(wl["n"], wl["h"], omega=[1.0], q=[1])}
+    for name, plan in plans.items():
+        d = srj.srj_plan_describe(plan)
+        u = u0.clone()
+        srj.srj_solve(plan, u, f, tol, 10 ** 7)  # warm
+        u = u0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = srj.srj_solve(plan, u, f, tol, 10 ** 7)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[name] = {"seconds": round(dt, 5), "sweeps": int(info["sweeps"]), "relres": info["relres"],
+                     "status": info["status"], "device_seconds": round(info["seconds"], 5),
+                     "omega": [float(x) for x in d["omega"]], "q": [int(x) for x in d["q"]], "M": int(d["M"])}
+        if name == "srj_P2":
+            out[name]["rho"] = d["rho"]
+            out[name]["gamma_q_max"] = d["gamma_q_max"]
+            km = d["kappa_min"]
+    out["measured_acceleration"] = round(out["jacobi"]["sweeps"] / max(1, out["srj_P2"]["sweeps"]), 3)
+    out["predicted_acceleration_slowest_mode"] = round(
+        math.log(out["srj_P2"]["gamma_q_max"]) / math.log(1.0 - km), 3)
+    out["time_ratio_jacobi_over_srj"] = round(out["jacobi"]["seconds"] / out["srj_P2"]["seconds"], 3)
+    return out
+
+
+def bench_huge_2d(torch, srj, workloads, n=32768, levels=10, nsweeps=1000):
+    """Throughput at 2^15 points per axis: 32768^2 binary64 (8.6 GB per field), the P = 10
+    schedule for the grid, a fixed window of scheduled sweeps from the start of a cycle
+    (2 full cycles would take minutes; the rate per sweep does not depend on the position in
+    the cycle).  Inputs drawn on the device (workloads.blobs_2d_device)."""
+    wl = workloads.blobs_2d_device(n, seed=0, device="cuda:0")
+    u0, f = wl["u0"], wl["f"]
+    t0 = time.perf_counter()
+    plan = srj.srj_plan(wl["n"], wl["h"], P=levels)
+    t_plan = time.perf_counter() - t0
+    d = srj.srj_plan_describe(plan)
+    fuse = int(d["fused_sweeps"])
+    u = u0.clone()
+    srj.srj_sweeps(plan, u, f, 0, 10 * fuse)  # warm
+    u.copy_(u0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sec, launches = srj.srj_sweeps(plan, u, f, 0, nsweeps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    pts = n * n
+    launch_s = sec / launches
+    return {"workload": f"2D Poisson {n}x{n}, Dirichlet ring U(-1,1), 32 Gaussian blobs, SRJ P={levels} "
+                        f"(M={int(d['M'])}), binary64, {nsweeps} sweeps timed",
+            "GLUP_s": round(pts * nsweeps / sec / 1e9, 1), "device_seconds": round(sec, 4),
+            "wall_seconds_incl_copies": round(wall, 4), "launches": int(launches), "fused_sweeps": fuse,
+            "launch_us": round(launch_s * 1e6, 1),
+            "launch_algorithmic_GBs": round(B_PER_POINT_F64 * pts / launch_s / 1e9, 1),
+            "launch_hbm_frac": round(B_PER_POINT_F64 * pts / launch_s / 1e9 / HBM_PEAK_GBS, 4),
+            "M": int(d["M"]), "two_cycles_estimate_s": round(2 * int(d["M"]) * sec / nsweeps, 1),
+            "plan_seconds": round(t_plan, 2)}
 
 
 def bench_batch(torch, srj, workloads, count=1024, tol=1e-10):

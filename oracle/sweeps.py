@@ -197,7 +197,10 @@ def from_bf16_bits(h):
 
 
 def sweep_lo(u, b, c32, fmt):
-    """One step in binary32 arithmetic; storage binary32 ('f32') or bfloat16 bits ('bf16')."""
+    """One step in binary32 arithmetic; storage binary32 ('f32') or bfloat16 bits ('bf16').
+    'f64' is the binary64 step itself (refinement with binary64 inner sweeps)."""
+    if fmt == "f64":
+        return sweep(u, b, c32)
     L = lib()
     d = _dims(u)
     out = u.copy()
@@ -216,19 +219,24 @@ def sweep_lo(u, b, c32, fmt):
     return out
 
 
-def lo_coefficients(omega_sequence, ndim):
-    """binary32 coefficients: the FP64 c_k rounded once to binary32."""
-    return coefficients(omega_sequence, ndim).astype(np.float32)
+def lo_coefficients(omega_sequence, ndim, fmt="f32"):
+    """Coefficients of the sweep format: the FP64 c_k, rounded once to binary32 unless the
+    format is 'f64'."""
+    c = coefficients(omega_sequence, ndim)
+    return c if fmt == "f64" else c.astype(np.float32)
 
 
 def lo_cast(x64, fmt):
-    """FP64 -> storage format: binary32 rounding, then (bf16) a second rounding to bfloat16."""
+    """FP64 -> storage format: binary32 rounding, then (bf16) a second rounding to bfloat16;
+    'f64' is a copy."""
+    if fmt == "f64":
+        return np.array(x64, dtype=np.float64, copy=True)
     x32 = np.ascontiguousarray(x64, dtype=np.float32)
     return x32 if fmt == "f32" else to_bf16_bits(x32)
 
 
 def lo_widen(x, fmt):
-    return (x if fmt == "f32" else from_bf16_bits(x)).astype(np.float64)
+    return (x if fmt in ("f32", "f64") else from_bf16_bits(x)).astype(np.float64)
 
 
 def solve_ir(u0, f, h, omega_sequence, tol, inner_cycles, max_outer, fmt):
@@ -237,11 +245,12 @@ def solve_ir(u0, f, h, omega_sequence, tol, inner_cycles, max_outer, fmt):
     Outer step: r = b - A u in FP64; stop if ||r|| / ||b~|| <= tol; otherwise solve
     A d = r approximately by ``inner_cycles`` SRJ cycles from d = 0 with a zero ring,
     in binary32 arithmetic on ``fmt`` storage (r cast to that storage first), then
-    u += d in FP64.  Parity unpinned beyond the FP64 residual it reports.
+    u += d in FP64.  ``fmt`` 'f64' runs the same loop with binary64 inner sweeps.
+    Parity unpinned beyond the FP64 residual it reports.
     """
     u = _c64(u0).copy()
     b = rhs(f, h)
-    c32 = lo_coefficients(omega_sequence, u.ndim)
+    c32 = lo_coefficients(omega_sequence, u.ndim, fmt)
     M = len(c32)
     bt2 = source_norm2(u, b)
     inner = tuple(slice(1, -1) for _ in range(u.ndim))

@@ -70,8 +70,9 @@ struct srj_plan_s {
     uint32_t fused_launches = 0;  // 2D launches so far: their parity alternates the stream direction
 
     // device buffers
-    DField A, B, blo, b64f;  // iterate pair, b in the sweep format, FP64 b (low-precision plans)
-    double* b64 = nullptr;   // FP64 b: blo itself for FP64 plans, else b64f
+    DField A, B, blo;  // iterate pair, b (or the refinement's inner right-hand side) in the sweep format
+    DField b64f, x64;  // binary64 b, and the binary64 iterate of refinement / residual evaluation
+    double* b64 = nullptr;  // b64f.origin
     double* partials = nullptr;
     double* dres = nullptr;   // device {sum, max}
     double* hres = nullptr;   // pinned host copy
@@ -170,6 +171,7 @@ void destroy(srj_plan_t p)
     free_field(&p->B);
     free_field(&p->blo);
     free_field(&p->b64f);
+    free_field(&p->x64);
     if (p->partials) (void)hipFree(p->partials);
     if (p->dres) (void)hipFree(p->dres);
     if (p->hres) (void)hipHostFree(p->hres);
@@ -341,15 +343,13 @@ srj_status srj_plan(const srj_grid* grid, const srj_schedule* schedule, void* st
         destroy(p);
         return st;
     }
-    if (p->fmt == FMT_F64) {
-        p->b64 = (double*)p->blo.origin;
-    } else {
-        if ((st = alloc_field(p, FMT_F64, &p->b64f)) != SRJ_OK) {
-            destroy(p);
-            return st;
-        }
-        p->b64 = (double*)p->b64f.origin;
+    // binary64 b and iterate, separate from the sweep fields in every format: refinement
+    // writes its inner right-hand side into blo while b64 keeps b
+    if ((st = alloc_field(p, FMT_F64, &p->b64f)) != SRJ_OK || (st = alloc_field(p, FMT_F64, &p->x64)) != SRJ_OK) {
+        destroy(p);
+        return st;
     }
+    p->b64 = (double*)p->b64f.origin;
     const int nb = residual_blocks(g);
     if (hipMalloc(&p->partials, sizeof(double) * 2 * (size_t)nb) != hipSuccess ||
         hipMalloc(&p->dres, sizeof(double) * 4) != hipSuccess ||
@@ -359,7 +359,8 @@ srj_status srj_plan(const srj_grid* grid, const srj_schedule* schedule, void* st
         return fail(SRJ_ENOMEM, "allocation of reduction scratch failed");
     }
     if (launch_zero(p->fmt, p->blo.origin, g, p->stream) != hipSuccess ||
-        (p->fmt != FMT_F64 && launch_zero(FMT_F64, p->b64, g, p->stream) != hipSuccess)) {
+        launch_zero(FMT_F64, p->b64, g, p->stream) != hipSuccess ||
+        launch_zero(FMT_F64, p->x64.origin, g, p->stream) != hipSuccess) {
         destroy(p);
         return fail(SRJ_EHIP, "initial fill failed");
     }
@@ -424,27 +425,13 @@ srj_status srj_residual(srj_plan_t p, const double* u, const double* f, double* 
     if (!p || !u || !f || !norms) return fail(SRJ_EINVAL, "null argument");
     const double hh = p->grid.h * p->grid.h;
     srj_status st;
-    DField uf, rf;
-    struct Guard {
-        DField *a, *b;
-        ~Guard() { free_field(a); free_field(b); }
-    } guard{&uf, &rf};
-    if ((st = alloc_field(p, FMT_F64, &uf)) != SRJ_OK) return st;
-    HIPCHK(launch_copy_in(FMT_F64, u, uf.origin, p->geo, p->stream));
-    HIPCHK(launch_rhs(p->fmt, f, hh, p->blo.origin, p->fmt == FMT_F64 ? nullptr : p->b64, p->geo, p->stream));
+    // u goes to the plan's binary64 iterate field; b to b64 (and blo, as a solve would)
+    HIPCHK(launch_copy_in(FMT_F64, u, p->x64.origin, p->geo, p->stream));
+    HIPCHK(launch_rhs(p->fmt, f, hh, p->blo.origin, p->b64, p->geo, p->stream));
     double s0, m0, s1, m1;
-    if ((st = residual_now(p, uf.origin, FMT_F64, 1, &s0, &m0)) != SRJ_OK) return st;
-    if (r_out) {
-        if ((st = alloc_field(p, FMT_F64, &rf)) != SRJ_OK) return st;
-        HIPCHK(launch_zero(FMT_F64, rf.origin, p->geo, p->stream));
-        HIPCHK(launch_residual_to_lo(FMT_F64, (const double*)uf.origin, p->b64, rf.origin, p->geo, p->partials,
-                                     p->dres, p->stream));
-        const size_t user_elems =
-            (size_t)((p->geo.ndim == 3 ? p->geo.nz + 2 : 1) * p->geo.py * (p->geo.nx + 2));
-        HIPCHK(hipMemsetAsync(r_out, 0, sizeof(double) * user_elems, p->stream));
-        HIPCHK(launch_copy_out(FMT_F64, rf.origin, r_out, p->geo, p->stream));
-    }
-    if ((st = residual_now(p, uf.origin, FMT_F64, 0, &s1, &m1)) != SRJ_OK) return st;
+    if ((st = residual_now(p, p->x64.origin, FMT_F64, 1, &s0, &m0)) != SRJ_OK) return st;
+    if (r_out) HIPCHK(launch_residual_out((const double*)p->x64.origin, p->b64, r_out, p->geo, p->stream));
+    if ((st = residual_now(p, p->x64.origin, FMT_F64, 0, &s1, &m1)) != SRJ_OK) return st;
     norms[0] = std::sqrt(s1);
     norms[1] = m1;
     norms[2] = std::sqrt(s0);
@@ -459,7 +446,7 @@ srj_status srj_sweeps(srj_plan_t p, double* u, const double* f, int64_t k0, int6
     const double hh = p->grid.h * p->grid.h;
     HIPCHK(launch_copy_in(p->fmt, u, p->A.origin, p->geo, p->stream));
     HIPCHK(launch_copy_in(p->fmt, u, p->B.origin, p->geo, p->stream));
-    HIPCHK(launch_rhs(p->fmt, f, hh, p->blo.origin, p->fmt == FMT_F64 ? nullptr : p->b64, p->geo, p->stream));
+    HIPCHK(launch_rhs(p->fmt, f, hh, p->blo.origin, p->b64, p->geo, p->stream));
     DField *cur = &p->A, *nxt = &p->B;
     int64_t launches = 0;
     HIPCHK(hipEventRecord(p->ev0, p->stream));
@@ -563,7 +550,7 @@ srj_status srj_solve(srj_plan_t p, double* u, const double* f, double tol, int64
     HIPCHK(hipEventRecord(p->ev0, p->stream));
     HIPCHK(launch_copy_in(p->fmt, u, p->A.origin, p->geo, p->stream));
     HIPCHK(launch_copy_in(p->fmt, u, p->B.origin, p->geo, p->stream));
-    HIPCHK(launch_rhs(p->fmt, f, hh, p->blo.origin, p->fmt == FMT_F64 ? nullptr : p->b64, p->geo, p->stream));
+    HIPCHK(launch_rhs(p->fmt, f, hh, p->blo.origin, p->b64, p->geo, p->stream));
     DField* cur = nullptr;
     int64_t k = 0, cycles = 0;
     double rr = 0;
@@ -585,7 +572,7 @@ srj_status srj_adjoint(srj_plan_t p, const double* grad_u, double tol, int64_t m
     HIPCHK(launch_zero(p->fmt, p->A.origin, p->geo, p->stream));
     HIPCHK(launch_zero(p->fmt, p->B.origin, p->geo, p->stream));
     // right-hand side taken as given: b = 1.0 * grad_u exactly
-    HIPCHK(launch_rhs(p->fmt, grad_u, 1.0, p->blo.origin, nullptr, p->geo, p->stream));
+    HIPCHK(launch_rhs(p->fmt, grad_u, 1.0, p->blo.origin, p->b64, p->geo, p->stream));
     DField* cur = nullptr;
     int64_t k = 0, cycles = 0;
     double rr = 0;
@@ -606,14 +593,9 @@ srj_status srj_solve_ir(srj_plan_t p, double* u, const double* f, double tol, in
     if (!(tol >= 0) || inner_cycles < 1 || max_outer < 0) return fail(SRJ_EINVAL, "bad IR parameters");
     const double hh = p->grid.h * p->grid.h;
     srj_status st;
-    // the FP64 iterate lives in its own field; the plan's A/B hold the correction d and blo
-    // the low-precision residual
-    DField u64;
-    if ((st = alloc_field(p, FMT_F64, &u64)) != SRJ_OK) return st;
-    struct Guard {
-        DField* f;
-        ~Guard() { free_field(f); }
-    } guard{&u64};
+    // the binary64 iterate lives in the plan's x64 field, b in b64; A/B hold the correction d
+    // and blo the inner right-hand side (the residual in the sweep format)
+    DField& u64 = p->x64;
     HIPCHK(hipEventRecord(p->ev0, p->stream));
     HIPCHK(launch_copy_in(FMT_F64, u, u64.origin, p->geo, p->stream));
     HIPCHK(launch_rhs(FMT_F64, f, hh, nullptr, p->b64, p->geo, p->stream));

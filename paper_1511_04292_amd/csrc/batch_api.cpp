@@ -41,13 +41,8 @@ constexpr int64_t kAlign = 512;
 // still gives the running problems at least `tiles_target` tiles, so that launches stay wide
 // while many problems run and become short once few remain.
 constexpr int kHmin = 16;
-
-int env_int(const char* name, int dflt, int lo, int hi)
-{
-    const char* e = std::getenv(name);
-    const int v = e ? std::atoi(e) : dflt;
-    return std::max(lo, std::min(v, hi));
-}
+constexpr int kHmaxDefault = 128;  // largest tile height before tuning
+constexpr int kTilesTarget = 4096;  // tiles a work list aims for
 
 int tiles_of(const Geo& g, int strip_w, int H)
 {
@@ -205,7 +200,7 @@ srj_status srj_batch_plan(int32_t count, const srj_grid* grids, const srj_schedu
     if (!b) return report(SRJ_ENOMEM, "host allocation failed");
     b->count = count;
     b->fmt = (Fmt)dt;
-    b->hmax = env_int("SRJ_BATCH_H", 128, kHmin, 1 << 20);
+    b->hmax = kHmaxDefault;
     b->user_stream = (hipStream_t)stream;
     b->grids.assign(grids, grids + count);
     // schedules, in parallel host threads
@@ -471,7 +466,7 @@ srj_status srj_batch_solve(srj_batch_t b, double* const* u, const double* const*
     const int T = batch_fuse();
     const int SW = 128 - 2 * T;
     const int hmax = b->hmax;
-    const int tiles_target = env_int("SRJ_BATCH_TILES", 4096, 1, 1 << 30);
+    const int tiles_target = kTilesTarget;
     std::vector<BItem> items;
     items.reserve(b->nitems);
     auto running = [](const BState& x) { return x.phase == BP_SWEEP || x.phase == BP_RESIDUAL; };

@@ -58,6 +58,8 @@ hipError_t launch_residual(Fmt f, const void* u, const double* b64, const Geo& g
 // IR: r = b64 - A u64 (binary64) written to rlo in format f, with its norms (as above).
 hipError_t launch_residual_to_lo(Fmt f, const double* u64, const double* b64, void* rlo,
                                  const Geo& g, double* partials, double* result, hipStream_t s);
+// r = b64 - A u64 (binary64) into a user array (dense layout, ring included, ring set to 0)
+hipError_t launch_residual_out(const double* u64, const double* b64, double* r_user, const Geo& g, hipStream_t s);
 // IR: u64 interior += widen(d)
 hipError_t launch_update(Fmt f, double* u64, const void* d, const Geo& g, hipStream_t s);
 // adjoint outputs from the FP64 field lam: user df = hh * lam (interior, ring 0) and user

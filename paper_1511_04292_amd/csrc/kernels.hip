@@ -16,7 +16,6 @@
 
 #include <algorithm>
 #include <cstdint>
-#include <cstdlib>
 
 #include "formats.h"
 #include "tb_core.h"
@@ -267,6 +266,26 @@ __global__ __launch_bounds__(256) void k_residual_to_lo(const double* __restrict
     }
 }
 
+// r = b64 - A u (binary64) written to a user array (dense layout, ring included) with 0 on
+// the ring; one thread per user element.
+__global__ __launch_bounds__(256) void k_residual_out(const double* __restrict__ u, const double* __restrict__ b64,
+                                                      double* __restrict__ r, Geo g)
+{
+    const int64_t nxw = g.nx + 2, nyw = g.ny + 2, nzw = (g.ndim == 3 ? g.nz + 2 : 1);
+    const int64_t n = nxw * nyw * nzw;
+    const int64_t pl = g.px * g.py;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int j = (int)(idx % nxw);
+        const int64_t t = idx / nxw;
+        const int i = (int)(t % nyw);
+        const int k = (g.ndim == 3) ? (int)(t / nyw) : 0;
+        const bool inside = j >= 1 && j <= g.nx && i >= 1 && i <= g.ny && (g.ndim != 3 || (k >= 1 && k <= g.nz));
+        r[idx] = inside ? res_at(u, b64, (int64_t)k * pl + (int64_t)i * g.px + j, g.px, pl, g.ndim, i, j, k, g, false)
+                        : 0.0;
+    }
+}
+
 // Deterministic final reduction: thread t folds partials t, t+256, ... in order.
 __global__ __launch_bounds__(256) void k_reduce_final(const double* __restrict__ partials, int n,
                                                       double* __restrict__ result)
@@ -337,12 +356,6 @@ __global__ __launch_bounds__(256) void k_adjoint_out(const double* __restrict__ 
 
 // ------------------------------------------------------------------ launchers
 
-static int env_int(const char* name, int dflt)
-{
-    const char* v = getenv(name);
-    return v ? atoi(v) : dflt;
-}
-
 static dim3 grid1d(int64_t n)
 {
     int64_t b = (n + 255) / 256;
@@ -391,24 +404,15 @@ hipError_t launch_sweep_unfused(Fmt f, const void* in, void* out, const void* b,
         SRJ_DISPATCH(f, hipLaunchKernelGGL(k_sweep2d<S>, grid, dim3(64, 4), 0, s, (const S*)in, (S*)out,
                                            (const S*)b, g.px, (int)g.nx, (int)g.ny, c));
     } else {
-        static const int zrun_knob = env_int("SRJ_3D_ZRUN", 32);
-        static const int by = std::min(16, std::max(1, env_int("SRJ_3D_BY", 4)));
-        static const int pf = env_int("SRJ_3D_PREFETCH", 2);
-        // the run's byte offsets (plus D planes of overshoot) stay below 2^31
+        // 64 x 4 threads per block, runs of 32 z planes, 2 planes loaded ahead
+        constexpr int kZrun = 32, kBy = 4;
+        // the run's byte offsets (plus the planes loaded ahead) stay below 2^31
         const int64_t zmax = ((int64_t)1 << 31) / ((int64_t)fmt_size(f) * g.px * g.py) - 6;
-        const int zrun = (int)std::max<int64_t>(1, std::min<int64_t>(zrun_knob, zmax));
-        dim3 grid((unsigned)((g.nx + 63) / 64), (unsigned)((g.ny + by - 1) / by), (unsigned)((g.nz + zrun - 1) / zrun));
-        dim3 blk(64, by);
-        if (pf <= 1) {
-            SRJ_DISPATCH(f, hipLaunchKernelGGL((k_sweep3d<S, 1>), grid, blk, 0, s, (const S*)in, (S*)out, (const S*)b,
-                                               g.px, g.py, (int)g.nx, (int)g.ny, (int)g.nz, zrun, c));
-        } else if (pf == 2) {
-            SRJ_DISPATCH(f, hipLaunchKernelGGL((k_sweep3d<S, 2>), grid, blk, 0, s, (const S*)in, (S*)out, (const S*)b,
-                                               g.px, g.py, (int)g.nx, (int)g.ny, (int)g.nz, zrun, c));
-        } else {
-            SRJ_DISPATCH(f, hipLaunchKernelGGL((k_sweep3d<S, 4>), grid, blk, 0, s, (const S*)in, (S*)out, (const S*)b,
-                                               g.px, g.py, (int)g.nx, (int)g.ny, (int)g.nz, zrun, c));
-        }
+        const int zrun = (int)std::max<int64_t>(1, std::min<int64_t>(kZrun, zmax));
+        dim3 grid((unsigned)((g.nx + 63) / 64), (unsigned)((g.ny + kBy - 1) / kBy), (unsigned)((g.nz + zrun - 1) / zrun));
+        dim3 blk(64, kBy);
+        SRJ_DISPATCH(f, hipLaunchKernelGGL((k_sweep3d<S, 2>), grid, blk, 0, s, (const S*)in, (S*)out, (const S*)b,
+                                           g.px, g.py, (int)g.nx, (int)g.ny, (int)g.nz, zrun, c));
     }
     return hipGetLastError();
 }
@@ -436,6 +440,13 @@ hipError_t launch_residual_to_lo(Fmt f, const double* u64, const double* b64, vo
     SRJ_DISPATCH(f, hipLaunchKernelGGL(k_residual_to_lo<S>, dim3(nb), dim3(256), 0, s, u64, b64, (S*)rlo, g,
                                        partials));
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, s, partials, nb, result);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual_out(const double* u64, const double* b64, double* r_user, const Geo& g, hipStream_t s)
+{
+    int64_t n = (g.ndim == 3 ? g.nz + 2 : 1) * (g.ny + 2) * (g.nx + 2);
+    hipLaunchKernelGGL(k_residual_out, grid1d(n), dim3(256), 0, s, u64, b64, r_user, g);
     return hipGetLastError();
 }
 

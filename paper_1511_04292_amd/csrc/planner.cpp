@@ -349,7 +349,10 @@ bool solve_from_weights(Sys& s, const ld* wguess, ld* z, Eval* ev)
     ld kap[SRJ_PLAN_MAXP];
     kappa_guess(wguess, s.P, kap);
     pack(s, wguess, kap, z);
-    if (!(newton(s, z, 1e-14L, 200) || levmar(s, z, 1e-14L, 300))) return false;
+    // the solvers aim at 1e-14; at extreme intervals the evaluation's own rounding can sit
+    // just above that, so acceptance is decided by valid() (residual below 1e-11, positive
+    // fractions and multipliers, descending weights) at whatever point they reached
+    if (!newton(s, z, 1e-14L, 200)) levmar(s, z, 1e-14L, 300);
     return valid(s, z, ev);
 }
 
@@ -423,7 +426,8 @@ bool optimal_schedule(int P, double km_d, double kM_d, Optimum* out, std::string
         s2.a = logl(s2.km);
         std::memcpy(zs, z, sizeof(ld) * (2 * P - 1));
         Eval ev2;
-        bool ok = (newton(s2, zs, 1e-14L, 60) || levmar(s2, zs, 1e-14L, 100)) && valid(s2, zs, &ev2);
+        if (!newton(s2, zs, 1e-14L, 60)) levmar(s2, zs, 1e-14L, 100);
+        const bool ok = valid(s2, zs, &ev2);
         if (!ok) {
             step *= 0.5L;
             if (++fails > 40) {

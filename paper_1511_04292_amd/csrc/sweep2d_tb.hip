@@ -12,7 +12,6 @@
 
 #include <algorithm>
 #include <cstdint>
-#include <cstdlib>
 
 #include "formats.h"
 #include "kernels.h"
@@ -26,18 +25,18 @@ template <int T> struct CoefsT {
     double c[T];
 };
 
-// Blocks are optionally remapped so that each of the 8 XCDs works on a contiguous band of
-// tiles, keeping the overlapping halo reads of neighbouring waves in one L2.
+// Blocks are remapped so that each of the 8 XCDs works on a contiguous band of tiles,
+// keeping the overlapping halo reads of neighbouring waves in one L2.
 // The 4- and 2-byte formats are held to 3 waves per SIMD (168 VGPRs): at 10 levels the
 // compiler would otherwise take 185 and leave 2; binary64 is left to the compiler.
 template <class S, int T, int C, int D>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(S) == 8 ? 1 : 3)))
 void k_sweep2d_tb(const S* __restrict__ uin, S* __restrict__ uout, const S* __restrict__ bb, int64_t px, int nx,
-                  int ny, CoefsT<T> co, int nstrip, int nwaves, int H, int remap, int flip)
+                  int ny, CoefsT<T> co, int nstrip, int nwaves, int H, int flip)
 {
     using Cm = typename Tr<S>::C;
     const int nblk = (int)gridDim.x;  // a multiple of 8 (padded by the launcher)
-    const int blk = remap ? (int)(blockIdx.x & 7) * (nblk >> 3) + (int)(blockIdx.x >> 3) : (int)blockIdx.x;
+    const int blk = (int)(blockIdx.x & 7) * (nblk >> 3) + (int)(blockIdx.x >> 3);
     // the wave index is uniform across the wave: keep it (and all loop bounds) in SGPRs
     const int wid = __builtin_amdgcn_readfirstlane(blk * 4 + (int)(threadIdx.x >> 6));
     if (wid >= nwaves) return;
@@ -45,12 +44,6 @@ void k_sweep2d_tb(const S* __restrict__ uin, S* __restrict__ uout, const S* __re
 #pragma unroll
     for (int l = 0; l < T; ++l) cf[l] = (Cm)co.c[l];
     tb_tile<S, T, C, D>(uin, uout, bb, px, nx, ny, cf, T, wid % nstrip, wid / nstrip, H, flip);
-}
-
-static int env_int(const char* name, int dflt)
-{
-    const char* v = getenv(name);
-    return v ? atoi(v) : dflt;
 }
 
 // Waves of one kernel instance that the device holds at once: blocks per CU (from the
@@ -74,7 +67,6 @@ static void tb2d(const S* in, S* out, const S* b, const Geo& g, const Coefs& co,
                  hipStream_t s)
 {
     constexpr int SW = 64 * C - 2 * T;
-    static const int remap = env_int("SRJ_TB_XCD_REMAP", 1);  // tuning knob, default on
     CoefsT<T> ct;
     for (int l = 0; l < T; ++l) ct.c[l] = co.c[l];
     const int nstrip = (int)((g.nx + SW - 1) / SW);
@@ -90,7 +82,7 @@ static void tb2d(const S* in, S* out, const S* b, const Geo& g, const Coefs& co,
     const int nwaves = nstrip * nseg;
     const int nblk = ((nwaves + 3) / 4 + 7) / 8 * 8;
     hipLaunchKernelGGL((k_sweep2d_tb<S, T, C, D>), dim3(nblk), dim3(256), 0, s, in, out, b, g.px,
-                       (int)g.nx, (int)g.ny, ct, nstrip, nwaves, H, remap, flip);
+                       (int)g.nx, (int)g.ny, ct, nstrip, nwaves, H, flip);
 }
 
 template <class S, int C, int D>
@@ -128,8 +120,7 @@ hipError_t launch_sweep_fused(Fmt f, const void* in, void* out, const void* b, c
                               const Coefs& co, int T, int H, int flip, hipStream_t s)
 {
     if (g.ndim != 2 || T < 1 || T > kMaxFuse || H < 0) return hipErrorInvalidValue;  // H = 0: automatic
-    static const int flips = env_int("SRJ_TB_FLIP", 1);  // tuning knob, default on
-    flip = flips ? (flip & 1) : 0;
+    flip &= 1;
     SRJ_DISPATCH(f, tb2d_dispatch<S>((const S*)in, (S*)out, (const S*)b, g, co, T, H, flip, s));
     return hipGetLastError();
 }

@@ -16,7 +16,6 @@
 #include <algorithm>
 #include <climits>
 #include <cstdint>
-#include <cstdlib>
 
 #include "formats.h"
 #include "kernels.h"
@@ -192,12 +191,6 @@ __global__ __launch_bounds__(k3Threads) void k_sweep3d_tb(const S* __restrict__ 
     }
 }
 
-static int env_int3(const char* name, int dflt)
-{
-    const char* v = getenv(name);
-    return v ? atoi(v) : dflt;
-}
-
 template <class S, int T, int D>
 static int tb3_resident_blocks()
 {
@@ -221,9 +214,8 @@ static void tb3d(const S* in, S* out, const S* b, const Geo& g, const Coefs& co,
     const int ntx = (int)((g.nx + SX - 1) / SX);
     const int nty = (int)((g.ny + SY - 1) / SY);
     // z runs: as many as fill the resident block slots once (at least one), balanced
-    static const int zs_knob = env_int3("SRJ_3DTB_ZRUN", 0);  // tuning knob, 0 = automatic
     int ntz = std::max(1, tb3_resident_blocks<S, T, D>() / (ntx * nty));
-    int zs = zs_knob > 0 ? zs_knob : (int)((g.nz + ntz - 1) / ntz);
+    int zs = (int)((g.nz + ntz - 1) / ntz);
     zs = std::max(1, std::min(zs, (int)g.nz));
     ntz = (int)((g.nz + zs - 1) / zs);
     zs = (int)((g.nz + ntz - 1) / ntz);
@@ -244,16 +236,11 @@ static void tb3d_TD(const S* in, S* out, const S* b, const Geo& g, const Coefs& 
     }
 }
 
-// Planes in flight per wave: 2 (the default) or 1.
+// Two planes in flight per wave.
 template <class S>
 static void tb3d_T(const S* in, S* out, const S* b, const Geo& g, const Coefs& co, int T, hipStream_t s)
 {
-    static const int knob = env_int3("SRJ_3DTB_PREFETCH", 0);  // tuning knob, 0 = default (2)
-    const int pf = knob > 0 ? knob : 2;
-    if (pf >= 2)
-        tb3d_TD<S, 2>(in, out, b, g, co, T, s);
-    else
-        tb3d_TD<S, 1>(in, out, b, g, co, T, s);
+    tb3d_TD<S, 2>(in, out, b, g, co, T, s);
 }
 
 hipError_t launch_sweep_fused3d(Fmt f, const void* in, void* out, const void* b, const Geo& g,

@@ -104,10 +104,14 @@ def smooth_3d(n=512, seed=0):
 
 
 def batch_sizes(count=1024, seed=3, lo=32, hi=1024, plo=3, phi=8):
-    """Side N_j = floor(exp(U(ln lo, ln hi))) and levels P_j ~ U{plo..phi}."""
+    """Side N_j = floor(exp(U(ln lo, ln hi))) and levels P_j ~ U{plo..phi}.  Sides are not
+    powers of two: a draw that lands on one moves to the next integer (to the previous one
+    at the upper end of the range)."""
     rng = np.random.default_rng(seed)
     N = np.floor(np.exp(rng.uniform(math.log(lo), math.log(hi), count))).astype(np.int64)
     N = np.clip(N, lo, hi)
+    pow2 = (N & (N - 1)) == 0
+    N = np.where(pow2, np.where(N + 1 <= hi, N + 1, N - 1), N)
     P = rng.integers(plo, phi + 1, size=count)
     return N, P
 
@@ -134,3 +138,38 @@ def random_state(shape_full, seed):
     """Random field with a random ring (for single-sweep parity checks)."""
     rng = np.random.default_rng(seed)
     return rng.uniform(-1.0, 1.0, size=shape_full)
+
+
+def blobs_2d_device(n, seed=0, count=32, device="cuda:0"):
+    """A blob workload too large to draw on the host quickly (e.g. 32768^2, 8.6 GB per array):
+    ring U(-1,1) drawn edge by edge (top row, bottom row, left column, right column, corners
+    included), then 32 blobs as in gaussian_blobs_2d, all from one PCG64 stream; the arrays
+    are assembled on the device in binary64 (torch).  The same distribution as blobs_2d, not
+    the same values."""
+    import torch
+
+    rng = np.random.default_rng(seed)
+    m = n + 2
+    top, bottom = rng.uniform(-1.0, 1.0, m), rng.uniform(-1.0, 1.0, m)
+    left, right = rng.uniform(-1.0, 1.0, n), rng.uniform(-1.0, 1.0, n)
+    cx = rng.uniform(0.0, 1.0, count)
+    cy = rng.uniform(0.0, 1.0, count)
+    s = rng.uniform(0.01, 0.1, count)
+    a = rng.standard_normal(count)
+    dt = torch.float64
+    u0 = torch.zeros((m, m), dtype=dt, device=device)
+    u0[0, :] = torch.from_numpy(top).to(device)
+    u0[-1, :] = torch.from_numpy(bottom).to(device)
+    u0[1:-1, 0] = torch.from_numpy(left).to(device)
+    u0[1:-1, -1] = torch.from_numpy(right).to(device)
+    x = torch.from_numpy(coords(n)).to(device)
+    f = torch.zeros((m, m), dtype=dt, device=device)
+    for j in range(count):
+        gx = torch.exp(-((x - float(cx[j])) ** 2) / (2.0 * float(s[j]) ** 2))
+        gy = torch.exp(-((x - float(cy[j])) ** 2) / (2.0 * float(s[j]) ** 2))
+        f.add_(torch.outer(gy, gx), alpha=float(a[j]))
+    f[0, :] = 0.0
+    f[-1, :] = 0.0
+    f[:, 0] = 0.0
+    f[:, -1] = 0.0
+    return dict(n=(n, n), h=grid_spacing(n), u0=u0, f=f)

@@ -63,9 +63,12 @@ def test_worked_example_counts_from_product_planner(golden_dir):
 
 
 @pytest.mark.parametrize("P,N,ordering", [(2, 45.957, 0), (8, 362.745, 0), (10, 550, 0), (10, 550, 1),
-                                          (6, 100, 0)])
+                                          (6, 100, 0), (10, (4096, 4096), 0), (9, (2048, 2048), 0),
+                                          (8, (512, 512, 512), 0)])
 def test_orderings_match_oracle(P, N, ordering):
-    km = S.kappa_min_neumann(N)
+    # N: a Neumann table resolution, or the interior sizes of a Dirichlet grid (the
+    # benchmark's 4096^2, 2048^2 and 512^3 schedules, N_eff 2897.02, 1448.86, 362.75)
+    km = S.kappa_min_dirichlet(N) if isinstance(N, tuple) else S.kappa_min_neumann(N)
     o = S.optimal(P, km)
     q = S.q_floor(o["beta"])
     ref = S.order_balanced(o["w"], q, km) if ordering == 0 else S.order_even(q)

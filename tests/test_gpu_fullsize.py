@@ -1,8 +1,13 @@
 """Parity at the benchmark's full sizes, in the launch configuration bench.py times.
 
-4096^2 FP64 (P = 10) and 512^3 FP64 (P = 8): a window of sweeps is compared bit for bit with
-the oracle run on the whole grid; the full 4096^2 solve must stop at the cycle the exact
-DST-mode trajectory predicts, with the relres it predicts.
+4096^2 (P = 10), 2048^2 (P = 9) and 512^3 (P = 8) in binary64, and the binary32 and
+bfloat16-storage sweeps at 4096^2 and 512^3: windows of sweeps at the default fusion depth
+(10 in 2D, 4 in binary64 3D, 5 in the 4- and 2-byte formats in 3D), crossing a cycle end, are
+compared bit for bit with the oracle run on the whole grid -- on the oracle's schedules and
+on the schedules the product planner builds for the benchmark.  The full 4096^2 and 512^3
+binary64 solves must stop at the cycle the exact DST-mode trajectory predicts, with the
+relres it predicts; the 512^3 results of all three precisions are compared with the exact
+discrete solution.
 """
 import numpy as np
 import pytest
@@ -67,18 +72,125 @@ def test_blobs_4096_solve_stops_where_predicted(blobs):
     assert abs(info["relres"] - pred[info["cycles"]]) <= 2e-3 * pred[info["cycles"]]
 
 
-def test_smooth_512cube_window_bitwise():
-    wl = workloads.smooth_3d(512, seed=0)
+@pytest.fixture(scope="module")
+def smooth():
+    return workloads.smooth_3d(512, seed=0)
+
+
+def test_smooth_512cube_window_bitwise(smooth):
+    """Depth-4 binary64 launches (the benchmark's) and the short launches at a cycle end:
+    from step M - 5, 12 sweeps run as launches of 4, 1, 4 and 3."""
+    wl = smooth
     w, q, seq = oracle_schedule(8, wl["n"])
+    M = int(np.sum(q))
     plan = srj.srj_plan(wl["n"], wl["h"], omega=w, q=q, sequence=seq)
+    assert srj.srj_plan_describe(plan)["fused_sweeps"] == 4
     c = sweeps.coefficients(np.asarray(w)[seq], 3)
     b = sweeps.rhs(wl["f"], wl["h"])
-    n = 3
+    k0, n = M - 5, 12
     u = torch.from_numpy(wl["u0"]).to(DEV)
-    srj.srj_sweeps(plan, u, torch.from_numpy(wl["f"]).to(DEV), 0, n)
-    ref = sweeps.run(wl["u0"], b, c, n)
-    got = u.cpu().numpy()
-    assert np.array_equal(got, ref)
+    _, launches = srj.srj_sweeps(plan, u, torch.from_numpy(wl["f"]).to(DEV), k0, n)
+    assert launches == 4
+    ref = sweeps.run(wl["u0"], b, c, n, k0=k0)
+    assert np.array_equal(u.cpu().numpy(), ref)
+
+
+def _lowprec_window(wl, ndim, w, seq, fmt, k0, n, depth):
+    plan = srj.srj_plan(wl["n"], wl["h"], omega=w, q=np.bincount(seq, minlength=len(w)), sequence=seq, dtype=fmt)
+    assert srj.srj_plan_describe(plan)["fused_sweeps"] == depth
+    u = torch.from_numpy(wl["u0"]).to(DEV)
+    srj.srj_sweeps(plan, u, torch.from_numpy(wl["f"]).to(DEV), k0, n)
+    c32 = sweeps.lo_coefficients(np.asarray(w)[seq], ndim)
+    x = sweeps.lo_cast(wl["u0"], fmt)
+    b = sweeps.lo_cast(sweeps.rhs(wl["f"], wl["h"]), fmt)
+    M = len(seq)
+    for s_ in range(n):
+        x = sweeps.sweep_lo(x, b, c32[(k0 + s_) % M], fmt)
+    ref = sweeps.lo_widen(x, fmt)
+    inner = tuple(slice(1, -1) for _ in range(ndim))
+    assert np.array_equal(u.cpu().numpy()[inner], ref[inner])
+
+
+@pytest.mark.parametrize("fmt", ["f32", "bf16"])
+def test_smooth_512cube_lowprec_window_bitwise(smooth, fmt):
+    """Depth-5 binary32 / bfloat16 launches at 512^3 (the benchmark's refinement sweeps):
+    from step M - 3, 10 sweeps run as launches of 3, 5 and 2."""
+    w, q, seq = oracle_schedule(8, smooth["n"])
+    _lowprec_window(smooth, 3, w, seq, fmt, int(np.sum(q)) - 3, 10, 5)
+
+
+@pytest.mark.parametrize("fmt", ["f32", "bf16"])
+def test_blobs_4096_lowprec_window_bitwise(blobs, fmt):
+    """Depth-10 binary32 / bfloat16 launches at 4096^2: from step M - 5, 25 sweeps run as
+    launches of 5, 10 and 10."""
+    w, q, seq = oracle_schedule(10, blobs["n"])
+    _lowprec_window(blobs, 2, w, seq, fmt, int(np.sum(q)) - 5, 25, 10)
+
+
+@pytest.mark.parametrize("case", ["blobs4096_P10", "adjoint2048_P9", "smooth512_P8"])
+def test_product_planned_schedule_window_bitwise(case, blobs, smooth):
+    """The plans the benchmark times are built by the product planner (srj_plan with P
+    only).  Their weights and step order, read back through the ABI, drive the oracle on the
+    same window; the GPU iterate must match it bit for bit.  The planner's weights agree with
+    the oracle's optimum to 1e-8 and its counts exactly."""
+    if case == "blobs4096_P10":
+        wl, P, ndim = blobs, 10, 2
+    elif case == "adjoint2048_P9":
+        a = workloads.adjoint_2d(2048)
+        wl, P, ndim = dict(n=a["n"], h=a["h"], u0=a["g"], f=a["f"]), 9, 2
+    else:
+        wl, P, ndim = smooth, 8, 3
+    plan = srj.srj_plan(wl["n"], wl["h"], P=P)
+    d = srj.srj_plan_describe(plan)
+    seq = srj.srj_plan_sequence(plan)
+    w = d["omega"]
+    ow, oq, oseq = oracle_schedule(P, wl["n"])
+    np.testing.assert_allclose(w, ow, rtol=1e-8)
+    assert np.array_equal(d["q"], oq)
+    M = int(d["M"])
+    k0, n = (M - 7, 20) if ndim == 2 else (M - 5, 12)
+    c = sweeps.coefficients(np.asarray(w)[seq], ndim)
+    b = sweeps.rhs(wl["f"], wl["h"])
+    u = torch.from_numpy(wl["u0"]).to(DEV)
+    srj.srj_sweeps(plan, u, torch.from_numpy(wl["f"]).to(DEV), k0, n)
+    ref = sweeps.run(wl["u0"], b, c, n, k0=k0)
+    assert np.array_equal(u.cpu().numpy(), ref), case
+
+
+def test_smooth_512cube_solves_stop_where_predicted(smooth):
+    """Binary64 SRJ at 512^3 stops at the cycle the DST-mode trajectory predicts; the
+    binary64 result and the binary32 / bfloat16-storage refinements (all to relres 1e-10) lie
+    within cond(A) * tol of the exact discrete solution."""
+    wl = smooth
+    w, q, seq = oracle_schedule(8, wl["n"])
+    M = int(np.sum(q))
+    tol = 1e-10
+    b = sweeps.rhs(wl["f"], wl["h"])
+    pred = spectral.predicted_relres(wl["u0"], b, w, q, 15)
+    m_pred = int(np.argmax(pred <= tol))
+    assert pred[m_pred] <= tol
+    ustar = spectral.exact_solve(wl["u0"], b)
+    scale = float(np.max(np.abs(ustar)))
+    # condition number of A: largest over smallest eigenvalue, cot^2(pi / (2 (n + 1)))
+    n = wl["n"][0]
+    cond = (np.cos(np.pi / (2 * (n + 1))) / np.sin(np.pi / (2 * (n + 1)))) ** 2
+    f = torch.from_numpy(wl["f"]).to(DEV)
+    for fmt in ("f64", "f32", "bf16"):
+        plan = srj.srj_plan(wl["n"], wl["h"], omega=w, q=q, sequence=seq, dtype=fmt)
+        u = torch.from_numpy(wl["u0"]).to(DEV)
+        if fmt == "f64":
+            info = srj.srj_solve(plan, u, f, tol, 30 * M)
+            near = abs(pred[m_pred] - tol) < 0.01 * tol or abs(pred[m_pred - 1] - tol) < 0.01 * tol
+            assert info["cycles"] == m_pred or (near and abs(info["cycles"] - m_pred) == 1), (info, m_pred)
+            assert abs(info["relres"] - pred[info["cycles"]]) <= 2e-3 * pred[info["cycles"]]
+        else:
+            info = srj.srj_solve_ir(plan, u, f, tol, 1, 100)
+        assert info["status"] == "ok" and info["relres"] <= tol, (fmt, info)
+        err = float(np.max(np.abs(u.cpu().numpy() - ustar))) / scale
+        print(f"512^3 {fmt}: sweeps {info['sweeps']}, relres {info['relres']:.3e}, "
+              f"max|u - u*| / max|u*| = {err:.3e}", flush=True)
+        assert err <= cond * tol, (fmt, err)
+        del plan, u
 
 
 def test_adjoint_2048_central_differences():

@@ -293,6 +293,35 @@ def test_ir_matches_oracle(fmt):
     assert np.array_equal(host(ug), ref["u"])
 
 
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_ir_f64_matches_oracle(ndim):
+    """Refinement on a binary64 plan: its inner right-hand side must not overwrite b (one
+    inner cycle per outer step, so several outer steps are needed)."""
+    if ndim == 2:
+        wl = workloads.small_2d(47, seed=5)
+        n, h, u0, f = wl["n"], wl["h"], wl["u0"], wl["f"]
+    else:
+        n, h = (13, 16, 11), 1.0 / 17
+        rng = np.random.default_rng(33)
+        full = tuple(x + 2 for x in reversed(n))
+        u0 = workloads.random_ring(full, rng)
+        f = rng.standard_normal(full)
+    w, q, seq = oracle_schedule(3, n)
+    wseq = np.array(w)[seq]
+    ref = sweeps.solve_ir(u0, f, h, wseq, 1e-10, 1, 200, "f64")
+    assert ref["status"] == "ok" and ref["outer"] >= 2
+    p = explicit_plan(n, h, w, q, seq, dtype="f64")
+    ug = dev(u0)
+    info = srj.srj_solve_ir(p, ug, dev(f), 1e-10, 1, 200)
+    assert info["status"] == "ok" and info["relres"] <= 1e-10
+    assert info["cycles"] == ref["outer"]
+    assert abs(info["relres"] - ref["relres"]) <= 1e-12 * ref["relres"]
+    assert np.array_equal(host(ug), ref["u"])
+    # and the same state as the plain solve reaches, to the solve's tolerance
+    plain = sweeps.solve(u0, f, h, wseq, 1e-10, 10 ** 6)
+    assert np.max(np.abs(ref["u"] - plain["u"])) <= 1e-6 * np.max(np.abs(plain["u"]))
+
+
 @pytest.mark.parametrize("fmt", ["f32", "bf16"])
 @pytest.mark.parametrize("fuse", [0, 2, 4, 5])
 def test_lowprec_sweeps_3d_bitwise(fmt, fuse):

@@ -11,7 +11,12 @@ from oracle import schedule as S
 # Printed Table 1 rows that are measurably off the optimum of the stated problem: our
 # solution has a strictly lower max Gamma for each of them (checked below), and the
 # P = 4, N = 450 row does not even have equal maxima.  Listed in the design notes.
-OFF_OPTIMUM_ROWS = {(4, 100), (4, 150), (4, 250), (4, 400), (4, 450), (4, 500), (5, 100)}
+OFF_OPTIMUM_ROWS = {(4, 150), (4, 250), (4, 400), (4, 450), (4, 500)}
+# Rows whose printed point lies close to the optimum but further from it than 6-digit
+# rounding explains (about 3e-6 relative for the other rows): the oracle's point solves the
+# optimality system in 30-digit arithmetic and the printed one does not (see
+# test_near_rows_optimality_in_extended_precision); compared at the stated tolerance.
+NEAR_OPTIMUM_ROWS = {(4, 100): 1e-3, (5, 100): 1.5e-4}
 
 
 def read_table1(golden_dir):
@@ -51,8 +56,9 @@ def test_table1_rows(golden_dir):
         assert ours <= printed + 1e-12, (P, N)
         if (P, N) in OFF_OPTIMUM_ROWS:
             continue
-        np.testing.assert_allclose(o["w"], w, rtol=3e-5, err_msg=f"P={P} N={N}")
-        np.testing.assert_allclose(o["beta"], beta, rtol=3e-5, err_msg=f"P={P} N={N}")
+        tol = NEAR_OPTIMUM_ROWS.get((P, N), 3e-5)
+        np.testing.assert_allclose(o["w"], w, rtol=tol, err_msg=f"P={P} N={N}")
+        np.testing.assert_allclose(o["beta"], beta, rtol=tol, err_msg=f"P={P} N={N}")
         assert abs(S.rho(o["w"], o["beta"]) - rho) <= 0.0051, (P, N)
 
 
@@ -168,3 +174,99 @@ def test_integer_scheme_stays_convergent():
         q = S.q_floor(o["beta"])
         g = np.exp(np.linspace(math.log(km), math.log(2.0), 100001))
         assert S.gamma_q_max(o["w"], q, g) < 1.0
+
+
+def test_balanced_order_hand_worked():
+    """Balanced greedy order on a two-point grid {0.5, 2}, worked by hand.
+
+    w = (3, 1, 0.6), q = (1, 2, 3), M = 6.  L_i = (ln|1 - 0.5 w_i|, ln|1 - 2 w_i|):
+      L_1 = (ln 0.5, ln 5) = (-0.693147, 1.609438)
+      L_2 = (ln 0.5, ln 1) = (-0.693147, 0)
+      L_3 = (ln 0.7, ln 0.2) = (-0.356675, -1.609438)
+    T = L_1 + 2 L_2 + 3 L_3 = (-3.149466, -3.218876); the step-k target is (k/6) T.
+    Step k takes the weight with uses left minimising max over the grid of |s + L_i - (k/6) T|:
+      k=1 target (-0.524911, -0.536479): i=1 -> 2.145917, i=2 -> 0.536479, i=3 -> 1.072959: take 2
+      k=2 target (-1.049822, -1.072959), s = L_2: i=1 -> 2.682397, i=2 -> 1.072959,
+          i=3 -> 0.536479: take 3
+      k=3 target (-1.574733, -1.609438): i=1 -> 1.609438, i=2 -> 0.168236, i=3 -> 1.609438: take 2
+      k=4 target (-2.099644, -2.145917) (weight 2 used up): i=1 -> 2.145917, i=3 -> 1.072959: take 3
+      k=5 target (-2.624555, -2.682397): i=1 -> 1.072959, i=3 -> 2.145917: take 1
+      k=6: only weight 3 is left.
+    Taking the target one step early, the largest instead of the smallest maximum, or the
+    signed instead of the absolute deviation each changes the sequence.
+    """
+    seq = S.order_balanced([3.0, 1.0, 0.6], [1, 2, 3], 0.5, 2.0, G=2)
+    assert list(seq) == [1, 2, 1, 2, 0, 2]
+
+
+def _mp_optimality(w, beta, km, kM=2.0):
+    """Equal-maxima spread and first-order minimax residual of log Gamma (Eq. Gamma) at a
+    point (w, beta), in 30-digit arithmetic, independent of the oracle's solver.
+
+    The local maxima of log Gamma on [km, kM] are km, kM and one stationary point between
+    each pair of consecutive poles 1/w_i (Sec. 3.2).  At a minimax optimum all P + 1 maxima
+    are equal (Eq. equMax), and no move of (w, beta) with sum beta fixed lowers all of them
+    at once: some convex combination mu of their gradients is parallel to the gradient of
+    sum beta.  The residual of that linear system (least squares, mu summing to 1) is
+    returned with the spread and the largest maximum."""
+    import mpmath as mp
+
+    mp.mp.dps = 30
+    w = [mp.mpf(float(x)) for x in w]
+    b = [mp.mpf(float(x)) for x in beta]
+    tot = mp.fsum(b)
+    b = [x / tot for x in b]
+    P = len(w)
+    lg = lambda k: mp.fsum(bi * mp.log(abs(1 - wi * k)) for wi, bi in zip(w, b))
+    dlg = lambda k: mp.fsum(-bi * wi / (1 - wi * k) for wi, bi in zip(w, b))
+    ks = [mp.mpf(float(km))]
+    for i in range(P - 1):
+        lo, hi = (1 / w[i]) * (1 + mp.mpf("1e-20")), (1 / w[i + 1]) * (1 - mp.mpf("1e-20"))
+        ks.append(mp.findroot(dlg, (lo, hi), solver="anderson"))
+    ks.append(mp.mpf(kM))
+    vals = [lg(k) for k in ks]
+    spread = (max(vals) - min(vals)) / abs(vals[0])
+    A = mp.zeros(2 * P + 1, P + 2)
+    rhs = mp.zeros(2 * P + 1, 1)
+    for j, k in enumerate(ks):
+        for i in range(P):
+            A[i, j] = b[i] * (-k) / (1 - w[i] * k)
+            A[P + i, j] = mp.log(abs(1 - w[i] * k))
+    for i in range(P):
+        A[P + i, P + 1] = -1
+        A[2 * P, i] = 1
+    A[2 * P, P] = 1
+    rhs[2 * P] = 1
+    x = mp.lu_solve(A.T * A, A.T * rhs)
+    res = mp.norm(A * x - rhs) / mp.norm(A)
+    mu = [x[j] for j in range(P + 1)]
+    return float(spread), float(res), float(max(vals)), [float(m) for m in mu]
+
+
+@pytest.mark.parametrize("P,N", [(4, 100), (5, 100)])
+def test_near_rows_optimality_in_extended_precision(golden_dir, P, N):
+    """Which point solves the optimality system of Sec. 3.2 for the two near rows: the
+    oracle's (spread of the maxima and the first-order residual at 30-digit rounding level,
+    multipliers positive).  The printed point has a higher maximum of Gamma and lies further
+    from it than its 6 printed digits explain (the regular rows agree to about 3e-6)."""
+    row = [r for r in read_table1(golden_dir) if r[0] == P and r[1] == N][0]
+    km = S.kappa_min_neumann(N)
+    o = S.optimal(P, km)
+    sp_o, res_o, max_o, mu_o = _mp_optimality(o["w"], o["beta"], km)
+    sp_p, res_p, max_p, _ = _mp_optimality(row[2], row[3], km)
+    assert sp_o < 1e-11 and res_o < 1e-16 and min(mu_o) > 0, (sp_o, res_o, mu_o)
+    assert max_p > max_o * (1 - 5e-5), (max_p, max_o)
+    assert res_p > 1e5 * res_o and sp_p > 1e3 * sp_o
+    assert float(np.max(np.abs(o["w"] / row[2] - 1.0))) > 2e-5
+
+
+def test_regular_row_optimality_in_extended_precision(golden_dir):
+    """A row reproduced to 3e-5: the oracle's point solves the system to 30-digit rounding
+    level too, and the printed point's maximum is higher only by its 6-digit rounding."""
+    row = [r for r in read_table1(golden_dir) if r[0] == 5 and r[1] == 200][0]
+    km = S.kappa_min_neumann(200)
+    o = S.optimal(5, km)
+    sp_o, res_o, max_o, mu_o = _mp_optimality(o["w"], o["beta"], km)
+    _, _, max_p, _ = _mp_optimality(row[2], row[3], km)
+    assert sp_o < 1e-11 and res_o < 1e-16 and min(mu_o) > 0
+    assert max_o <= max_p <= max_o * (1 - 1e-3)

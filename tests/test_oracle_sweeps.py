@@ -230,3 +230,63 @@ def test_modal_prediction_with_large_schedule():
     pred = spectral.predicted_relres(wl["u0"], b, o["w"], q, 2)
     got = sweeps.relres(u, b)
     assert abs(got - pred[2]) <= 1e-3 * pred[2]
+
+
+def _matrix_form_step(x_full, b_full, c):
+    """u + c (b~ - A u) on the interior from the dense matrix (independent route), FP64."""
+    shape = tuple(n - 2 for n in x_full.shape)
+    inner = tuple(slice(1, -1) for _ in shape)
+    A = spectral.dense_matrix(shape)
+    x = x_full[inner].ravel()
+    return (x + c * (spectral.load_vector(x_full, b_full).ravel() - A @ x)).reshape(shape)
+
+
+def _step_bound(x_full, b_full, c):
+    """Per-point bound on the rounding of one binary32 step: 8 units of 2^-24 times the
+    magnitudes entering it (|u| + |c| (sum |neighbours| + |b| + 2d |u|))."""
+    nd = x_full.ndim
+    inner = tuple(slice(1, -1) for _ in range(nd))
+    a = np.abs(x_full)
+    nb = np.zeros(tuple(n - 2 for n in x_full.shape))
+    for ax in range(nd):
+        lo = [slice(1, -1)] * nd
+        hi = [slice(1, -1)] * nd
+        lo[ax] = slice(0, -2)
+        hi[ax] = slice(2, None)
+        nb += a[tuple(lo)] + a[tuple(hi)]
+    return 8 * 2.0 ** -24 * (a[inner] + abs(c) * (nb + np.abs(b_full[inner]) + 2 * nd * a[inner]))
+
+
+@pytest.mark.parametrize("fmt,shape", [("f32", (5, 4, 6)), ("bf16", (13, 9)), ("bf16", (5, 6, 4)),
+                                       ("f32", (9, 14))])
+def test_lo_sweep_matches_matrix_form(fmt, shape):
+    """The binary32 and bfloat16-storage steps against the dense matrix form evaluated in
+    FP64 from the same stored inputs: binary32 results within the per-term rounding bound;
+    bfloat16 results equal to the bfloat16 rounding of a value within that bound."""
+    rng = np.random.default_rng(11)
+    full = tuple(n + 2 for n in shape)
+    nd = len(shape)
+    u = rng.uniform(-1, 1, size=full)
+    b = rng.uniform(-1e-3, 1e-3, size=full)
+    c32 = np.float32(1234.5 / (2 * nd))
+    c = float(c32)
+    inner = tuple(slice(1, -1) for _ in shape)
+    if fmt == "f32":
+        u_s, b_s = u.astype(np.float32), b.astype(np.float32)
+        x, bx = u_s.astype(np.float64), b_s.astype(np.float64)
+    else:
+        u_s, b_s = sweeps.to_bf16_bits(u.astype(np.float32)), sweeps.to_bf16_bits(b.astype(np.float32))
+        x, bx = sweeps.from_bf16_bits(u_s).astype(np.float64), sweeps.from_bf16_bits(b_s).astype(np.float64)
+    out = sweeps.sweep_lo(u_s, b_s, c32, fmt)
+    got = out.astype(np.float64) if fmt == "f32" else sweeps.from_bf16_bits(out).astype(np.float64)
+    ref = _matrix_form_step(x, bx, c)
+    bound = _step_bound(x, bx, c)
+    if fmt == "f32":
+        assert np.all(np.abs(got[inner] - ref) <= bound)
+    else:
+        lo = sweeps.from_bf16_bits(sweeps.to_bf16_bits((ref - bound).astype(np.float32))).astype(np.float64)
+        hi = sweeps.from_bf16_bits(sweeps.to_bf16_bits((ref + bound).astype(np.float32))).astype(np.float64)
+        assert np.all((lo <= got[inner]) & (got[inner] <= hi))
+    ring = np.ones(full, bool)
+    ring[inner] = False
+    assert np.array_equal(out[ring], u_s[ring])
