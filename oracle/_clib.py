@@ -30,21 +30,23 @@ def lib():
         build()
     L = ctypes.CDLL(SO)
     i64, dbl, flt, vp = ctypes.c_int64, ctypes.c_double, ctypes.c_float, ctypes.c_void_p
+    # every sweep and residual routine takes the axis weights wt = {wy, wz, dg} (binary64, or
+    # their binary32 roundings for the binary32 / bfloat16 routines) before its coefficient
     sig = {
-        "or_sweep2d": [i64, i64, vp, vp, dbl, vp],
-        "or_sweep3d": [i64, i64, i64, vp, vp, dbl, vp],
+        "or_sweep2d": [i64, i64, vp, vp, vp, dbl, vp],
+        "or_sweep3d": [i64, i64, i64, vp, vp, vp, dbl, vp],
         "or_jacobi2d": [i64, i64, vp, vp, vp],
         "or_jacobi3d": [i64, i64, i64, vp, vp, vp],
-        "or_srj2d": [i64, i64, vp, vp, vp, i64, i64, i64, vp],
-        "or_srj3d": [i64, i64, i64, vp, vp, vp, i64, i64, i64, vp],
-        "or_residual2d": [i64, i64, vp, vp, vp, vp, vp],
-        "or_residual3d": [i64, i64, i64, vp, vp, vp, vp, vp],
-        "or_residual_field2d": [i64, i64, vp, vp, vp],
-        "or_residual_field3d": [i64, i64, i64, vp, vp, vp],
-        "or_sweep2d_f32": [i64, i64, vp, vp, flt, vp],
-        "or_sweep3d_f32": [i64, i64, i64, vp, vp, flt, vp],
-        "or_sweep2d_bf16": [i64, i64, vp, vp, flt, vp],
-        "or_sweep3d_bf16": [i64, i64, i64, vp, vp, flt, vp],
+        "or_srj2d": [i64, i64, vp, vp, vp, vp, i64, i64, i64, vp],
+        "or_srj3d": [i64, i64, i64, vp, vp, vp, vp, i64, i64, i64, vp],
+        "or_residual2d": [i64, i64, vp, vp, vp, vp, vp, vp],
+        "or_residual3d": [i64, i64, i64, vp, vp, vp, vp, vp, vp],
+        "or_residual_field2d": [i64, i64, vp, vp, vp, vp],
+        "or_residual_field3d": [i64, i64, i64, vp, vp, vp, vp],
+        "or_sweep2d_f32": [i64, i64, vp, vp, vp, flt, vp],
+        "or_sweep3d_f32": [i64, i64, i64, vp, vp, vp, flt, vp],
+        "or_sweep2d_bf16": [i64, i64, vp, vp, vp, flt, vp],
+        "or_sweep3d_bf16": [i64, i64, i64, vp, vp, vp, flt, vp],
         "or_f32_to_bf16": [i64, vp, vp],
         "or_bf16_to_f32": [i64, vp, vp],
     }

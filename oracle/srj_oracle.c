@@ -7,13 +7,17 @@
  *
  * Discretisation (paper Sec. 3.1, Eq. 2nd-order_CD, written for the Poisson problem
  * of Sec. 5.1 with the sign convention -lap(u) = f):
- *   grid of n_i interior points per dimension, spacing h, ring of Dirichlet values;
- *   b = (h*h) * f ;  weighted Jacobi step with weight w, c = w / (2d):
- *     s  = (W + E) + (S + N)            [ + (D + U) in 3D ]
- *     t  = (s + b) - (2d) * u           (t is the residual b - A u of the input state)
+ *   grid of n_i interior points per dimension, spacing h_x, h_y (, h_z), ring of Dirichlet
+ *   values.  Multiplied through by h_x^2 the operator has weight 1 on the x neighbours,
+ *   wy = h_x^2 / h_y^2 on the y neighbours, wz = h_x^2 / h_z^2 on the z neighbours and the
+ *   diagonal dg = 2 ((1 + wy) + wz) (2 (1 + wy) in 2D); with equal spacings wy = wz = 1 and
+ *   dg = 2d.  b = (h_x*h_x) * f ;  weighted Jacobi step with weight w, c = w / dg:
+ *     s  = (W + E) + wy (S + N)         [ + wz (D + U) in 3D ]
+ *     t  = (s + b) - dg * u             (t is the residual b - A u of the input state)
  *     u' = u + c * t
- *   The association above is fixed; the file is compiled with -ffp-contract=off so no
- *   multiply-add is fused.
+ *   The weights come in as wt = {wy, wz, dg}.  The association above is fixed; the file is
+ *   compiled with -ffp-contract=off so no multiply-add is fused.  With unit weights every
+ *   product by a weight is exact and the step is the equal-spacing step.
  *
  * Layout: row-major, x fastest.  2D: (ny+2) rows of (nx+2); 3D: (nz+2) planes of
  * (ny+2) rows of (nx+2).  Index 0 and n+1 of every dimension is the Dirichlet ring.
@@ -28,30 +32,33 @@
 /* ---------------------------------------------------------------- FP64 sweeps */
 
 /* One weighted-Jacobi step, 2D 5-point (Eq. 2nd-order_CD).  out's ring is not touched. */
-void or_sweep2d(int64_t nx, int64_t ny, const double* u, const double* b, double c, double* out)
+void or_sweep2d(int64_t nx, int64_t ny, const double* u, const double* b, const double* wt, double c,
+                double* out)
 {
+    const double wy = wt[0], dg = wt[2];
 #pragma omp parallel for schedule(static)
     for (int64_t i = 1; i <= ny; ++i) {
         for (int64_t j = 1; j <= nx; ++j) {
-            double s = (u[I2(i, j - 1)] + u[I2(i, j + 1)]) + (u[I2(i - 1, j)] + u[I2(i + 1, j)]);
-            double t = (s + b[I2(i, j)]) - 4.0 * u[I2(i, j)];
+            double s = (u[I2(i, j - 1)] + u[I2(i, j + 1)]) + wy * (u[I2(i - 1, j)] + u[I2(i + 1, j)]);
+            double t = (s + b[I2(i, j)]) - dg * u[I2(i, j)];
             out[I2(i, j)] = u[I2(i, j)] + c * t;
         }
     }
 }
 
 /* One weighted-Jacobi step, 3D 7-point (Eq. 2nd-order_CD extended to d = 3, Sec. 3.1). */
-void or_sweep3d(int64_t nx, int64_t ny, int64_t nz, const double* u, const double* b, double c,
-                double* out)
+void or_sweep3d(int64_t nx, int64_t ny, int64_t nz, const double* u, const double* b, const double* wt,
+                double c, double* out)
 {
+    const double wy = wt[0], wz = wt[1], dg = wt[2];
 #pragma omp parallel for schedule(static)
     for (int64_t k = 1; k <= nz; ++k) {
         for (int64_t i = 1; i <= ny; ++i) {
             for (int64_t j = 1; j <= nx; ++j) {
                 double s = ((u[I3(k, i, j - 1)] + u[I3(k, i, j + 1)]) +
-                            (u[I3(k, i - 1, j)] + u[I3(k, i + 1, j)])) +
-                           (u[I3(k - 1, i, j)] + u[I3(k + 1, i, j)]);
-                double t = (s + b[I3(k, i, j)]) - 6.0 * u[I3(k, i, j)];
+                            wy * (u[I3(k, i - 1, j)] + u[I3(k, i + 1, j)])) +
+                           wz * (u[I3(k - 1, i, j)] + u[I3(k + 1, i, j)]);
+                double t = (s + b[I3(k, i, j)]) - dg * u[I3(k, i, j)];
                 out[I3(k, i, j)] = u[I3(k, i, j)] + c * t;
             }
         }
@@ -83,25 +90,25 @@ void or_jacobi3d(int64_t nx, int64_t ny, int64_t nz, const double* u, const doub
 /* Run `nsweeps` scheduled steps: step s uses c_seq[(k0 + s) mod M] (Sec. 2: the M-cycle
  * repeated).  u holds the start state and receives the result; work is a second array of
  * the same shape whose ring already equals u's ring. */
-void or_srj2d(int64_t nx, int64_t ny, double* u, const double* b, const double* c_seq, int64_t M,
-              int64_t k0, int64_t nsweeps, double* work)
-{
-    double* cur = u;
-    double* nxt = work;
-    for (int64_t s = 0; s < nsweeps; ++s) {
-        or_sweep2d(nx, ny, cur, b, c_seq[(k0 + s) % M], nxt);
-        double* t = cur; cur = nxt; nxt = t;
-    }
-    if (cur != u) memcpy(u, cur, sizeof(double) * (size_t)(nx + 2) * (size_t)(ny + 2));
-}
-
-void or_srj3d(int64_t nx, int64_t ny, int64_t nz, double* u, const double* b, const double* c_seq,
+void or_srj2d(int64_t nx, int64_t ny, double* u, const double* b, const double* wt, const double* c_seq,
               int64_t M, int64_t k0, int64_t nsweeps, double* work)
 {
     double* cur = u;
     double* nxt = work;
     for (int64_t s = 0; s < nsweeps; ++s) {
-        or_sweep3d(nx, ny, nz, cur, b, c_seq[(k0 + s) % M], nxt);
+        or_sweep2d(nx, ny, cur, b, wt, c_seq[(k0 + s) % M], nxt);
+        double* t = cur; cur = nxt; nxt = t;
+    }
+    if (cur != u) memcpy(u, cur, sizeof(double) * (size_t)(nx + 2) * (size_t)(ny + 2));
+}
+
+void or_srj3d(int64_t nx, int64_t ny, int64_t nz, double* u, const double* b, const double* wt,
+              const double* c_seq, int64_t M, int64_t k0, int64_t nsweeps, double* work)
+{
+    double* cur = u;
+    double* nxt = work;
+    for (int64_t s = 0; s < nsweeps; ++s) {
+        or_sweep3d(nx, ny, nz, cur, b, wt, c_seq[(k0 + s) % M], nxt);
         double* t = cur; cur = nxt; nxt = t;
     }
     if (cur != u)
@@ -120,17 +127,18 @@ static inline void kadd(kahan_t* k, double x)
     k->s = t;
 }
 
-/* r = b - A u = (s + b) - 2d u on the interior.  out[0] = sum r^2, out[1] = max |r|. */
-void or_residual2d(int64_t nx, int64_t ny, const double* u, const double* b, double* out,
+/* r = b - A u = (s + b) - dg u on the interior.  out[0] = sum r^2, out[1] = max |r|. */
+void or_residual2d(int64_t nx, int64_t ny, const double* u, const double* b, const double* wt, double* out,
                    double* rowsum, double* rowmax)
 {
+    const double wy = wt[0], dg = wt[2];
 #pragma omp parallel for schedule(static)
     for (int64_t i = 1; i <= ny; ++i) {
         kahan_t acc = {0.0, 0.0};
         double m = 0.0;
         for (int64_t j = 1; j <= nx; ++j) {
-            double s = (u[I2(i, j - 1)] + u[I2(i, j + 1)]) + (u[I2(i - 1, j)] + u[I2(i + 1, j)]);
-            double r = (s + b[I2(i, j)]) - 4.0 * u[I2(i, j)];
+            double s = (u[I2(i, j - 1)] + u[I2(i, j + 1)]) + wy * (u[I2(i - 1, j)] + u[I2(i + 1, j)]);
+            double r = (s + b[I2(i, j)]) - dg * u[I2(i, j)];
             kadd(&acc, r * r);
             double a = fabs(r);
             if (a > m || a != a) m = a;
@@ -148,9 +156,10 @@ void or_residual2d(int64_t nx, int64_t ny, const double* u, const double* b, dou
     out[1] = m;
 }
 
-void or_residual3d(int64_t nx, int64_t ny, int64_t nz, const double* u, const double* b, double* out,
-                   double* rowsum, double* rowmax)
+void or_residual3d(int64_t nx, int64_t ny, int64_t nz, const double* u, const double* b, const double* wt,
+                   double* out, double* rowsum, double* rowmax)
 {
+    const double wy = wt[0], wz = wt[1], dg = wt[2];
 #pragma omp parallel for schedule(static)
     for (int64_t k = 1; k <= nz; ++k) {
         for (int64_t i = 1; i <= ny; ++i) {
@@ -158,9 +167,9 @@ void or_residual3d(int64_t nx, int64_t ny, int64_t nz, const double* u, const do
             double m = 0.0;
             for (int64_t j = 1; j <= nx; ++j) {
                 double s = ((u[I3(k, i, j - 1)] + u[I3(k, i, j + 1)]) +
-                            (u[I3(k, i - 1, j)] + u[I3(k, i + 1, j)])) +
-                           (u[I3(k - 1, i, j)] + u[I3(k + 1, i, j)]);
-                double r = (s + b[I3(k, i, j)]) - 6.0 * u[I3(k, i, j)];
+                            wy * (u[I3(k, i - 1, j)] + u[I3(k, i + 1, j)])) +
+                           wz * (u[I3(k - 1, i, j)] + u[I3(k + 1, i, j)]);
+                double r = (s + b[I3(k, i, j)]) - dg * u[I3(k, i, j)];
                 kadd(&acc, r * r);
                 double a = fabs(r);
                 if (a > m || a != a) m = a;
@@ -180,57 +189,63 @@ void or_residual3d(int64_t nx, int64_t ny, int64_t nz, const double* u, const do
 }
 
 /* r written out (interior; ring set to 0). */
-void or_residual_field2d(int64_t nx, int64_t ny, const double* u, const double* b, double* r)
+void or_residual_field2d(int64_t nx, int64_t ny, const double* u, const double* b, const double* wt, double* r)
 {
+    const double wy = wt[0], dg = wt[2];
     memset(r, 0, sizeof(double) * (size_t)(nx + 2) * (size_t)(ny + 2));
 #pragma omp parallel for schedule(static)
     for (int64_t i = 1; i <= ny; ++i)
         for (int64_t j = 1; j <= nx; ++j) {
-            double s = (u[I2(i, j - 1)] + u[I2(i, j + 1)]) + (u[I2(i - 1, j)] + u[I2(i + 1, j)]);
-            r[I2(i, j)] = (s + b[I2(i, j)]) - 4.0 * u[I2(i, j)];
+            double s = (u[I2(i, j - 1)] + u[I2(i, j + 1)]) + wy * (u[I2(i - 1, j)] + u[I2(i + 1, j)]);
+            r[I2(i, j)] = (s + b[I2(i, j)]) - dg * u[I2(i, j)];
         }
 }
 
 void or_residual_field3d(int64_t nx, int64_t ny, int64_t nz, const double* u, const double* b,
-                         double* r)
+                         const double* wt, double* r)
 {
+    const double wy = wt[0], wz = wt[1], dg = wt[2];
     memset(r, 0, sizeof(double) * (size_t)(nx + 2) * (size_t)(ny + 2) * (size_t)(nz + 2));
 #pragma omp parallel for schedule(static)
     for (int64_t k = 1; k <= nz; ++k)
         for (int64_t i = 1; i <= ny; ++i)
             for (int64_t j = 1; j <= nx; ++j) {
                 double s = ((u[I3(k, i, j - 1)] + u[I3(k, i, j + 1)]) +
-                            (u[I3(k, i - 1, j)] + u[I3(k, i + 1, j)])) +
-                           (u[I3(k - 1, i, j)] + u[I3(k + 1, i, j)]);
-                r[I3(k, i, j)] = (s + b[I3(k, i, j)]) - 6.0 * u[I3(k, i, j)];
+                            wy * (u[I3(k, i - 1, j)] + u[I3(k, i + 1, j)])) +
+                           wz * (u[I3(k - 1, i, j)] + u[I3(k + 1, i, j)]);
+                r[I3(k, i, j)] = (s + b[I3(k, i, j)]) - dg * u[I3(k, i, j)];
             }
 }
 
 /* ------------------------------------------------- reduced-precision sweeps */
-/* Same association, evaluated in binary32.  c32 is the binary32 rounding of c. */
+/* Same association, evaluated in binary32.  c and the weights wt = {wy, wz, dg} are the
+ * binary32 roundings of their binary64 values. */
 
-void or_sweep2d_f32(int64_t nx, int64_t ny, const float* u, const float* b, float c, float* out)
+void or_sweep2d_f32(int64_t nx, int64_t ny, const float* u, const float* b, const float* wt, float c,
+                    float* out)
 {
+    const float wy = wt[0], dg = wt[2];
 #pragma omp parallel for schedule(static)
     for (int64_t i = 1; i <= ny; ++i)
         for (int64_t j = 1; j <= nx; ++j) {
-            float s = (u[I2(i, j - 1)] + u[I2(i, j + 1)]) + (u[I2(i - 1, j)] + u[I2(i + 1, j)]);
-            float t = (s + b[I2(i, j)]) - 4.0f * u[I2(i, j)];
+            float s = (u[I2(i, j - 1)] + u[I2(i, j + 1)]) + wy * (u[I2(i - 1, j)] + u[I2(i + 1, j)]);
+            float t = (s + b[I2(i, j)]) - dg * u[I2(i, j)];
             out[I2(i, j)] = u[I2(i, j)] + c * t;
         }
 }
 
-void or_sweep3d_f32(int64_t nx, int64_t ny, int64_t nz, const float* u, const float* b, float c,
-                    float* out)
+void or_sweep3d_f32(int64_t nx, int64_t ny, int64_t nz, const float* u, const float* b, const float* wt,
+                    float c, float* out)
 {
+    const float wy = wt[0], wz = wt[1], dg = wt[2];
 #pragma omp parallel for schedule(static)
     for (int64_t k = 1; k <= nz; ++k)
         for (int64_t i = 1; i <= ny; ++i)
             for (int64_t j = 1; j <= nx; ++j) {
                 float s = ((u[I3(k, i, j - 1)] + u[I3(k, i, j + 1)]) +
-                           (u[I3(k, i - 1, j)] + u[I3(k, i + 1, j)])) +
-                          (u[I3(k - 1, i, j)] + u[I3(k + 1, i, j)]);
-                float t = (s + b[I3(k, i, j)]) - 6.0f * u[I3(k, i, j)];
+                           wy * (u[I3(k, i - 1, j)] + u[I3(k, i + 1, j)])) +
+                          wz * (u[I3(k - 1, i, j)] + u[I3(k + 1, i, j)]);
+                float t = (s + b[I3(k, i, j)]) - dg * u[I3(k, i, j)];
                 out[I3(k, i, j)] = u[I3(k, i, j)] + c * t;
             }
 }
@@ -262,32 +277,34 @@ void or_bf16_to_f32(int64_t n, const uint16_t* in, float* out)
     for (int64_t i = 0; i < n; ++i) out[i] = bf_load(in[i]);
 }
 
-void or_sweep2d_bf16(int64_t nx, int64_t ny, const uint16_t* u, const uint16_t* b, float c,
+void or_sweep2d_bf16(int64_t nx, int64_t ny, const uint16_t* u, const uint16_t* b, const float* wt, float c,
                      uint16_t* out)
 {
+    const float wy = wt[0], dg = wt[2];
 #pragma omp parallel for schedule(static)
     for (int64_t i = 1; i <= ny; ++i)
         for (int64_t j = 1; j <= nx; ++j) {
             float s = (bf_load(u[I2(i, j - 1)]) + bf_load(u[I2(i, j + 1)])) +
-                      (bf_load(u[I2(i - 1, j)]) + bf_load(u[I2(i + 1, j)]));
+                      wy * (bf_load(u[I2(i - 1, j)]) + bf_load(u[I2(i + 1, j)]));
             float uc = bf_load(u[I2(i, j)]);
-            float t = (s + bf_load(b[I2(i, j)])) - 4.0f * uc;
+            float t = (s + bf_load(b[I2(i, j)])) - dg * uc;
             out[I2(i, j)] = bf_store(uc + c * t);
         }
 }
 
 void or_sweep3d_bf16(int64_t nx, int64_t ny, int64_t nz, const uint16_t* u, const uint16_t* b,
-                     float c, uint16_t* out)
+                     const float* wt, float c, uint16_t* out)
 {
+    const float wy = wt[0], wz = wt[1], dg = wt[2];
 #pragma omp parallel for schedule(static)
     for (int64_t k = 1; k <= nz; ++k)
         for (int64_t i = 1; i <= ny; ++i)
             for (int64_t j = 1; j <= nx; ++j) {
                 float s = ((bf_load(u[I3(k, i, j - 1)]) + bf_load(u[I3(k, i, j + 1)])) +
-                           (bf_load(u[I3(k, i - 1, j)]) + bf_load(u[I3(k, i + 1, j)]))) +
-                          (bf_load(u[I3(k - 1, i, j)]) + bf_load(u[I3(k + 1, i, j)]));
+                           wy * (bf_load(u[I3(k, i - 1, j)]) + bf_load(u[I3(k, i + 1, j)]))) +
+                          wz * (bf_load(u[I3(k - 1, i, j)]) + bf_load(u[I3(k + 1, i, j)]));
                 float uc = bf_load(u[I3(k, i, j)]);
-                float t = (s + bf_load(b[I3(k, i, j)])) - 6.0f * uc;
+                float t = (s + bf_load(b[I3(k, i, j)])) - dg * uc;
                 out[I3(k, i, j)] = bf_store(uc + c * t);
             }
 }

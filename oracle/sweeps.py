@@ -6,6 +6,10 @@ shape ``(n_y + 2, n_x + 2)`` in 2D or ``(n_z + 2, n_y + 2, n_x + 2)`` in 3D; ind
 
 Paper passages followed:
 * one step omega_i J -- Sec. 3.1, Eq. 2nd-order_CD (Poisson form, -lap u = f, b = h^2 f);
+  on a box whose axes have different spacings (the unit square of Sec. 5.1 cut into
+  585 x 280 zones) the equation is multiplied through by h_x^2: weight 1 on the x
+  neighbours, wy = h_x^2 / h_y^2 and wz = h_x^2 / h_z^2 on the others, diagonal
+  dg = 2 ((1 + wy) + wz), b = h_x^2 f and c = omega / dg (``axis_weights``);
 * the M-cycle, weight i applied q_i times, cycles repeated -- Sec. 2;
 * the residual used to stop: r = b - A u with A = 2d I - (sum of neighbours) in units
   of h^2; relres = ||r||_2 / ||b~||_2 with b~ the residual of the zero interior (source
@@ -36,32 +40,60 @@ def _c64(a):
     return a
 
 
+def _hx(h):
+    return float(h) if np.isscalar(h) else float(h[0])
+
+
+def axis_weights(h, ndim):
+    """wt = (wy, wz, dg) for spacing h: a number (every axis) or (h_x, h_y[, h_z]).
+    wy = h_x^2 / h_y^2, wz = h_x^2 / h_z^2 (1 in 2D), dg = 2 (1 + wy) in 2D and
+    2 ((1 + wy) + wz) in 3D; equal spacings give (1, 1, 2d) exactly."""
+    hs = (float(h),) * ndim if np.isscalar(h) else tuple(float(x) for x in h)
+    if len(hs) != ndim:
+        raise ValueError("one spacing per axis")
+    hxx = hs[0] * hs[0]
+    wy = hxx / (hs[1] * hs[1])
+    wz = hxx / (hs[2] * hs[2]) if ndim == 3 else 1.0
+    dg = 2.0 * (1.0 + wy) if ndim == 2 else 2.0 * ((1.0 + wy) + wz)
+    return np.array([wy, wz, dg], dtype=np.float64)
+
+
+def _wt(wt, ndim):
+    if wt is None:
+        return np.array([1.0, 1.0, 2.0 * ndim], dtype=np.float64)
+    return np.ascontiguousarray(wt, dtype=np.float64)
+
+
 def rhs(f, h):
-    """b = (h*h) * f on the interior, 0 on the ring (h*h is rounded once, then the product)."""
+    """b = (h_x*h_x) * f on the interior, 0 on the ring (h_x*h_x is rounded once, then the
+    product); h is the spacing of every axis or (h_x, h_y[, h_z])."""
     f = _c64(f)
-    hh = float(h) * float(h)
+    hh = _hx(h) * _hx(h)
     b = np.zeros_like(f)
     inner = tuple(slice(1, -1) for _ in range(f.ndim))
     b[inner] = hh * f[inner]
     return b
 
 
-def sweep(u, b, c):
-    """One weighted-Jacobi step with coefficient c = omega / (2d)  (Eq. 2nd-order_CD)."""
+def sweep(u, b, c, wt=None):
+    """One weighted-Jacobi step with coefficient c = omega / dg  (Eq. 2nd-order_CD); wt the
+    axis weights (default: equal spacings)."""
     u = _c64(u)
     b = _c64(b)
+    w = _wt(wt, u.ndim)
     out = u.copy()
     L = lib()
     d = _dims(u)
     if u.ndim == 2:
-        L.or_sweep2d(d[0], d[1], _p(u), _p(b), float(c), _p(out))
+        L.or_sweep2d(d[0], d[1], _p(u), _p(b), _p(w), float(c), _p(out))
     else:
-        L.or_sweep3d(d[0], d[1], d[2], _p(u), _p(b), float(c), _p(out))
+        L.or_sweep3d(d[0], d[1], d[2], _p(u), _p(b), _p(w), float(c), _p(out))
     return out
 
 
 def jacobi(u, b):
-    """One plain Jacobi step from its own definition, u' = (sum of neighbours + b) / (2d)."""
+    """One plain Jacobi step from its own definition, u' = (sum of neighbours + b) / (2d)
+    (equal spacings)."""
     u = _c64(u)
     b = _c64(b)
     out = u.copy()
@@ -74,57 +106,61 @@ def jacobi(u, b):
     return out
 
 
-def coefficients(omega_sequence, ndim):
-    """c_k = omega_k / (2d) for an ordered weight sequence (one IEEE division each)."""
+def coefficients(omega_sequence, ndim, wt=None):
+    """c_k = omega_k / dg for an ordered weight sequence (one IEEE division each; dg = 2d for
+    equal spacings)."""
     w = np.asarray(omega_sequence, dtype=np.float64)
-    return w / float(2 * ndim)
+    return w / float(_wt(wt, ndim)[2])
 
 
-def run(u, b, c_seq, nsweeps, k0=0):
+def run(u, b, c_seq, nsweeps, k0=0, wt=None):
     """Apply ``nsweeps`` scheduled steps; step s uses c_seq[(k0 + s) mod M] (Sec. 2)."""
     u = _c64(u).copy()
     b = _c64(b)
+    w = _wt(wt, u.ndim)
     c_seq = np.ascontiguousarray(c_seq, dtype=np.float64)
     work = u.copy()
     L = lib()
     d = _dims(u)
     if u.ndim == 2:
-        L.or_srj2d(d[0], d[1], _p(u), _p(b), _p(c_seq), len(c_seq), int(k0), int(nsweeps), _p(work))
+        L.or_srj2d(d[0], d[1], _p(u), _p(b), _p(w), _p(c_seq), len(c_seq), int(k0), int(nsweeps), _p(work))
     else:
-        L.or_srj3d(d[0], d[1], d[2], _p(u), _p(b), _p(c_seq), len(c_seq), int(k0), int(nsweeps),
+        L.or_srj3d(d[0], d[1], d[2], _p(u), _p(b), _p(w), _p(c_seq), len(c_seq), int(k0), int(nsweeps),
                    _p(work))
     return u
 
 
-def residual_norms(u, b):
+def residual_norms(u, b, wt=None):
     """(sum r^2, max |r|) of r = b - A u on the interior, compensated summation."""
     u = _c64(u)
     b = _c64(b)
+    w = _wt(wt, u.ndim)
     L = lib()
     d = _dims(u)
     out = np.zeros(2)
     if u.ndim == 2:
         rs = np.zeros(d[1])
         rm = np.zeros(d[1])
-        L.or_residual2d(d[0], d[1], _p(u), _p(b), _p(out), _p(rs), _p(rm))
+        L.or_residual2d(d[0], d[1], _p(u), _p(b), _p(w), _p(out), _p(rs), _p(rm))
     else:
         rs = np.zeros(d[1] * d[2])
         rm = np.zeros(d[1] * d[2])
-        L.or_residual3d(d[0], d[1], d[2], _p(u), _p(b), _p(out), _p(rs), _p(rm))
+        L.or_residual3d(d[0], d[1], d[2], _p(u), _p(b), _p(w), _p(out), _p(rs), _p(rm))
     return float(out[0]), float(out[1])
 
 
-def residual_field(u, b):
+def residual_field(u, b, wt=None):
     """r = b - A u on the interior, 0 on the ring."""
     u = _c64(u)
     b = _c64(b)
+    w = _wt(wt, u.ndim)
     r = np.empty_like(u)
     L = lib()
     d = _dims(u)
     if u.ndim == 2:
-        L.or_residual_field2d(d[0], d[1], _p(u), _p(b), _p(r))
+        L.or_residual_field2d(d[0], d[1], _p(u), _p(b), _p(w), _p(r))
     else:
-        L.or_residual_field3d(d[0], d[1], d[2], _p(u), _p(b), _p(r))
+        L.or_residual_field3d(d[0], d[1], d[2], _p(u), _p(b), _p(w), _p(r))
     return r
 
 
@@ -134,30 +170,32 @@ def zero_interior(u):
     return z
 
 
-def source_norm2(u, b):
+def source_norm2(u, b, wt=None):
     """||b~||_2^2: the squared residual of the state whose interior is zero."""
-    return residual_norms(zero_interior(u), b)[0]
+    return residual_norms(zero_interior(u), b, wt)[0]
 
 
-def relres(u, b, bt2=None):
+def relres(u, b, bt2=None, wt=None):
     if bt2 is None:
-        bt2 = source_norm2(u, b)
-    r2, _ = residual_norms(u, b)
+        bt2 = source_norm2(u, b, wt)
+    r2, _ = residual_norms(u, b, wt)
     return float(np.sqrt(r2) / np.sqrt(bt2)) if bt2 > 0 else 0.0
 
 
 def solve(u0, f, h, omega_sequence, tol, max_sweeps, history=False):
     """SRJ to a relative residual: checks at k = 0 and at every cycle end (k = 0 mod M).
 
-    Returns a dict with u, sweeps, relres, status ('ok' | 'noconv' | 'diverged') and, if
-    ``history``, the relres at every check.  Plain Jacobi is the one-weight schedule
-    [1.0] and is then checked after every sweep.
+    h is the spacing of every axis or one per axis (h_x, h_y[, h_z]).  Returns a dict with
+    u, sweeps, relres, status ('ok' | 'noconv' | 'diverged') and, if ``history``, the relres
+    at every check.  Plain Jacobi is the one-weight schedule [1.0] and is then checked after
+    every sweep.
     """
     u = _c64(u0).copy()
     b = rhs(f, h)
-    c_seq = coefficients(omega_sequence, u.ndim)
+    wt = axis_weights(h, u.ndim)
+    c_seq = coefficients(omega_sequence, u.ndim, wt)
     M = len(c_seq)
-    bt2 = source_norm2(u, b)
+    bt2 = source_norm2(u, b, wt)
     hist = []
     if bt2 == 0.0:
         # zero source and zero boundary: u = 0 is exact
@@ -165,7 +203,7 @@ def solve(u0, f, h, omega_sequence, tol, max_sweeps, history=False):
         return dict(u=u, sweeps=0, relres=0.0, status="ok", history=hist)
     k = 0
     while True:
-        r2, _ = residual_norms(u, b)
+        r2, _ = residual_norms(u, b, wt)
         rr = float(np.sqrt(r2) / np.sqrt(bt2))
         if history:
             hist.append(rr)
@@ -175,7 +213,7 @@ def solve(u0, f, h, omega_sequence, tol, max_sweeps, history=False):
             return dict(u=u, sweeps=k, relres=rr, status="ok", history=hist)
         if k + M > max_sweeps:
             return dict(u=u, sweeps=k, relres=rr, status="noconv", history=hist)
-        u = run(u, b, c_seq, M, k0=0)
+        u = run(u, b, c_seq, M, k0=0, wt=wt)
         k += M
 
 
@@ -196,33 +234,35 @@ def from_bf16_bits(h):
     return out
 
 
-def sweep_lo(u, b, c32, fmt):
-    """One step in binary32 arithmetic; storage binary32 ('f32') or bfloat16 bits ('bf16').
-    'f64' is the binary64 step itself (refinement with binary64 inner sweeps)."""
+def sweep_lo(u, b, c32, fmt, wt=None):
+    """One step in binary32 arithmetic; storage binary32 ('f32') or bfloat16 bits ('bf16'),
+    with the binary32 roundings of the axis weights.  'f64' is the binary64 step itself
+    (refinement with binary64 inner sweeps)."""
     if fmt == "f64":
-        return sweep(u, b, c32)
+        return sweep(u, b, c32, wt)
+    w32 = _wt(wt, u.ndim).astype(np.float32)
     L = lib()
     d = _dims(u)
     out = u.copy()
     if fmt == "f32":
         if u.ndim == 2:
-            L.or_sweep2d_f32(d[0], d[1], _p(u), _p(b), float(c32), _p(out))
+            L.or_sweep2d_f32(d[0], d[1], _p(u), _p(b), _p(w32), float(c32), _p(out))
         else:
-            L.or_sweep3d_f32(d[0], d[1], d[2], _p(u), _p(b), float(c32), _p(out))
+            L.or_sweep3d_f32(d[0], d[1], d[2], _p(u), _p(b), _p(w32), float(c32), _p(out))
     elif fmt == "bf16":
         if u.ndim == 2:
-            L.or_sweep2d_bf16(d[0], d[1], _p(u), _p(b), float(c32), _p(out))
+            L.or_sweep2d_bf16(d[0], d[1], _p(u), _p(b), _p(w32), float(c32), _p(out))
         else:
-            L.or_sweep3d_bf16(d[0], d[1], d[2], _p(u), _p(b), float(c32), _p(out))
+            L.or_sweep3d_bf16(d[0], d[1], d[2], _p(u), _p(b), _p(w32), float(c32), _p(out))
     else:
         raise ValueError(fmt)
     return out
 
 
-def lo_coefficients(omega_sequence, ndim, fmt="f32"):
+def lo_coefficients(omega_sequence, ndim, fmt="f32", wt=None):
     """Coefficients of the sweep format: the FP64 c_k, rounded once to binary32 unless the
     format is 'f64'."""
-    c = coefficients(omega_sequence, ndim)
+    c = coefficients(omega_sequence, ndim, wt)
     return c if fmt == "f64" else c.astype(np.float32)
 
 
@@ -250,15 +290,16 @@ def solve_ir(u0, f, h, omega_sequence, tol, inner_cycles, max_outer, fmt):
     """
     u = _c64(u0).copy()
     b = rhs(f, h)
-    c32 = lo_coefficients(omega_sequence, u.ndim, fmt)
+    wt = axis_weights(h, u.ndim)
+    c32 = lo_coefficients(omega_sequence, u.ndim, fmt, wt)
     M = len(c32)
-    bt2 = source_norm2(u, b)
+    bt2 = source_norm2(u, b, wt)
     inner = tuple(slice(1, -1) for _ in range(u.ndim))
     hist = []
     sweeps = 0
     for outer in range(max_outer + 1):
-        r = residual_field(u, b)
-        rr = float(np.sqrt(residual_norms(u, b)[0]) / np.sqrt(bt2)) if bt2 > 0 else 0.0
+        r = residual_field(u, b, wt)
+        rr = float(np.sqrt(residual_norms(u, b, wt)[0]) / np.sqrt(bt2)) if bt2 > 0 else 0.0
         hist.append(rr)
         if not np.isfinite(rr):
             return dict(u=u, outer=outer, sweeps=sweeps, relres=rr, status="diverged", history=hist)
@@ -269,7 +310,7 @@ def solve_ir(u0, f, h, omega_sequence, tol, inner_cycles, max_outer, fmt):
         rl = lo_cast(r, fmt)
         d = lo_cast(np.zeros_like(u), fmt)
         for s in range(inner_cycles * M):
-            d = sweep_lo(d, rl, c32[s % M], fmt)
+            d = sweep_lo(d, rl, c32[s % M], fmt, wt)
         sweeps += inner_cycles * M
         u[inner] = u[inner] + lo_widen(d, fmt)[inner]
     return dict(u=u, outer=max_outer, sweeps=sweeps, relres=hist[-1], status="noconv", history=hist)
