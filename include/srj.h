@@ -145,6 +145,21 @@ srj_status srj_sweeps(srj_plan_t plan, double* u, const double* f, int64_t k0, i
 srj_status srj_residual(srj_plan_t plan, const double* u, const double* f, double* r_out,
                         double norms[4]);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the residual norms of srj_residual for a
+ * grid described by grid (ndim, n, h; dtype ignored), computed from the caller's DEVICE
+ * arrays u and f (ABI layout) without a plan, without allocating and without synchronising:
+ * every launch goes on stream (a hipStream_t, NULL = default stream).  norms (DEVICE, 4
+ * doubles) receives ||r||_2, max |r|, ||b~||_2, relres when the stream reaches that point;
+ * r_out (DEVICE, full layout, may be NULL) receives r with a zero ring.  The results are
+ * bit-identical to srj_residual's.  Scratch: a 2 MiB array per GPU held by the library until
+ * the process ends (per-block partial sums, fully rewritten by every call), enough for grids
+ * of at most 524288 lines (n[1] in 2D, n[1] * n[2] in 3D); larger grids return SRJ_EINVAL
+ * before anything is launched.  Calls that overlap on one GPU (two streams, or two threads)
+ * race on that array: order them. */
+srj_status srj_residual_static(const srj_grid* grid, const double* u, const double* f, double* r_out,
+                               double* norms, void* stream);
+
 /* FP64 iterative refinement around the plan's low-precision sweeps (plan dtype F32 or
  * BF16; an F64 plan runs the same loop in binary64): repeat { r = b - A u (binary64);
  * stop if relres <= tol; d = inner_cycles SRJ cycles on A d = r from d = 0 with a zero

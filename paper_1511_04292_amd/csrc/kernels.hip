@@ -20,6 +20,7 @@
 #include "formats.h"
 #include "tb_core.h"
 #include "kernels.h"
+#include "reduce.h"
 
 namespace srj {
 
@@ -153,39 +154,6 @@ __global__ __launch_bounds__(1024) void k_sweep3d(const S* __restrict__ u, S* __
 }
 
 // ------------------------------------------------------------------ residuals
-
-__device__ __forceinline__ void nanmax(double& m, double a)
-{
-    if (a > m || a != a) m = a;
-}
-
-// Block reduction of (sum, max) over 256 threads; thread 0 returns the result.
-__device__ void block_reduce(double& s, double& m)
-{
-    __shared__ double ss[4], sm[4];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        double so = __shfl_xor(s, o, 64);
-        double mo = __shfl_xor(m, o, 64);
-        s = s + so;
-        nanmax(m, mo);
-    }
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-        ss[w] = s;
-        sm[w] = m;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        s = (ss[0] + ss[1]) + (ss[2] + ss[3]);
-        m = sm[0];
-        nanmax(m, sm[1]);
-        nanmax(m, sm[2]);
-        nanmax(m, sm[3]);
-    }
-}
-
-constexpr int kResRows = 8;  // rows (2D) or (k, i) lines (3D) per residual block
 
 template <class S>
 __device__ __forceinline__ double ldz(const S* u, int64_t p, bool zero)

@@ -62,7 +62,7 @@ EXPORTS = ["srj_plan", "srj_plan_destroy", "srj_plan_describe", "srj_plan_sequen
            "srj_plan_set_fusion", "srj_solve", "srj_sweeps", "srj_residual", "srj_solve_ir",
            "srj_schedule_optimal", "srj_schedule_order", "srj_status_string", "srj_last_error",
            "srj_adjoint", "srj_batch_plan", "srj_batch_solve", "srj_batch_destroy", "srj_plan_tune",
-           "srj_batch_tune"]
+           "srj_batch_tune", "srj_residual_static"]
 
 
 def lib():
@@ -83,6 +83,7 @@ def lib():
     L.srj_sweeps.argtypes = [vp, vp, vp, i64, i64, ctypes.POINTER(dbl)]
     L.srj_residual.argtypes = [vp, vp, vp, vp, ctypes.POINTER(dbl)]
     L.srj_solve_ir.argtypes = [vp, vp, vp, dbl, i32, i32, ctypes.POINTER(_Info)]
+    L.srj_residual_static.argtypes = [ctypes.POINTER(_Grid), vp, vp, vp, vp, vp]
     L.srj_adjoint.argtypes = [vp, vp, dbl, i64, vp, vp, ctypes.POINTER(_Info)]
     L.srj_batch_plan.argtypes = [i32, ctypes.POINTER(_Grid), ctypes.POINTER(_Schedule), vp, ctypes.POINTER(vp)]
     L.srj_batch_solve.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), dbl, i32, i32, ctypes.POINTER(_Info),
@@ -101,7 +102,8 @@ def lib():
     L.srj_last_error.restype = ctypes.c_char_p
     for name in ["srj_plan", "srj_plan_describe", "srj_plan_sequence", "srj_plan_set_fusion", "srj_solve",
                  "srj_sweeps", "srj_residual", "srj_solve_ir", "srj_schedule_optimal", "srj_schedule_order",
-                 "srj_adjoint", "srj_batch_plan", "srj_batch_solve", "srj_plan_tune", "srj_batch_tune"]:
+                 "srj_adjoint", "srj_batch_plan", "srj_batch_solve", "srj_plan_tune", "srj_batch_tune",
+                 "srj_residual_static"]:
         getattr(L, name).restype = i32
     _lib = L
     return L
@@ -238,6 +240,24 @@ def srj_residual(plan, u, f, r_out=None):
     rp = _dptr(r_out, plan.full_shape) if r_out is not None else None
     _check(lib().srj_residual(plan.handle, _dptr(u, plan.full_shape), _dptr(f, plan.full_shape), rp, norms))
     return dict(l2=norms[0], linf=norms[1], source_l2=norms[2], relres=norms[3])
+
+
+def srj_residual_static(n, h, u, f, norms, r_out=None, stream=None):
+    """Residual norms of u without a plan and without allocating device memory: writes
+    (||r||_2, max |r|, ||b~||_2, relres) into the device tensor norms (4 float64) on the
+    stream, asynchronously; r_out (optional) receives r with a zero ring."""
+    g = _Grid()
+    g.ndim = len(n)
+    for i, v in enumerate(n):
+        g.n[i] = int(v)
+    g.h = float(h)
+    g.dtype = SRJ_F64
+    shape = tuple(x + 2 for x in reversed(tuple(n)))
+    if norms.numel() < 4:
+        raise ValueError("norms needs 4 elements")
+    st = stream if stream is not None else _stream_handle()
+    _check(lib().srj_residual_static(ctypes.byref(g), _dptr(u, shape), _dptr(f, shape),
+                                     _dptr(r_out, shape) if r_out is not None else None, _dptr(norms), st))
 
 
 def srj_solve_ir(plan, u, f, tol, inner_cycles, max_outer):
