@@ -9,15 +9,19 @@
  * weights; Sec. 4.3 the integer counts; Sec. 5.1 the Dirichlet Poisson setting and the
  * need to spread the large weights over the cycle.
  *
- * Problem solved:  -lap(u) = f  on a box of n_i interior points per axis with equal
- * spacing h on every axis and Dirichlet data on the ring of points around the box.
- * With b = (h*h) f, one step with weight w (c = w / (2d)) is
- *     u' = u + c * ( (sum of the 2d neighbours + b) - 2d u ),
- * evaluated with the fixed association ((W+E)+(S+N))[+(D+U)], then + b, then - 2d u,
- * then u + c*t, each operation rounded on its own (in 2D the kernels form "- 4u" with a
- * fused multiply-add, which is the same value since 4u is exact).  The residual r = b - A u (A = 2d I minus
- * the neighbour sum, units of h^2) is the t of that step; relres = ||r||_2 / ||b~||_2,
- * b~ being the residual of the state with a zero interior (source plus boundary terms).
+ * Problem solved:  -lap(u) = f  on a box of n_i interior points per axis with spacing h_i
+ * on axis i and Dirichlet data on the ring of points around the box (Sec. 5.1).  The
+ * equation is multiplied through by h_x^2: weight 1 on the x neighbours, wy = h_x^2/h_y^2,
+ * wz = h_x^2/h_z^2 on the others, diagonal dg = 2(1 + wy) in 2D, 2((1 + wy) + wz) in 3D
+ * (2d when the spacings are equal).  With b = (h_x*h_x) f, one step with weight w
+ * (c = w / dg) is
+ *     u' = u + c * ( ((W+E) + wy (S+N) [+ wz (D+U)] + b) - dg u ),
+ * evaluated in that association, then + b, then - dg u, then u + c*t, each operation
+ * rounded on its own (with equal spacings the kernels form "- 4u" in 2D with a fused
+ * multiply-add, which is the same value since 4u is exact).  The residual r = b - A u
+ * (A = dg I minus the weighted neighbour sum) is the t of that step;
+ * relres = ||r||_2 / ||b~||_2, b~ being the residual of the state with a zero interior
+ * (source plus boundary terms).  Plans with unequal spacings run one sweep per launch.
  *
  * Array layout at the ABI: dense, row-major, x fastest, ring included:
  *   2D: (n[1] + 2) rows of (n[0] + 2) doubles;  3D: (n[2]+2) x (n[1]+2) x (n[0]+2).
@@ -59,17 +63,24 @@ typedef enum { SRJ_F64 = 0, SRJ_F32 = 1, SRJ_BF16 = 2 } srj_dtype;
 typedef struct {
     int32_t ndim;     /* 2 or 3 */
     int64_t n[3];     /* interior points per axis, n[0] = x (fastest); n[2] unused in 2D */
-    double h;         /* grid spacing, equal on every axis (unit box: 1 / (n + 1)) */
+    double h[3];      /* spacing per axis, h[0] = x (unit box: 1 / (n_i + 1)); h[2] unused in 2D */
     int32_t dtype;    /* srj_dtype of the sweeps */
 } srj_grid;
 
 /* Schedule request (Sec. 2-4).
- *  omega == NULL: optimise P levels (Sec. 3) on [kappa_min, 2] (Eq. boundaries), counts
- *    q_i = floor(beta_i / beta_1) (Sec. 4.3).  kappa_min == 0 takes the exact smallest
- *    Jacobi symbol of the grid, (2/d) sum_i sin^2(pi / (2 (n_i + 1))) (Eq.
- *    effectiveNDirichlet with N_i = n_i + 1 zones); kappa_min > 0 uses the value given
- *    (e.g. sin^2(pi / 2N) of a Neumann table row, Eq. boundaries).
- *  omega != NULL: P explicit weights, strictly descending, with P counts q >= 1.
+ *  omega == NULL: optimise P levels (Sec. 3) on [kappa_min, 2] (Eq. boundaries).
+ *    The lower end: kappa_min > 0 as given; else n_eff > 0 takes the Neumann table row of
+ *    resolution N = n_eff, sin^2(pi / (2 N)) (Eq. boundaries; e.g. the rows N = 550 and
+ *    N = 250 of Sec. 5.1); else (both 0) the exact smallest Jacobi symbol of the grid,
+ *    (2/d) sum_i sin^2(pi / (2 (n_i + 1))) with equal spacings (Eq. effectiveNDirichlet with
+ *    N_i = n_i + 1 zones), 4 (s_x + wy s_y [+ wz s_z]) / dg otherwise.  Giving both is an error.
+ *    Counts from the fractions (Sec. 4.3), q_rounding: 0 floor(beta_i / beta_1) (the
+ *    paper's choice), 1 nearest integer, 2 ceiling, 3 floor or ceiling per level, whichever
+ *    combination has the smallest per-step factor max |prod (1 - w_i k)^q_i|^(1/M) over
+ *    [kappa_min, 2] (P <= 12; exact ties to fewer ceilings, then to the earlier combination
+ *    in binary order with level 2 the lowest bit).  q_1 = 1 in every mode.
+ *  omega != NULL: P explicit weights, strictly descending, with P counts q >= 1 (n_eff and
+ *    kappa_min then only set the interval the order is built on; q_rounding is ignored).
  *  ordering: 0 balanced greedy order of the M steps (default), 1 even spread of each
  *    weight over the cycle (Sec. 5.1), 2 explicit: sequence[0..M) of level indices. */
 typedef struct {
@@ -77,6 +88,8 @@ typedef struct {
     const double* omega;
     const int64_t* q;
     double kappa_min;
+    double n_eff;
+    int32_t q_rounding;
     int32_t ordering;
     const int32_t* sequence;
     int64_t M;
@@ -108,10 +121,11 @@ typedef struct {
 typedef struct srj_plan_s* srj_plan_t;
 
 /* Create a plan: validates the grid, builds the schedule and its coefficient sequence
- * c_k = w_k / (2d),
- * allocates the plan-owned device buffers (two iterate buffers in the sweep format, the
- * scaled source, reduction scratch).  Returns SRJ_ESCHEDULE if the optimiser fails or
- * the integer scheme is not convergent on the grid's spectrum. */
+ * c_k = w_k / dg, allocates the plan-owned device buffers (two iterate buffers in the sweep
+ * format, the scaled source in the sweep format and in binary64, a binary64 iterate for
+ * refinement and residual evaluation, reduction scratch): solves, sweeps, residuals and
+ * refinement then allocate nothing.  Returns SRJ_ESCHEDULE if the optimiser fails or the
+ * integer scheme is not convergent on the grid's spectrum. */
 srj_status srj_plan(const srj_grid* grid, const srj_schedule* schedule, void* stream,
                     srj_plan_t* out);
 void srj_plan_destroy(srj_plan_t plan);
@@ -161,7 +175,8 @@ srj_status srj_residual_static(const srj_grid* grid, const double* u, const doub
                                double* norms, void* stream);
 
 /* FP64 iterative refinement around the plan's low-precision sweeps (plan dtype F32 or
- * BF16; an F64 plan runs the same loop in binary64): repeat { r = b - A u (binary64);
+ * BF16; an F64 plan runs the same loop with binary64 sweeps, its inner right-hand side kept
+ * apart from b): repeat { r = b - A u (binary64);
  * stop if relres <= tol; d = inner_cycles SRJ cycles on A d = r from d = 0 with a zero
  * ring, in the plan's format; u += d (binary64) } at most max_outer times. */
 srj_status srj_solve_ir(srj_plan_t plan, double* u, const double* f, double tol,
@@ -173,10 +188,11 @@ srj_status srj_solve_ir(srj_plan_t plan, double* u, const double* f, double tol,
  * each point) (Sec. 5.1 setting).  Given grad_u = dL/du (device, full layout) this solves
  * A lambda = (interior of grad_u) with the plan's schedule and stopping rule (zero ring,
  * zero start), then writes
- *     df = h^2 lambda on the interior, 0 on the ring;
- *     dg = grad_u + (lambda at the interior neighbour) on each ring cell -- the neighbour
- *          term is absent on ring cells no stencil reads (2D corners; 3D edges and
- *          corners) -- and 0 on the interior.
+ *     df = h_x^2 lambda on the interior, 0 on the ring;
+ *     dg = grad_u + (axis weight) * (lambda at the interior neighbour) on each ring cell --
+ *          the weight of the axis along which the neighbour reads it (1, wy or wz); the
+ *          neighbour term is absent on ring cells no stencil reads (2D corners; 3D edges
+ *          and corners) -- and 0 on the interior.
  * df or dg may be NULL.  No forward iterate is needed or stored.  FP64 plans only.
  * Status as srj_solve. */
 srj_status srj_adjoint(srj_plan_t plan, const double* grad_u, double tol, int64_t max_sweeps,
@@ -192,8 +208,9 @@ srj_status srj_adjoint(srj_plan_t plan, const double* grad_u, double tol, int64_
  * internal stream (the plan's stream is synchronised first).  Problems never wait on one
  * another; finished problems drop out of the work list. */
 typedef struct srj_batch_s* srj_batch_t;
-/* grids[count], schedules[count] as for srj_plan (ndim must be 2, one dtype for all).  The
- * batch owns all device buffers (about 3 FP64 + 3 sweep-format fields per problem). */
+/* grids[count], schedules[count] as for srj_plan (ndim must be 2 with h[0] == h[1], one
+ * dtype for all).  The batch owns all device buffers (about 3 FP64 + 3 sweep-format fields
+ * per problem). */
 srj_status srj_batch_plan(int32_t count, const srj_grid* grids, const srj_schedule* schedules,
                           void* stream, srj_batch_t* out);
 /* u[j], f[j]: device FP64 arrays of problem j in the ABI layout (u in/out).  infos[j] (may be
@@ -234,6 +251,11 @@ srj_status srj_batch_tune(srj_batch_t batch, srj_tune_info* info);
  * interior maxima of Gamma. */
 srj_status srj_schedule_optimal(int32_t P, double kappa_min, double kappa_max, double* omega,
                                 double* beta, int64_t* q, double* kappa);
+/* Integer counts q[0..P) from fractions beta (Sec. 4.3), rounding mode as srj_schedule's
+ * q_rounding (0 floor, 1 nearest, 2 ceiling, 3 best floor/ceiling combination on
+ * [kappa_min, kappa_max] for the weights omega, P <= 12; omega may be NULL for modes 0-2). */
+srj_status srj_schedule_counts(int32_t P, const double* beta, const double* omega, double kappa_min,
+                               double kappa_max, int32_t q_rounding, int64_t* q);
 /* Order of the M steps for weights omega / counts q (ordering 0 balanced, 1 even). */
 srj_status srj_schedule_order(int32_t P, const double* omega, const int64_t* q, double kappa_min,
                               double kappa_max, int32_t ordering, int32_t* seq);

@@ -49,10 +49,23 @@ def kappa_min_neumann(N, d=2):
     return (2.0 / d) * math.sin(math.pi / (2.0 * N)) ** 2
 
 
-def kappa_min_dirichlet(n_interior):
-    """(2/d) sum_i sin^2(pi / (2 N_i)) with N_i = n_i + 1 zones (Eq. effectiveNDirichlet)."""
+def kappa_min_dirichlet(n_interior, h=None):
+    """(2/d) sum_i sin^2(pi / (2 N_i)) with N_i = n_i + 1 zones (Eq. effectiveNDirichlet).
+
+    With one spacing per axis, h = (h_x, h_y[, h_z]) in the order of n_interior, the
+    equation multiplied through by h_x^2 has axis weights a = (1, h_x^2/h_y^2, h_x^2/h_z^2)
+    and diagonal dg = 2 sum a_i; the smallest symbol is then 4 sum_i a_i sin^2(..) / dg."""
     d = len(n_interior)
-    return (2.0 / d) * sum(math.sin(math.pi / (2.0 * (n + 1))) ** 2 for n in n_interior)
+    if h is None:
+        return (2.0 / d) * sum(math.sin(math.pi / (2.0 * (n + 1))) ** 2 for n in n_interior)
+    from .sweeps import axis_weights
+
+    wy, wz, dg = axis_weights(h, d)
+    a = (1.0, float(wy), float(wz))
+    s = 0.0
+    for i, n in enumerate(n_interior):
+        s = s + a[i] * (math.sin(math.pi / (2.0 * (n + 1))) ** 2)
+    return (4.0 * s) / float(dg)
 
 
 def n_eff(zones):
@@ -247,6 +260,48 @@ def q_floor(beta):
     """q_i = floor(beta_i / beta_1)  (Sec. 4.3)."""
     beta = np.asarray(beta, dtype=np.float64)
     return np.floor(beta / beta[0]).astype(np.int64)
+
+
+def q_counts(beta, mode, w=None, km=None, kM=KAPPA_M, G=4096):
+    """Integer counts from the fractions (Sec. 4.3; the paper tries floor, rounding to the
+    nearest integer, ceiling and per-level mixtures of them).  q_1 = 1 always.
+      mode 0: floor(beta_i / beta_1);  1: nearest integer (floor(x + 1/2));  2: ceiling;
+      3: every combination of floor and ceiling per level (levels whose ratio is an integer
+         have one choice), keeping the one with the smallest per-step factor
+         max over the log-spaced grid of [km, kM] of sum_i q_i log|1 - w_i k| / M; exact
+         ties to fewer ceilings, then to the earlier combination in binary order (level 2
+         the lowest bit).  An exhaustive search, for P <= 12."""
+    beta = np.asarray(beta, dtype=np.float64)
+    r = beta / beta[0]
+    fl = np.floor(r).astype(np.int64)
+    ce = np.ceil(r).astype(np.int64)
+    fl[0] = ce[0] = 1
+    if mode == 0:
+        return fl
+    if mode == 2:
+        return ce
+    if mode == 1:
+        q = np.floor(r + 0.5).astype(np.int64)
+        q[0] = 1
+        return q
+    if mode != 3:
+        raise ValueError("mode must be 0..3")
+    free = [i for i in range(1, len(r)) if ce[i] != fl[i]]
+    grid = balanced_grid(km, kM, G)
+    L = [[math.log(abs(1.0 - float(w[i]) * k)) for k in grid] for i in range(len(r))]
+    best, best_rate, best_ceils = fl, None, None
+    for mask in range(1 << len(free)):
+        q = fl.copy()
+        for b, lv in enumerate(free):
+            if mask & (1 << b):
+                q[lv] = ce[lv]
+        ceils = bin(mask).count("1")
+        M = int(np.sum(q))
+        mx = max(sum(float(q[i]) * L[i][g] for i in range(len(r))) for g in range(len(grid)))
+        rate = mx / M
+        if best_rate is None or rate < best_rate or (rate == best_rate and ceils < best_ceils):
+            best, best_rate, best_ceils = q, rate, ceils
+    return best
 
 
 def gamma_q_max(w, q, kappa_grid):

@@ -13,6 +13,7 @@
 #include "../../include/srj.h"
 #include "kernels.h"
 #include "planner.h"
+#include "schedule_build.h"
 
 using namespace srj;
 
@@ -47,10 +48,94 @@ struct DField {
 namespace srj {
 // Error reporting shared with the batched entry points.
 srj_status report(srj_status s, const std::string& msg) { return fail(s, msg); }
+
+srj_status make_schedule(int d, const int64_t* n, const double* wt, const srj_schedule* sc, bool peaks,
+                         SchedOut* out, std::string* err)
+{
+    auto bad = [&](srj_status st, const std::string& m) {
+        *err = m;
+        return st;
+    };
+    const double kmax_grid = grid_kappa_max(d, n, wt);
+    if (sc->kappa_min > 0 && sc->n_eff > 0) return bad(SRJ_EINVAL, "give kappa_min or n_eff, not both");
+    if (sc->kappa_min < 0 || sc->n_eff < 0 || !std::isfinite(sc->kappa_min) || !std::isfinite(sc->n_eff))
+        return bad(SRJ_EINVAL, "kappa_min and n_eff must be finite and >= 0");
+    if (sc->n_eff > 0 && !(sc->n_eff > 1)) return bad(SRJ_EINVAL, "n_eff must exceed 1");
+    if (sc->kappa_min > 0) {
+        out->kappa_min = sc->kappa_min;
+    } else if (sc->n_eff > 0) {
+        // the Neumann table row for resolution N (Eq. boundaries): sin^2(pi / (2N))
+        const double v = std::sin(3.14159265358979323846 / (2.0 * sc->n_eff));
+        out->kappa_min = v * v;
+    } else {
+        out->kappa_min = grid_kappa_min(d, n, wt);
+    }
+    out->kappa_max = 2.0;
+    if (!(out->kappa_min < out->kappa_max)) return bad(SRJ_EINVAL, "kappa_min must be below 2");
+    if (sc->P < 1 || sc->P > SRJ_MAX_LEVELS) return bad(SRJ_EINVAL, "P must be in [1, 16]");
+    if (sc->q_rounding < 0 || sc->q_rounding > 3) return bad(SRJ_EINVAL, "q_rounding must be 0, 1, 2 or 3");
+    const int P = sc->P;
+    out->P = P;
+    if (sc->omega) {
+        if (!sc->q) return bad(SRJ_EINVAL, "explicit weights need counts q");
+        for (int i = 0; i < P; ++i) {
+            if (!std::isfinite(sc->omega[i]) || sc->omega[i] <= 0) return bad(SRJ_EINVAL, "weights must be positive");
+            if (i > 0 && !(sc->omega[i] < sc->omega[i - 1]))
+                return bad(SRJ_EINVAL, "weights must be strictly descending");
+            if (sc->q[i] < 1) return bad(SRJ_EINVAL, "counts must be >= 1");
+            out->omega[i] = sc->omega[i];
+            out->q[i] = sc->q[i];
+            out->beta[i] = 0.0;
+        }
+    } else {
+        Optimum o;
+        std::string e2;
+        if (!optimal_schedule(P, out->kappa_min, out->kappa_max, &o, &e2))
+            return bad(SRJ_ESCHEDULE, "schedule optimiser: " + e2);
+        if (sc->q_rounding == 3 && P > 12) return bad(SRJ_EINVAL, "q_rounding 3 needs P <= 12");
+        std::vector<int64_t> qq = round_counts(o.beta, sc->q_rounding, o.w.data(), out->kappa_min, out->kappa_max);
+        if ((int)qq.size() != P) return bad(SRJ_EINVAL, "integer counts could not be formed");
+        for (int i = 0; i < P; ++i) {
+            out->omega[i] = o.w[i];
+            out->beta[i] = o.beta[i];
+            out->q[i] = qq[i];
+        }
+    }
+    out->M = 0;
+    for (int i = 0; i < P; ++i) out->M += out->q[i];
+    if (sc->ordering == 2) {
+        if (!sc->sequence || sc->M != out->M) return bad(SRJ_EINVAL, "explicit sequence must have M entries");
+        std::vector<int64_t> cnt(P, 0);
+        for (int64_t k = 0; k < out->M; ++k) {
+            const int32_t i = sc->sequence[k];
+            if (i < 0 || i >= P) return bad(SRJ_EINVAL, "sequence index out of range");
+            cnt[i]++;
+        }
+        for (int i = 0; i < P; ++i)
+            if (cnt[i] != out->q[i]) return bad(SRJ_EINVAL, "sequence counts differ from q");
+        out->seq.assign(sc->sequence, sc->sequence + out->M);
+    } else if (sc->ordering == 0 || sc->ordering == 1) {
+        out->seq = order_steps(P, out->omega, out->q, out->kappa_min, out->kappa_max, sc->ordering);
+    } else {
+        return bad(SRJ_EINVAL, "ordering must be 0, 1 or 2");
+    }
+    // convergence of the integer scheme on the grid's own spectrum (Sec. 4.3)
+    out->gamma_q = gamma_q_max(P, out->omega, out->q, out->kappa_min,
+                               std::max(kmax_grid, out->kappa_min * 1.0000001));
+    if (!(out->gamma_q < 1.0))
+        return bad(SRJ_ESCHEDULE, "integer scheme not convergent: max Gamma_q = " + std::to_string(out->gamma_q));
+    if (peaks) partial_peaks(P, out->omega, out->seq, out->kappa_min, out->kappa_max, &out->pre, &out->suf);
+    double r = 0;
+    for (int i = 0; i < P; ++i) r += out->omega[i] * (double)out->q[i];
+    out->rho = r / (double)out->M;
+    return SRJ_OK;
+}
 }  // namespace srj
 
 struct srj_plan_s {
     srj_grid grid{};
+    bool iso = true;  // equal spacings: the temporally blocked kernels apply
+    double hh = 0;    // h_x^2, the scale of b
     Fmt fmt = FMT_F64;
     hipStream_t stream = nullptr;
     Geo geo{};
@@ -104,63 +189,25 @@ bool is_finite(double x) { return std::isfinite(x); }
 
 srj_status build_schedule(srj_plan_t p, const srj_schedule* sc)
 {
-    const int d = p->grid.ndim;
-    const double kmax_grid = grid_kappa_max(d, p->grid.n);
-    p->kappa_min = sc->kappa_min > 0 ? sc->kappa_min : grid_kappa_min(d, p->grid.n);
-    p->kappa_max = 2.0;
-    if (sc->P < 1 || sc->P > SRJ_MAX_LEVELS) return fail(SRJ_EINVAL, "P must be in [1, 16]");
-    p->P = sc->P;
-    if (sc->omega) {
-        if (!sc->q) return fail(SRJ_EINVAL, "explicit weights need counts q");
-        for (int i = 0; i < p->P; ++i) {
-            if (!is_finite(sc->omega[i]) || sc->omega[i] <= 0) return fail(SRJ_EINVAL, "weights must be positive");
-            if (i > 0 && !(sc->omega[i] < sc->omega[i - 1]))
-                return fail(SRJ_EINVAL, "weights must be strictly descending");
-            if (sc->q[i] < 1) return fail(SRJ_EINVAL, "counts must be >= 1");
-            p->omega[i] = sc->omega[i];
-            p->q[i] = sc->q[i];
-            p->beta[i] = 0.0;
-        }
-    } else {
-        Optimum o;
-        std::string err;
-        if (!optimal_schedule(p->P, p->kappa_min, p->kappa_max, &o, &err))
-            return fail(SRJ_ESCHEDULE, "schedule optimiser: " + err);
-        std::vector<int64_t> qq = floor_counts(o.beta);
-        for (int i = 0; i < p->P; ++i) {
-            p->omega[i] = o.w[i];
-            p->beta[i] = o.beta[i];
-            p->q[i] = qq[i];
-        }
-    }
-    p->M = 0;
-    for (int i = 0; i < p->P; ++i) p->M += p->q[i];
-    if (sc->ordering == 2) {
-        if (!sc->sequence || sc->M != p->M) return fail(SRJ_EINVAL, "explicit sequence must have M entries");
-        std::vector<int64_t> cnt(p->P, 0);
-        for (int64_t k = 0; k < p->M; ++k) {
-            int32_t i = sc->sequence[k];
-            if (i < 0 || i >= p->P) return fail(SRJ_EINVAL, "sequence index out of range");
-            cnt[i]++;
-        }
-        for (int i = 0; i < p->P; ++i)
-            if (cnt[i] != p->q[i]) return fail(SRJ_EINVAL, "sequence counts differ from q");
-        p->seq.assign(sc->sequence, sc->sequence + p->M);
-    } else if (sc->ordering == 0 || sc->ordering == 1) {
-        p->seq = order_steps(p->P, p->omega, p->q, p->kappa_min, p->kappa_max, sc->ordering);
-    } else {
-        return fail(SRJ_EINVAL, "ordering must be 0, 1 or 2");
-    }
-    // convergence of the integer scheme on the grid's own spectrum (Sec. 4.3)
-    p->gamma_q = gamma_q_max(p->P, p->omega, p->q, p->kappa_min, std::max(kmax_grid, p->kappa_min * 1.0000001));
-    if (!(p->gamma_q < 1.0))
-        return fail(SRJ_ESCHEDULE, "integer scheme not convergent: max Gamma_q = " + std::to_string(p->gamma_q));
-    partial_peaks(p->P, p->omega, p->seq, p->kappa_min, p->kappa_max, &p->pre, &p->suf);
-    double r = 0;
-    for (int i = 0; i < p->P; ++i) r += p->omega[i] * (double)p->q[i];
-    p->rho = r / (double)p->M;
+    SchedOut o;
+    std::string err;
+    const double wt[3] = {p->geo.wy, p->geo.wz, p->geo.dg};
+    srj_status st = make_schedule(p->grid.ndim, p->grid.n, p->iso ? nullptr : wt, sc, true, &o, &err);
+    if (st != SRJ_OK) return fail(st, err);
+    p->P = o.P;
+    std::memcpy(p->omega, o.omega, sizeof(o.omega));
+    std::memcpy(p->beta, o.beta, sizeof(o.beta));
+    std::memcpy(p->q, o.q, sizeof(o.q));
+    p->M = o.M;
+    p->seq = std::move(o.seq);
+    p->kappa_min = o.kappa_min;
+    p->kappa_max = o.kappa_max;
+    p->rho = o.rho;
+    p->gamma_q = o.gamma_q;
+    p->pre = o.pre;
+    p->suf = o.suf;
     p->cseq.resize(p->M);
-    for (int64_t k = 0; k < p->M; ++k) p->cseq[k] = p->omega[p->seq[k]] / (double)(2 * d);
+    for (int64_t k = 0; k < p->M; ++k) p->cseq[k] = p->omega[p->seq[k]] / p->geo.dg;
     return SRJ_OK;
 }
 
@@ -312,26 +359,32 @@ srj_status srj_plan(const srj_grid* grid, const srj_schedule* schedule, void* st
     if (!grid || !schedule || !out) return fail(SRJ_EINVAL, "null argument");
     *out = nullptr;
     if (grid->ndim != 2 && grid->ndim != 3) return fail(SRJ_EINVAL, "ndim must be 2 or 3");
-    for (int i = 0; i < grid->ndim; ++i)
+    for (int i = 0; i < grid->ndim; ++i) {
         if (grid->n[i] < 1 || grid->n[i] > (1 << 20)) return fail(SRJ_EINVAL, "n must be in [1, 2^20]");
-    if (!(grid->h > 0) || !is_finite(grid->h)) return fail(SRJ_EINVAL, "h must be positive");
+        if (!(grid->h[i] > 0) || !is_finite(grid->h[i])) return fail(SRJ_EINVAL, "every h[i] must be positive");
+    }
     if (grid->dtype < 0 || grid->dtype > 2) return fail(SRJ_EINVAL, "dtype must be 0, 1 or 2");
     srj_plan_t p = new (std::nothrow) srj_plan_s();
     if (!p) return fail(SRJ_ENOMEM, "host allocation failed");
     p->grid = *grid;
-    if (grid->ndim == 2) p->grid.n[2] = 1;
+    if (grid->ndim == 2) {
+        p->grid.n[2] = 1;
+        p->grid.h[2] = grid->h[0];
+    }
     p->fmt = (Fmt)grid->dtype;
     p->stream = (hipStream_t)stream;
-    srj_status st = build_schedule(p, schedule);
-    if (st != SRJ_OK) {
-        destroy(p);
-        return st;
-    }
     Geo& g = p->geo;
     g.ndim = grid->ndim;
     g.nx = grid->n[0];
     g.ny = grid->n[1];
     g.nz = grid->ndim == 3 ? grid->n[2] : 1;
+    geo_set_weights(g, p->grid.h, &p->iso);
+    p->hh = p->grid.h[0] * p->grid.h[0];
+    srj_status st = build_schedule(p, schedule);
+    if (st != SRJ_OK) {
+        destroy(p);
+        return st;
+    }
     // pitch: multiple of 512 bytes for the narrowest format used (bf16 -> 256 elements)
     const int64_t ae = kAlignBytes / 2;
     g.px = ((g.nx + 2 + ae - 1) / ae) * ae;
@@ -365,9 +418,11 @@ srj_status srj_plan(const srj_grid* grid, const srj_schedule* schedule, void* st
         return fail(SRJ_EHIP, "initial fill failed");
     }
     // 3D: 5 sweeps per launch for the 4- and 2-byte formats, 4 for binary64 (at 5 its
-    // registers spill and the launch is slower per sweep)
-    p->fuse = (g.ndim == 2) ? kMaxFuse
-                            : (fused3d_fits(g, p->fmt) ? (p->fmt == FMT_F64 ? kMaxFuse3d - 1 : kMaxFuse3d) : 0);
+    // registers spill and the launch is slower per sweep); unequal spacings: one sweep per
+    // launch (the temporally blocked kernels implement the equal-spacing operator only)
+    p->fuse = !p->iso ? 0
+                      : (g.ndim == 2) ? kMaxFuse
+                                      : (fused3d_fits(g, p->fmt) ? (p->fmt == FMT_F64 ? kMaxFuse3d - 1 : kMaxFuse3d) : 0);
     *out = p;
     return SRJ_OK;
 }
@@ -412,6 +467,7 @@ srj_status srj_plan_set_fusion(srj_plan_t p, int32_t fused, int32_t seg_rows)
     if (!p) return fail(SRJ_EINVAL, "null plan");
     if (fused < 0 || fused > kMaxFuse) return fail(SRJ_EINVAL, "fusion depth must be in [0, 10]");
     if (p->geo.ndim == 3 && fused > kMaxFuse3d) return fail(SRJ_EINVAL, "3D fusion depth must be in [0, 5]");
+    if (fused > 0 && !p->iso) return fail(SRJ_EINVAL, "fused sweeps need equal spacings on every axis");
     if (p->geo.ndim == 3 && fused > 0 && !fused3d_fits(p->geo, p->fmt))
         return fail(SRJ_EINVAL, "z planes too large for the fused 3D kernel (1 GiB per plane at most)");
     if (seg_rows < 0 || seg_rows > (1 << 20)) return fail(SRJ_EINVAL, "segment rows must be in [0, 2^20]");
@@ -423,7 +479,7 @@ srj_status srj_plan_set_fusion(srj_plan_t p, int32_t fused, int32_t seg_rows)
 srj_status srj_residual(srj_plan_t p, const double* u, const double* f, double* r_out, double norms[4])
 {
     if (!p || !u || !f || !norms) return fail(SRJ_EINVAL, "null argument");
-    const double hh = p->grid.h * p->grid.h;
+    const double hh = p->hh;
     srj_status st;
     // u goes to the plan's binary64 iterate field; b to b64 (and blo, as a solve would)
     HIPCHK(launch_copy_in(FMT_F64, u, p->x64.origin, p->geo, p->stream));
@@ -443,7 +499,7 @@ srj_status srj_sweeps(srj_plan_t p, double* u, const double* f, int64_t k0, int6
 {
     if (!p || !u || !f) return fail(SRJ_EINVAL, "null argument");
     if (k0 < 0 || n < 0) return fail(SRJ_EINVAL, "k0 and nsweeps must be >= 0");
-    const double hh = p->grid.h * p->grid.h;
+    const double hh = p->hh;
     HIPCHK(launch_copy_in(p->fmt, u, p->A.origin, p->geo, p->stream));
     HIPCHK(launch_copy_in(p->fmt, u, p->B.origin, p->geo, p->stream));
     HIPCHK(launch_rhs(p->fmt, f, hh, p->blo.origin, p->b64, p->geo, p->stream));
@@ -472,7 +528,9 @@ srj_status srj_plan_tune(srj_plan_t p, srj_tune_info* info)
     };
     std::vector<Cand> cands;
     cands.push_back({p->fuse, p->seg_rows});  // the configuration in place, timed first
-    if (p->geo.ndim == 2) {
+    if (!p->iso) {
+        // unequal spacings: the unfused kernel is the only one
+    } else if (p->geo.ndim == 2) {
         for (int T : {10, 8, 6, 4})
             for (int H : {0, 24, 32, 48, 64, 96, 128}) cands.push_back({T, H});
     } else {
@@ -546,7 +604,7 @@ srj_status srj_solve(srj_plan_t p, double* u, const double* f, double tol, int64
     fill_info(info, 0, 0, NAN, 0, SRJ_EINVAL);
     if (!p || !u || !f) return fail(SRJ_EINVAL, "null argument");
     if (!(tol >= 0) || max_sweeps < 0) return fail(SRJ_EINVAL, "bad tolerance or sweep budget");
-    const double hh = p->grid.h * p->grid.h;
+    const double hh = p->hh;
     HIPCHK(hipEventRecord(p->ev0, p->stream));
     HIPCHK(launch_copy_in(p->fmt, u, p->A.origin, p->geo, p->stream));
     HIPCHK(launch_copy_in(p->fmt, u, p->B.origin, p->geo, p->stream));
@@ -580,7 +638,7 @@ srj_status srj_adjoint(srj_plan_t p, const double* grad_u, double tol, int64_t m
     srj_status st = solve_fields(p, tol, max_sweeps, &cur, &k, &cycles, &rr, &result);
     if (st != SRJ_OK) return st;
     if (result != SRJ_EDIVERGED && (df || dg))
-        HIPCHK(launch_adjoint_out((const double*)cur->origin, grad_u, p->grid.h * p->grid.h, df, dg, p->geo,
+        HIPCHK(launch_adjoint_out((const double*)cur->origin, grad_u, p->hh, df, dg, p->geo,
                                   p->stream));
     return finish_info(p, info, k, cycles, rr, result);
 }
@@ -591,7 +649,7 @@ srj_status srj_solve_ir(srj_plan_t p, double* u, const double* f, double tol, in
     fill_info(info, 0, 0, NAN, 0, SRJ_EINVAL);
     if (!p || !u || !f) return fail(SRJ_EINVAL, "null argument");
     if (!(tol >= 0) || inner_cycles < 1 || max_outer < 0) return fail(SRJ_EINVAL, "bad IR parameters");
-    const double hh = p->grid.h * p->grid.h;
+    const double hh = p->hh;
     srj_status st;
     // the binary64 iterate lives in the plan's x64 field, b in b64; A/B hold the correction d
     // and blo the inner right-hand side (the residual in the sweep format)
@@ -662,6 +720,22 @@ srj_status srj_schedule_optimal(int32_t P, double kappa_min, double kappa_max, d
     }
     if (kappa)
         for (int j = 0; j + 1 < P; ++j) kappa[j] = o.kappa[j];
+    return SRJ_OK;
+}
+
+srj_status srj_schedule_counts(int32_t P, const double* beta, const double* omega, double kappa_min,
+                               double kappa_max, int32_t q_rounding, int64_t* q)
+{
+    if (!beta || !q) return fail(SRJ_EINVAL, "null argument");
+    if (P < 1 || P > SRJ_MAX_LEVELS) return fail(SRJ_EINVAL, "P must be in [1, 16]");
+    if (q_rounding < 0 || q_rounding > 3) return fail(SRJ_EINVAL, "q_rounding must be 0, 1, 2 or 3");
+    if (q_rounding == 3 && (!omega || P > 12 || !(kappa_min > 0) || !(kappa_max > kappa_min)))
+        return fail(SRJ_EINVAL, "q_rounding 3 needs weights, P <= 12 and 0 < kappa_min < kappa_max");
+    for (int i = 0; i < P; ++i)
+        if (!(beta[i] > 0) || !std::isfinite(beta[i])) return fail(SRJ_EINVAL, "fractions must be positive");
+    std::vector<int64_t> qq = round_counts(std::vector<double>(beta, beta + P), q_rounding, omega, kappa_min, kappa_max);
+    if ((int)qq.size() != P) return fail(SRJ_EINVAL, "integer counts could not be formed");
+    std::memcpy(q, qq.data(), sizeof(int64_t) * (size_t)P);
     return SRJ_OK;
 }
 

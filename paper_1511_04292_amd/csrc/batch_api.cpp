@@ -15,6 +15,7 @@
 #include "batch.h"
 #include "kernels.h"
 #include "planner.h"
+#include "schedule_build.h"
 #include "tb_core.h"
 
 using namespace srj;
@@ -61,74 +62,13 @@ struct Sched {
 // Schedule of one problem, as srj_plan builds it.
 void build_one(const srj_grid& g, const srj_schedule& sc, Sched* out)
 {
-    const double km = sc.kappa_min > 0 ? sc.kappa_min : grid_kappa_min(2, g.n);
-    if (sc.P < 1 || sc.P > SRJ_MAX_LEVELS) {
-        out->st = SRJ_EINVAL;
-        out->err = "P must be in [1, 16]";
-        return;
-    }
-    const int P = sc.P;
-    out->w.resize(P);
-    out->q.resize(P);
-    if (sc.omega) {
-        if (!sc.q) {
-            out->st = SRJ_EINVAL;
-            out->err = "explicit weights need counts";
-            return;
-        }
-        for (int i = 0; i < P; ++i) {
-            if (!(sc.omega[i] > 0) || sc.q[i] < 1 || (i > 0 && !(sc.omega[i] < sc.omega[i - 1]))) {
-                out->st = SRJ_EINVAL;
-                out->err = "bad explicit schedule";
-                return;
-            }
-            out->w[i] = sc.omega[i];
-            out->q[i] = sc.q[i];
-        }
-    } else {
-        Optimum o;
-        if (!optimal_schedule(P, km, 2.0, &o, &out->err)) {
-            out->st = SRJ_ESCHEDULE;
-            return;
-        }
-        std::vector<int64_t> qq = floor_counts(o.beta);
-        for (int i = 0; i < P; ++i) {
-            out->w[i] = o.w[i];
-            out->q[i] = qq[i];
-        }
-    }
-    out->M = 0;
-    for (int i = 0; i < P; ++i) out->M += out->q[i];
-    if (sc.ordering == 2) {
-        if (!sc.sequence || sc.M != out->M) {
-            out->st = SRJ_EINVAL;
-            out->err = "explicit sequence must have M entries";
-            return;
-        }
-        std::vector<int64_t> cnt(P, 0);
-        for (int64_t k = 0; k < out->M; ++k) {
-            if (sc.sequence[k] < 0 || sc.sequence[k] >= P) {
-                out->st = SRJ_EINVAL;
-                out->err = "sequence index out of range";
-                return;
-            }
-            cnt[sc.sequence[k]]++;
-        }
-        for (int i = 0; i < P; ++i)
-            if (cnt[i] != out->q[i]) {
-                out->st = SRJ_EINVAL;
-                out->err = "sequence counts differ from q";
-                return;
-            }
-        out->seq.assign(sc.sequence, sc.sequence + out->M);
-    } else {
-        out->seq = order_steps(P, out->w.data(), out->q.data(), km, 2.0, sc.ordering == 1 ? 1 : 0);
-    }
-    const double gq = gamma_q_max(P, out->w.data(), out->q.data(), km, std::max(grid_kappa_max(2, g.n), km * 1.0000001));
-    if (!(gq < 1.0)) {
-        out->st = SRJ_ESCHEDULE;
-        out->err = "integer scheme not convergent";
-    }
+    SchedOut o;
+    out->st = make_schedule(2, g.n, nullptr, &sc, false, &o, &out->err);
+    if (out->st != SRJ_OK) return;
+    out->w.assign(o.omega, o.omega + o.P);
+    out->q.assign(o.q, o.q + o.P);
+    out->seq = std::move(o.seq);
+    out->M = o.M;
 }
 
 }  // namespace
@@ -193,7 +133,8 @@ srj_status srj_batch_plan(int32_t count, const srj_grid* grids, const srj_schedu
         if (g.ndim != 2) return report(SRJ_EINVAL, "batched problems are 2D");
         if (g.n[0] < 1 || g.n[1] < 1 || g.n[0] > (1 << 20) || g.n[1] > (1 << 20))
             return report(SRJ_EINVAL, "n must be in [1, 2^20]");
-        if (!(g.h > 0)) return report(SRJ_EINVAL, "h must be positive");
+        if (!(g.h[0] > 0) || !std::isfinite(g.h[0])) return report(SRJ_EINVAL, "h must be positive");
+        if (g.h[1] != g.h[0]) return report(SRJ_EINVAL, "batched problems need equal spacings (h[0] == h[1])");
         if (g.dtype != dt || dt < 0 || dt > 2) return report(SRJ_EINVAL, "one storage format per batch");
     }
     srj_batch_t b = new (std::nothrow) srj_batch_s();
@@ -246,6 +187,8 @@ srj_status srj_batch_plan(int32_t count, const srj_grid* grids, const srj_schedu
         g.nz = 1;
         g.px = (g.nx + 2 + 63) / 64 * 64;
         g.py = g.ny + 2;
+        g.wy = g.wz = 1.0;  // equal spacings
+        g.dg = 4.0;
         const size_t elems = (size_t)(g.px * g.py);
         off_u0[j] = carve(elems, 8);
         off_u1[j] = carve(elems, 8);
@@ -429,7 +372,7 @@ srj_status srj_batch_solve(srj_batch_t b, double* const* u, const double* const*
         const Geo& g = b->geos[j];
         BProb& P = b->probs[j];
         P.inner_total = inner_cycles * P.M;
-        const double hh = b->grids[j].h * b->grids[j].h;
+        const double hh = b->grids[j].h[0] * b->grids[j].h[0];
         BCHK(launch_copy_in(FMT_F64, u[j], P.u64[0], g, s));
         BCHK(launch_copy_in(FMT_F64, u[j], P.u64[1], g, s));
         BCHK(launch_rhs(FMT_F64, f[j], hh, nullptr, P.b64, g, s));

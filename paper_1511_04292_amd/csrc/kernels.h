@@ -18,7 +18,21 @@ struct Geo {
     int ndim;
     int64_t nx, ny, nz;  // interior sizes (nz = 1 in 2D)
     int64_t px, py;      // row pitch (elements) and rows per plane (ny + 2)
+    // operator weights, the equation multiplied through by h_x^2: 1 on the x neighbours,
+    // wy = h_x^2 / h_y^2, wz = h_x^2 / h_z^2 (1 in 2D), diagonal dg = 2 (1 + wy) in 2D and
+    // 2 ((1 + wy) + wz) in 3D; equal spacings give 1, 1 and 2d
+    double wy, wz, dg;
 };
+
+// Geo's operator weights for spacings h[0..ndim); iso is set when they are all equal.
+inline void geo_set_weights(Geo& g, const double* h, bool* iso)
+{
+    const double hxx = h[0] * h[0];
+    g.wy = hxx / (h[1] * h[1]);
+    g.wz = g.ndim == 3 ? hxx / (h[2] * h[2]) : 1.0;
+    g.dg = g.ndim == 2 ? 2.0 * (1.0 + g.wy) : 2.0 * ((1.0 + g.wy) + g.wz);
+    if (iso) *iso = g.wy == 1.0 && g.wz == 1.0;
+}
 
 struct Coefs {
     double c[kMaxFuse];  // c = w / (2d) of consecutive sweeps
@@ -33,12 +47,13 @@ hipError_t launch_copy_out(Fmt f, const void* field, double* user, const Geo& g,
 // b = (h*h) * f on the interior: blo in format f (may be null), b64 in FP64 (may be null)
 hipError_t launch_rhs(Fmt f, const double* user_f, double hh, void* blo, double* b64, const Geo& g,
                       hipStream_t s);
-// One sweep in -> out with coefficient c (2D or 3D).
+// One sweep in -> out with coefficient c = w / g.dg (2D or 3D), with the operator weights of g.
 hipError_t launch_sweep_unfused(Fmt f, const void* in, void* out, const void* b, const Geo& g,
                                 double c, hipStream_t s);
 // T consecutive 2D sweeps in -> out in one launch with coefficients co.c[0..T), row
 // segments of H output rows per wave.  flip (0 or 1) reverses the direction every segment
 // streams in; callers alternate it from launch to launch (it changes no result).
+// (The temporally blocked kernels implement the equal-spacing operator only.)
 hipError_t launch_sweep_fused(Fmt f, const void* in, void* out, const void* b, const Geo& g,
                               const Coefs& co, int T, int H, int flip, hipStream_t s);
 // T <= kMaxFuse3d sweeps (coefficients co.c[0..T)) of a 3D grid in one launch: x-y tiles of

@@ -1,12 +1,15 @@
 // SRJ device kernels for gfx950 (CDNA4, wave64).
 //
-// The weighted-Jacobi step (Sec. 3.1, Eq. 2nd-order_CD, Poisson form with b = h^2 f):
-//     s = (W + E) + (S + N)  [ + (D + U) in 3D ]
-//     t = (s + b) - 2d * u
-//     u' = u + c * t,        c = w / (2d)
+// The weighted-Jacobi step (Sec. 3.1, Eq. 2nd-order_CD, Poisson form with b = h_x^2 f):
+//     s = (W + E) + wy (S + N)  [ + wz (D + U) in 3D ]
+//     t = (s + b) - dg * u
+//     u' = u + c * t,        c = w / dg
 // with exactly this association and no fused multiply-add (the file is built with
 // -ffp-contract=off), so every kernel below -- unfused or temporally blocked -- produces
-// bit-identical iterates for the same sweep sequence.  Storage formats: binary64,
+// bit-identical iterates for the same sweep sequence.  wy, wz and dg are the weights of a
+// box whose axes have different spacings (Geo); with equal spacings they are 1, 1 and 2d,
+// every product by them is exact, and the temporally blocked kernels, which implement that
+// case only, give the same bits.  Storage formats: binary64,
 // binary32, and bfloat16 (binary32 arithmetic, round-to-nearest-even on every store).
 //
 // The sweep is bound by HBM bandwidth (0.3 flop per byte unfused), so no kernel uses the
@@ -93,17 +96,17 @@ __global__ __launch_bounds__(256) void k_zero(S* __restrict__ f, int64_t n)
 template <class S>
 __global__ __launch_bounds__(256) void k_sweep2d(const S* __restrict__ u, S* __restrict__ o,
                                                  const S* __restrict__ b, int64_t px, int nx, int ny,
-                                                 double c64)
+                                                 double wy64, double dg64, double c64)
 {
     using Cm = typename Tr<S>::C;
     const int j = blockIdx.x * 64 + threadIdx.x + 1;
     const int i = blockIdx.y * 4 + threadIdx.y + 1;
     if (j > nx || i > ny) return;
-    const Cm c = (Cm)c64;
+    const Cm c = (Cm)c64, wy = (Cm)wy64, dg = (Cm)dg64;
     const int64_t p = (int64_t)i * px + j;
     Cm m = Tr<S>::ld(u[p]);
-    Cm s = (Tr<S>::ld(u[p - 1]) + Tr<S>::ld(u[p + 1])) + (Tr<S>::ld(u[p - px]) + Tr<S>::ld(u[p + px]));
-    Cm t = (s + Tr<S>::ld(b[p])) - (Cm)4 * m;
+    Cm s = (Tr<S>::ld(u[p - 1]) + Tr<S>::ld(u[p + 1])) + wy * (Tr<S>::ld(u[p - px]) + Tr<S>::ld(u[p + px]));
+    Cm t = (s + Tr<S>::ld(b[p])) - dg * m;
     o[p] = Tr<S>::st(m + c * t);
 }
 
@@ -116,7 +119,8 @@ __global__ __launch_bounds__(256) void k_sweep2d(const S* __restrict__ u, S* __r
 template <class S, int D>
 __global__ __launch_bounds__(1024) void k_sweep3d(const S* __restrict__ u, S* __restrict__ o,
                                                   const S* __restrict__ b, int64_t px, int64_t py,
-                                                  int nx, int ny, int nz, int zrun, double c64)
+                                                  int nx, int ny, int nz, int zrun, double wy64, double wz64,
+                                                  double dg64, double c64)
 {
     using Cm = typename Tr<S>::C;
     const int j = blockIdx.x * 64 + threadIdx.x + 1;
@@ -124,7 +128,7 @@ __global__ __launch_bounds__(1024) void k_sweep3d(const S* __restrict__ u, S* __
     if (j > nx || i > ny) return;
     const int k0 = blockIdx.z * zrun + 1;
     const int k1 = min(k0 + zrun, nz + 1);
-    const Cm c = (Cm)c64;
+    const Cm c = (Cm)c64, wy = (Cm)wy64, wz = (Cm)wz64, dg = (Cm)dg64;
     const int64_t pl = px * py;
     const int64_t col = (int64_t)i * px + j;
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
@@ -141,9 +145,9 @@ __global__ __launch_bounds__(1024) void k_sweep3d(const S* __restrict__ u, S* __
             const int64_t p = (int64_t)min(k, nz) * pl + col;
             const Cm up = Q[s];
             const Cm sm = ((Tr<S>::ld(u[p - 1]) + Tr<S>::ld(u[p + 1])) +
-                           (Tr<S>::ld(u[p - px]) + Tr<S>::ld(u[p + px]))) +
-                          (dn + up);
-            const Cm t = (sm + Tr<S>::ld(b[p])) - (Cm)6 * m;
+                           wy * (Tr<S>::ld(u[p - px]) + Tr<S>::ld(u[p + px]))) +
+                          wz * (dn + up);
+            const Cm t = (sm + Tr<S>::ld(b[p])) - dg * m;
             // planes k >= k1 land at or past the record count and are dropped
             tb_store(Tr<S>::st(m + c * t), rs, (int)(((int64_t)(k - k0) * pl + col) * (int64_t)sizeof(S)));
             dn = m;
@@ -169,16 +173,12 @@ __device__ __forceinline__ double res_at(const S* u, const double* b64, int64_t 
 {
     const bool zl = zi && j - 1 >= 1, zr = zi && j + 1 <= g.nx;
     const bool zs = zi && i - 1 >= 1, zn = zi && i + 1 <= g.ny;
-    double s = (ldz(u, p - 1, zl) + ldz(u, p + 1, zr)) + (ldz(u, p - px, zs) + ldz(u, p + px, zn));
-    double twod_u;
+    double s = (ldz(u, p - 1, zl) + ldz(u, p + 1, zr)) + g.wy * (ldz(u, p - px, zs) + ldz(u, p + px, zn));
     if (ndim == 3) {
         const bool zd = zi && k - 1 >= 1, zu = zi && k + 1 <= g.nz;
-        s = s + (ldz(u, p - pl, zd) + ldz(u, p + pl, zu));
-        twod_u = 6.0 * ldz(u, p, zi);
-    } else {
-        twod_u = 4.0 * ldz(u, p, zi);
+        s = s + g.wz * (ldz(u, p - pl, zd) + ldz(u, p + pl, zu));
     }
-    return (s + b64[p]) - twod_u;
+    return (s + b64[p]) - g.dg * ldz(u, p, zi);
 }
 
 template <class S>
@@ -286,7 +286,9 @@ __global__ __launch_bounds__(256) void k_update(double* __restrict__ u, const S*
     }
 }
 
-// Adjoint outputs, one thread per point of the user (dense, ring included) layout.
+// Adjoint outputs, one thread per point of the user (dense, ring included) layout:
+// df = hh * lam on the interior; dg = grad_u + (axis weight) * lam at the reading interior
+// cell on the ring.
 __global__ __launch_bounds__(256) void k_adjoint_out(const double* __restrict__ lam,
                                                      const double* __restrict__ gu, double hh,
                                                      double* __restrict__ df, double* __restrict__ dg,
@@ -307,14 +309,22 @@ __global__ __launch_bounds__(256) void k_adjoint_out(const double* __restrict__ 
         if (dg) {
             double v = 0.0;
             // a ring cell is read by exactly one stencil when it lies outside the box along
-            // exactly one axis; its reader is the adjacent interior cell along that axis
+            // exactly one axis; its reader is the adjacent interior cell along that axis,
+            // which weighs it with that axis's weight
             const int outs = (!ix) + (!iy) + ((g.ndim == 3) && !iz);
             if (outs == 1) {
                 int64_t jj = j, ii = i, kk = k;
+                double wa = 1.0;
                 if (!ix) jj = (j == 0) ? 1 : g.nx;
-                if (!iy) ii = (i == 0) ? 1 : g.ny;
-                if (g.ndim == 3 && !iz) kk = (k == 0) ? 1 : g.nz;
-                v = lam[(kk * g.py + ii) * g.px + jj];
+                if (!iy) {
+                    ii = (i == 0) ? 1 : g.ny;
+                    wa = g.wy;
+                }
+                if (g.ndim == 3 && !iz) {
+                    kk = (k == 0) ? 1 : g.nz;
+                    wa = g.wz;
+                }
+                v = wa * lam[(kk * g.py + ii) * g.px + jj];
             }
             // the ring of u is g itself: its own gradient passes straight through
             dg[idx] = (ix && iy && iz) ? 0.0 : v + gu[idx];
@@ -370,7 +380,7 @@ hipError_t launch_sweep_unfused(Fmt f, const void* in, void* out, const void* b,
     if (g.ndim == 2) {
         dim3 grid((unsigned)((g.nx + 63) / 64), (unsigned)((g.ny + 3) / 4));
         SRJ_DISPATCH(f, hipLaunchKernelGGL(k_sweep2d<S>, grid, dim3(64, 4), 0, s, (const S*)in, (S*)out,
-                                           (const S*)b, g.px, (int)g.nx, (int)g.ny, c));
+                                           (const S*)b, g.px, (int)g.nx, (int)g.ny, g.wy, g.dg, c));
     } else {
         // 64 x 4 threads per block, runs of 32 z planes, 2 planes loaded ahead
         constexpr int kZrun = 32, kBy = 4;
@@ -380,7 +390,8 @@ hipError_t launch_sweep_unfused(Fmt f, const void* in, void* out, const void* b,
         dim3 grid((unsigned)((g.nx + 63) / 64), (unsigned)((g.ny + kBy - 1) / kBy), (unsigned)((g.nz + zrun - 1) / zrun));
         dim3 blk(64, kBy);
         SRJ_DISPATCH(f, hipLaunchKernelGGL((k_sweep3d<S, 2>), grid, blk, 0, s, (const S*)in, (S*)out, (const S*)b,
-                                           g.px, g.py, (int)g.nx, (int)g.ny, (int)g.nz, zrun, c));
+                                           g.px, g.py, (int)g.nx, (int)g.ny, (int)g.nz, zrun, g.wy, g.wz, g.dg,
+                                           c));
     }
     return hipGetLastError();
 }

@@ -41,25 +41,21 @@ using ld = long double;
 
 static const double kPi = 3.14159265358979323846;
 
-double grid_kappa_min(int ndim, const int64_t* n)
+static double grid_kappa(int ndim, const int64_t* n, const double* wt, bool lowest)
 {
     double s = 0.0;
     for (int i = 0; i < ndim; ++i) {
-        double v = std::sin(kPi / (2.0 * (double)(n[i] + 1)));
-        s = s + v * v;
+        const double a = kPi / (2.0 * (double)(n[i] + 1));
+        const double v = lowest ? std::sin(a) : std::cos(a);
+        const double axis = (!wt || i == 0) ? 1.0 : wt[i - 1];
+        s = s + (wt ? axis * (v * v) : v * v);
     }
-    return (2.0 / (double)ndim) * s;
+    return wt ? (4.0 * s) / wt[2] : (2.0 / (double)ndim) * s;
 }
 
-double grid_kappa_max(int ndim, const int64_t* n)
-{
-    double s = 0.0;
-    for (int i = 0; i < ndim; ++i) {
-        double v = std::cos(kPi / (2.0 * (double)(n[i] + 1)));
-        s = s + v * v;
-    }
-    return (2.0 / (double)ndim) * s;
-}
+double grid_kappa_min(int ndim, const int64_t* n, const double* wt) { return grid_kappa(ndim, n, wt, true); }
+
+double grid_kappa_max(int ndim, const int64_t* n, const double* wt) { return grid_kappa(ndim, n, wt, false); }
 
 // ----------------------------------------------------------------- the system
 
@@ -457,6 +453,67 @@ std::vector<int64_t> floor_counts(const std::vector<double>& beta)
     std::vector<int64_t> q(beta.size());
     for (size_t i = 0; i < beta.size(); ++i) q[i] = (int64_t)std::floor(beta[i] / beta[0]);
     return q;
+}
+
+static std::vector<double> log_grid(double km, double kM, int G);
+
+std::vector<int64_t> round_counts(const std::vector<double>& beta, int mode, const double* w, double km,
+                                  double kM)
+{
+    const int P = (int)beta.size();
+    std::vector<int64_t> fl(P), ce(P);
+    for (int i = 0; i < P; ++i) {
+        const double r = beta[i] / beta[0];
+        fl[i] = (int64_t)std::floor(r);
+        ce[i] = (int64_t)std::ceil(r);
+    }
+    fl[0] = ce[0] = 1;
+    if (mode == 0) return fl;
+    if (mode == 2) return ce;
+    if (mode == 1) {
+        std::vector<int64_t> q(P);
+        for (int i = 0; i < P; ++i) q[i] = (int64_t)std::floor(beta[i] / beta[0] + 0.5);
+        q[0] = 1;
+        return q;
+    }
+    if (mode != 3 || P > 12 || !w || !(km > 0) || !(kM > km)) return {};
+    // levels whose ratio is an integer have one choice; the others two
+    std::vector<int> free_lv;
+    for (int i = 1; i < P; ++i)
+        if (ce[i] != fl[i]) free_lv.push_back(i);
+    const int G = 4096;
+    std::vector<double> grid = log_grid(km, kM, G);
+    std::vector<double> L((size_t)P * G);
+    for (int i = 0; i < P; ++i)
+        for (int g = 0; g < G; ++g) L[(size_t)i * G + g] = std::log(std::fabs(1.0 - w[i] * grid[g]));
+    std::vector<int64_t> best = fl, q(P);
+    double best_rate = std::numeric_limits<double>::infinity();
+    int best_ceils = P + 1;
+    const uint32_t ncomb = 1u << free_lv.size();
+    for (uint32_t mask = 0; mask < ncomb; ++mask) {
+        q = fl;
+        int ceils = 0;
+        for (size_t b = 0; b < free_lv.size(); ++b)
+            if (mask & (1u << b)) {
+                q[free_lv[b]] = ce[free_lv[b]];
+                ++ceils;
+            }
+        int64_t M = 0;
+        for (int i = 0; i < P; ++i) M += q[i];
+        double mx = -std::numeric_limits<double>::infinity();
+        for (int g = 0; g < G; ++g) {
+            double v = 0.0;
+            for (int i = 0; i < P; ++i) v += (double)q[i] * L[(size_t)i * G + g];
+            mx = std::max(mx, v);
+        }
+        const double rate = mx / (double)M;  // log of the per-step factor
+        if (rate < best_rate || (rate == best_rate && ceils < best_ceils)) {
+            best_rate = rate;
+            best_ceils = ceils;
+            best = q;
+        }
+    }
+    return best;
 }
 
 // ------------------------------------------------------------------- ordering

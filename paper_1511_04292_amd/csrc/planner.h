@@ -16,16 +16,26 @@ struct Optimum {
     std::vector<double> kappa;  // interior maxima of Gamma (P - 1)
 };
 
-// Smallest Jacobi symbol of the Dirichlet grid: (2/d) sum_i sin^2(pi / (2 (n_i + 1))).
-double grid_kappa_min(int ndim, const int64_t* n);
-// Largest Jacobi symbol of the Dirichlet grid: (2/d) sum_i cos^2(pi / (2 (n_i + 1))).
-double grid_kappa_max(int ndim, const int64_t* n);
+// Smallest Jacobi symbol of the Dirichlet grid: (2/d) sum_i sin^2(pi / (2 (n_i + 1))) with
+// equal spacings (wt = null); with axis weights wt = {wy, wz, dg} (the equation multiplied
+// through by h_x^2) it is 4 (s_x + wy s_y [+ wz s_z]) / dg, s_i = sin^2(pi / (2 (n_i + 1))).
+double grid_kappa_min(int ndim, const int64_t* n, const double* wt = nullptr);
+// Largest Jacobi symbol of the Dirichlet grid: the same with cos^2.
+double grid_kappa_max(int ndim, const int64_t* n, const double* wt = nullptr);
 
 // Minimax-optimal P-level scheme on [km, kM]; false (with a message) if the solve fails.
 bool optimal_schedule(int P, double km, double kM, Optimum* out, std::string* err);
 
 // q_i = floor(beta_i / beta_1).
 std::vector<int64_t> floor_counts(const std::vector<double>& beta);
+
+// Integer counts from the fractions (Sec. 4.3): mode 0 floor, 1 nearest integer, 2 ceiling
+// of beta_i / beta_1 (q_1 = 1 in every mode), 3 floor or ceiling per level, whichever
+// combination gives the smallest max over [km, kM] of |prod (1 - w_i k)^q_i|^(1/M) (P <= 12;
+// ties to the combination with more floors, then to the lower levels' floors).  Returns an
+// empty vector for a bad mode.
+std::vector<int64_t> round_counts(const std::vector<double>& beta, int mode, const double* w, double km,
+                                  double kM);
 
 // Order of the M steps: balanced greedy (0) or even spread (1).
 std::vector<int32_t> order_steps(int P, const double* w, const int64_t* q, double km, double kM,

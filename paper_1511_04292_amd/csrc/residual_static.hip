@@ -2,9 +2,9 @@
 //
 // The reduction scratch (per-block partial sums) lives in a file-scope device array, one
 // copy per GPU, whose device address is looked up once per device; the kernels read the
-// caller's dense arrays directly and form b = (h*h) f on the fly.  They follow the
+// caller's dense arrays directly and form b = (h_x*h_x) f on the fly.  They follow the
 // association and reduction order of the plan-based srj_residual, so both give the same
-// bits (r = b - A u in binary64, A = 2d I minus the neighbour sum; Sec. 5.1 setting).
+// bits (r = b - A u in binary64, A = dg I minus the weighted neighbour sum; Sec. 5.1 setting).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -55,30 +55,31 @@ srj_status scratch_ptr(double** out)
 
 __device__ __forceinline__ double ldz_d(const double* u, int64_t p, bool zero) { return zero ? 0.0 : u[p]; }
 
+struct Wts {
+    double wy, wz, dg;
+};
+
 // r at interior point p of the dense layout (pitch nx + 2, ny + 2 rows per plane), with b
-// = hh * f[p]; zi reads u's interior as 0 (the residual of the zero interior is b~).
-__device__ __forceinline__ double res_dense(const double* u, const double* f, double hh, int64_t p, int64_t px,
-                                            int64_t pl, int ndim, int i, int j, int k, int nx, int ny, int nz,
-                                            bool zi)
+// = hh * f[p] and the operator weights w; zi reads u's interior as 0 (the residual of the
+// zero interior is b~).
+__device__ __forceinline__ double res_dense(const double* u, const double* f, double hh, const Wts& w, int64_t p,
+                                            int64_t px, int64_t pl, int ndim, int i, int j, int k, int nx, int ny,
+                                            int nz, bool zi)
 {
     const bool zl = zi && j - 1 >= 1, zr = zi && j + 1 <= nx;
     const bool zs = zi && i - 1 >= 1, zn = zi && i + 1 <= ny;
-    double s = (ldz_d(u, p - 1, zl) + ldz_d(u, p + 1, zr)) + (ldz_d(u, p - px, zs) + ldz_d(u, p + px, zn));
-    double twod_u;
+    double s = (ldz_d(u, p - 1, zl) + ldz_d(u, p + 1, zr)) + w.wy * (ldz_d(u, p - px, zs) + ldz_d(u, p + px, zn));
     if (ndim == 3) {
         const bool zd = zi && k - 1 >= 1, zu = zi && k + 1 <= nz;
-        s = s + (ldz_d(u, p - pl, zd) + ldz_d(u, p + pl, zu));
-        twod_u = 6.0 * ldz_d(u, p, zi);
-    } else {
-        twod_u = 4.0 * ldz_d(u, p, zi);
+        s = s + w.wz * (ldz_d(u, p - pl, zd) + ldz_d(u, p + pl, zu));
     }
-    return (s + hh * f[p]) - twod_u;
+    return (s + hh * f[p]) - w.dg * ldz_d(u, p, zi);
 }
 
 // One block per kResRows lines: (sum r^2, max |r|) into part[0..2nb) and (sum b~^2, max |b~|)
 // into part[2nb..4nb); r_out (may be null) receives r on the interior.
 __global__ __launch_bounds__(256) void k_residual_static(const double* __restrict__ u, const double* __restrict__ f,
-                                                         double hh, int ndim, int nx, int ny, int nz,
+                                                         double hh, Wts w, int ndim, int nx, int ny, int nz,
                                                          double* __restrict__ r_out, double* __restrict__ part,
                                                          int nb)
 {
@@ -91,8 +92,8 @@ __global__ __launch_bounds__(256) void k_residual_static(const double* __restric
         const int k = (ndim == 3) ? (int)(q / ny) + 1 : 0;
         const int64_t rowp = (int64_t)k * pl + (int64_t)i * px;
         for (int j = threadIdx.x + 1; j <= nx; j += 256) {
-            const double r = res_dense(u, f, hh, rowp + j, px, pl, ndim, i, j, k, nx, ny, nz, false);
-            const double b = res_dense(u, f, hh, rowp + j, px, pl, ndim, i, j, k, nx, ny, nz, true);
+            const double r = res_dense(u, f, hh, w, rowp + j, px, pl, ndim, i, j, k, nx, ny, nz, false);
+            const double b = res_dense(u, f, hh, w, rowp + j, px, pl, ndim, i, j, k, nx, ny, nz, true);
             if (r_out) r_out[rowp + j] = r;
             s1 = s1 + r * r;
             nanmax(m1, fabs(r));
@@ -154,9 +155,10 @@ extern "C" srj_status srj_residual_static(const srj_grid* grid, const double* u,
 {
     if (!grid || !u || !f || !norms) return report(SRJ_EINVAL, "null argument");
     if (grid->ndim != 2 && grid->ndim != 3) return report(SRJ_EINVAL, "ndim must be 2 or 3");
-    for (int i = 0; i < grid->ndim; ++i)
+    for (int i = 0; i < grid->ndim; ++i) {
         if (grid->n[i] < 1 || grid->n[i] > (1 << 20)) return report(SRJ_EINVAL, "n must be in [1, 2^20]");
-    if (!(grid->h > 0) || !std::isfinite(grid->h)) return report(SRJ_EINVAL, "h must be positive");
+        if (!(grid->h[i] > 0) || !std::isfinite(grid->h[i])) return report(SRJ_EINVAL, "every h[i] must be positive");
+    }
     const int64_t nz = grid->ndim == 3 ? grid->n[2] : 1;
     const int64_t lines = grid->n[1] * nz;
     const int64_t nb = (lines + kResRows - 1) / kResRows;
@@ -168,14 +170,18 @@ extern "C" srj_status srj_residual_static(const srj_grid* grid, const double* u,
     srj_status st = scratch_ptr(&part);
     if (st != SRJ_OK) return st;
     hipStream_t s = (hipStream_t)stream;
-    const double hh = grid->h * grid->h;
+    Geo g{};
+    g.ndim = grid->ndim;
+    geo_set_weights(g, grid->h, nullptr);
+    const Wts w{g.wy, g.wz, g.dg};
+    const double hh = grid->h[0] * grid->h[0];
     const int nx = (int)grid->n[0], ny = (int)grid->n[1];
     if (r_out) {
         const int64_t total = (int64_t)(nx + 2) * (ny + 2) * (grid->ndim == 3 ? nz + 2 : 1);
         const int64_t blocks = std::min<int64_t>(65536, std::max<int64_t>(1, (total + 255) / 256));
         hipLaunchKernelGGL(k_ring_zero, dim3((unsigned)blocks), dim3(256), 0, s, r_out, grid->ndim, nx, ny, (int)nz);
     }
-    hipLaunchKernelGGL(k_residual_static, dim3((unsigned)nb), dim3(256), 0, s, u, f, hh, grid->ndim, nx, ny, (int)nz,
+    hipLaunchKernelGGL(k_residual_static, dim3((unsigned)nb), dim3(256), 0, s, u, f, hh, w, grid->ndim, nx, ny, (int)nz,
                        r_out, part, (int)nb);
     hipLaunchKernelGGL(k_residual_static_final, dim3(1), dim3(256), 0, s, (const double*)part, (int)nb, norms);
     const hipError_t e = hipGetLastError();

@@ -26,15 +26,29 @@ class SrjError(RuntimeError):
 
 
 class _Grid(ctypes.Structure):
-    _fields_ = [("ndim", ctypes.c_int32), ("n", ctypes.c_int64 * 3), ("h", ctypes.c_double),
+    _fields_ = [("ndim", ctypes.c_int32), ("n", ctypes.c_int64 * 3), ("h", ctypes.c_double * 3),
                 ("dtype", ctypes.c_int32)]
 
 
 class _Schedule(ctypes.Structure):
     _fields_ = [("P", ctypes.c_int32), ("omega", ctypes.POINTER(ctypes.c_double)),
                 ("q", ctypes.POINTER(ctypes.c_int64)), ("kappa_min", ctypes.c_double),
+                ("n_eff", ctypes.c_double), ("q_rounding", ctypes.c_int32),
                 ("ordering", ctypes.c_int32), ("sequence", ctypes.POINTER(ctypes.c_int32)),
                 ("M", ctypes.c_int64)]
+
+
+def _fill_grid(g, n, h, dtype):
+    """n = (n_x, n_y[, n_z]); h one spacing for every axis or one per axis (h_x, h_y[, h_z])."""
+    g.ndim = len(n)
+    for i, v in enumerate(n):
+        g.n[i] = int(v)
+    hs = [float(h)] * len(n) if np.isscalar(h) else [float(x) for x in h]
+    if len(hs) != len(n):
+        raise ValueError("one spacing per axis")
+    for i, v in enumerate(hs):
+        g.h[i] = v
+    g.dtype = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
 
 
 class _Desc(ctypes.Structure):
@@ -62,7 +76,7 @@ EXPORTS = ["srj_plan", "srj_plan_destroy", "srj_plan_describe", "srj_plan_sequen
            "srj_plan_set_fusion", "srj_solve", "srj_sweeps", "srj_residual", "srj_solve_ir",
            "srj_schedule_optimal", "srj_schedule_order", "srj_status_string", "srj_last_error",
            "srj_adjoint", "srj_batch_plan", "srj_batch_solve", "srj_batch_destroy", "srj_plan_tune",
-           "srj_batch_tune", "srj_residual_static"]
+           "srj_batch_tune", "srj_residual_static", "srj_schedule_counts"]
 
 
 def lib():
@@ -94,6 +108,8 @@ def lib():
     L.srj_batch_tune.argtypes = [vp, ctypes.POINTER(_Tune)]
     L.srj_schedule_optimal.argtypes = [i32, dbl, dbl, ctypes.POINTER(dbl), ctypes.POINTER(dbl),
                                        ctypes.POINTER(i64), ctypes.POINTER(dbl)]
+    L.srj_schedule_counts.argtypes = [i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl), dbl, dbl, i32,
+                                      ctypes.POINTER(i64)]
     L.srj_schedule_order.argtypes = [i32, ctypes.POINTER(dbl), ctypes.POINTER(i64), dbl, dbl, i32,
                                      ctypes.POINTER(i32)]
     L.srj_status_string.argtypes = [i32]
@@ -103,7 +119,7 @@ def lib():
     for name in ["srj_plan", "srj_plan_describe", "srj_plan_sequence", "srj_plan_set_fusion", "srj_solve",
                  "srj_sweeps", "srj_residual", "srj_solve_ir", "srj_schedule_optimal", "srj_schedule_order",
                  "srj_adjoint", "srj_batch_plan", "srj_batch_solve", "srj_plan_tune", "srj_batch_tune",
-                 "srj_residual_static"]:
+                 "srj_residual_static", "srj_schedule_counts"]:
         getattr(L, name).restype = i32
     _lib = L
     return L
@@ -153,19 +169,17 @@ class Plan:
 
 
 def srj_plan(n, h, P=None, omega=None, q=None, kappa_min=0.0, ordering=0, sequence=None,
-             dtype="f64", stream=None):
-    """Create a plan for a grid of interior sizes n = (n_x, n_y[, n_z]) and spacing h.
+             dtype="f64", stream=None, n_eff=0.0, q_rounding=0):
+    """Create a plan for a grid of interior sizes n = (n_x, n_y[, n_z]) and spacing h (one
+    number, or one per axis).
 
     Either P (optimised schedule) or omega/q (explicit) is given; ordering 0 balanced,
-    1 even spread, 2 explicit sequence.
+    1 even spread, 2 explicit sequence; n_eff > 0 optimises for the Neumann table row of
+    resolution n_eff; q_rounding 0 floor, 1 nearest, 2 ceiling, 3 best per level.
     """
     L = lib()
     g = _Grid()
-    g.ndim = len(n)
-    for i, v in enumerate(n):
-        g.n[i] = int(v)
-    g.h = float(h)
-    g.dtype = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
+    _fill_grid(g, n, h, dtype)
     s = _Schedule()
     keep = []
     if omega is not None:
@@ -178,6 +192,8 @@ def srj_plan(n, h, P=None, omega=None, q=None, kappa_min=0.0, ordering=0, sequen
     else:
         s.P = int(P)
     s.kappa_min = float(kappa_min)
+    s.n_eff = float(n_eff)
+    s.q_rounding = int(q_rounding)
     s.ordering = int(ordering)
     if sequence is not None:
         sq = np.ascontiguousarray(sequence, dtype=np.int32)
@@ -247,11 +263,7 @@ def srj_residual_static(n, h, u, f, norms, r_out=None, stream=None):
     (||r||_2, max |r|, ||b~||_2, relres) into the device tensor norms (4 float64) on the
     stream, asynchronously; r_out (optional) receives r with a zero ring."""
     g = _Grid()
-    g.ndim = len(n)
-    for i, v in enumerate(n):
-        g.n[i] = int(v)
-    g.h = float(h)
-    g.dtype = SRJ_F64
+    _fill_grid(g, n, h, SRJ_F64)
     shape = tuple(x + 2 for x in reversed(tuple(n)))
     if norms.numel() < 4:
         raise ValueError("norms needs 4 elements")
@@ -303,10 +315,7 @@ def srj_batch_plan(problems, dtype="f32", stream=None):
     keep = []
     for j, pr in enumerate(problems):
         g = grids[j]
-        g.ndim = 2
-        g.n[0], g.n[1] = int(pr["n"][0]), int(pr["n"][1])
-        g.h = float(pr["h"])
-        g.dtype = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
+        _fill_grid(g, pr["n"], pr["h"], dtype)
         s = scheds[j]
         if pr.get("omega") is not None:
             w = np.ascontiguousarray(pr["omega"], dtype=np.float64)
@@ -318,6 +327,8 @@ def srj_batch_plan(problems, dtype="f32", stream=None):
         else:
             s.P = int(pr["P"])
         s.kappa_min = float(pr.get("kappa_min", 0.0))
+        s.n_eff = float(pr.get("n_eff", 0.0))
+        s.q_rounding = int(pr.get("q_rounding", 0))
         s.ordering = int(pr.get("ordering", 0))
         if pr.get("sequence") is not None:
             sq = np.ascontiguousarray(pr["sequence"], dtype=np.int32)
@@ -356,6 +367,19 @@ def srj_schedule_optimal(P, kappa_min, kappa_max=2.0):
                                       q.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                       k.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
     return dict(w=w, beta=b, q=q, kappa=k[:P - 1])
+
+
+def srj_schedule_counts(beta, q_rounding=0, omega=None, kappa_min=0.0, kappa_max=2.0):
+    """Integer counts from fractions (Sec. 4.3): 0 floor, 1 nearest, 2 ceiling, 3 best
+    floor/ceiling combination for the weights omega on [kappa_min, kappa_max]."""
+    b = np.ascontiguousarray(beta, dtype=np.float64)
+    w = np.ascontiguousarray(omega, dtype=np.float64) if omega is not None else None
+    q = np.zeros(len(b), dtype=np.int64)
+    _check(lib().srj_schedule_counts(len(b), b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if w is not None else None,
+                                     float(kappa_min), float(kappa_max), int(q_rounding),
+                                     q.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+    return q
 
 
 def srj_schedule_order(omega, q, kappa_min, kappa_max=2.0, ordering=0):

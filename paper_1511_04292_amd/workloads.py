@@ -173,3 +173,24 @@ def blobs_2d_device(n, seed=0, count=32, device="cuda:0"):
     f[:, 0] = 0.0
     f[:, -1] = 0.0
     return dict(n=(n, n), h=grid_spacing(n), u0=u0, f=f)
+
+
+def exp_xy_unit_square(nx_zones=585, ny_zones=280):
+    """The Dirichlet test problem of Sec. 5.1 on the unit square cut into nx_zones x ny_zones
+    uniform zones: interior points (nx_zones - 1) x (ny_zones - 1), spacings
+    h = (1/nx_zones, 1/ny_zones).  With -lap(u) = f the source is f = (x^2 + y^2) e^(xy) and
+    the ring holds the exact solution u = -e^(xy) (so u(0, y) = u(x, 0) = -1, u(1, y) = -e^y,
+    u(x, 1) = -e^x).  Returns n, h, u0 (ring set, interior 0), f (ring 0) and u_exact on the
+    full grid."""
+    nx, ny = nx_zones - 1, ny_zones - 1
+    hx, hy = 1.0 / nx_zones, 1.0 / ny_zones
+    x = np.arange(nx + 2, dtype=np.float64) * hx
+    y = np.arange(ny + 2, dtype=np.float64) * hy
+    X, Y = np.meshgrid(x, y, indexing="xy")
+    ue = -np.exp(X * Y)
+    f = (X * X + Y * Y) * np.exp(X * Y)
+    f[0, :] = f[-1, :] = 0.0
+    f[:, 0] = f[:, -1] = 0.0
+    u0 = ue.copy()
+    u0[1:-1, 1:-1] = 0.0
+    return dict(n=(nx, ny), h=(hx, hy), u0=u0, f=f, u_exact=ue)

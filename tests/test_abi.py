@@ -82,3 +82,13 @@ def test_grid_kappa_min_matches_oracle():
         d = len(shape)
         v = (2.0 / d) * sum(math.sin(math.pi / (2.0 * (n + 1))) ** 2 for n in shape)
         assert v == S.kappa_min_dirichlet(shape)
+
+
+@pytest.mark.parametrize("P,N", [(3, 100), (6, 256), (8, 362.745)])
+def test_counts_match_oracle(P, N):
+    km = S.kappa_min_neumann(N)
+    o = S.optimal(P, km)
+    for mode in (0, 1, 2, 3):
+        ref = S.q_counts(o["beta"], mode, o["w"], km)
+        got = srj.srj_schedule_counts(o["beta"], mode, o["w"], km, 2.0)
+        assert np.array_equal(got, ref), (P, N, mode, got, ref)

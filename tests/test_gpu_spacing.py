@@ -1,0 +1,228 @@
+"""Unequal spacings per axis (the unit square of Sec. 5.1 cut into 585 x 280 zones) on the
+GPU, through the C ABI, against the oracle: single and scheduled sweeps in every storage
+format, residuals (plan-based and allocation-free), solves, refinement and the adjoint, all
+on the weighted operator; and the paper's case study itself: its two Neumann-row schedules
+(N = 550 and N = 250 of the P = 10 table), bit for bit against the oracle's solves."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import adjoint as OA
+from oracle import schedule as S
+from oracle import spectral, sweeps
+from paper_1511_04292_amd import srj, workloads
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rand_case(n_xyz, seed):
+    full = tuple(n + 2 for n in reversed(n_xyz))
+    return workloads.random_state(full, seed), workloads.random_state(full, seed + 1000)
+
+
+def sched(P, km):
+    o = S.optimal(P, km)
+    q = S.q_floor(o["beta"])
+    return o["w"], q, S.order_balanced(o["w"], q, km)
+
+
+H2 = {(67, 45): (1.0 / 68, 1.0 / 30), (130, 9): (0.01, 0.003), (5, 200): (0.2, 0.0049)}
+H3 = {(33, 17, 12): (1.0 / 34, 1.0 / 20, 1.0 / 9), (8, 40, 5): (0.1, 0.03, 0.2)}
+
+
+@pytest.mark.parametrize("n", list(H2) + list(H3))
+@pytest.mark.parametrize("fmt", ["f64", "f32", "bf16"])
+def test_weighted_sweeps_bitwise(n, fmt):
+    h = H2.get(n) or H3.get(n)
+    nd = len(n)
+    u, f = rand_case(n, 3)
+    wt = sweeps.axis_weights(h, nd)
+    km = S.kappa_min_dirichlet(n, h)
+    w, q, seq = sched(3, km)
+    p = srj.srj_plan(n, h, omega=w, q=q, sequence=seq, dtype=fmt)
+    assert srj.srj_plan_describe(p)["fused_sweeps"] == 0
+    with pytest.raises(srj.SrjError):
+        srj.srj_plan_set_fusion(p, 2)
+    nsw = len(seq) + 3
+    ug = dev(u)
+    srj.srj_sweeps(p, ug, dev(f), 2, nsw)
+    b = sweeps.rhs(f, h)
+    inner = tuple(slice(1, -1) for _ in range(nd))
+    if fmt == "f64":
+        ref = sweeps.run(u, b, sweeps.coefficients(np.asarray(w)[seq], nd, wt), nsw, k0=2, wt=wt)
+        assert np.array_equal(host(ug), ref)
+    else:
+        c32 = sweeps.lo_coefficients(np.asarray(w)[seq], nd, fmt, wt)
+        x = sweeps.lo_cast(u, fmt)
+        bl = sweeps.lo_cast(b, fmt)
+        for s_ in range(nsw):
+            x = sweeps.sweep_lo(x, bl, c32[(2 + s_) % len(seq)], fmt, wt)
+        assert np.array_equal(host(ug)[inner], sweeps.lo_widen(x, fmt)[inner])
+
+
+@pytest.mark.parametrize("n", [(67, 45), (33, 17, 12)])
+def test_weighted_residuals(n):
+    h = H2.get(n) or H3.get(n)
+    u, f = rand_case(n, 5)
+    wt = sweeps.axis_weights(h, len(n))
+    p = srj.srj_plan(n, h, omega=[1.0], q=[1])
+    r = torch.zeros_like(dev(u))
+    got = srj.srj_residual(p, dev(u), dev(f), r)
+    b = sweeps.rhs(f, h)
+    r2, rmax = sweeps.residual_norms(u, b, wt)
+    assert math.isclose(got["l2"], math.sqrt(r2), rel_tol=1e-12)
+    assert got["linf"] == rmax
+    assert math.isclose(got["source_l2"], math.sqrt(sweeps.source_norm2(u, b, wt)), rel_tol=1e-12)
+    assert np.array_equal(host(r), sweeps.residual_field(u, b, wt))
+    norms = torch.zeros(4, dtype=torch.float64, device=DEV)
+    r2t = torch.zeros_like(r)
+    srj.srj_residual_static(n, h, dev(u), dev(f), norms, r2t)
+    assert np.array_equal(host(norms), np.array([got["l2"], got["linf"], got["source_l2"], got["relres"]]))
+    assert torch.equal(r2t, r)
+
+
+@pytest.mark.parametrize("n", [(67, 45), (33, 17, 12)])
+def test_weighted_solves_match_oracle(n):
+    h = H2.get(n) or H3.get(n)
+    nd = len(n)
+    rng = np.random.default_rng(9)
+    full = tuple(x + 2 for x in reversed(n))
+    u0 = workloads.random_ring(full, rng)
+    f = rng.standard_normal(full)
+    km = S.kappa_min_dirichlet(n, h)
+    w, q, seq = sched(4, km)
+    wseq = np.asarray(w)[seq]
+    ref = sweeps.solve(u0, f, h, wseq, 1e-10, 10 ** 6)
+    p = srj.srj_plan(n, h, omega=w, q=q, sequence=seq)
+    ug = dev(u0)
+    info = srj.srj_solve(p, ug, dev(f), 1e-10, 10 ** 6)
+    assert ref["status"] == "ok" and info["status"] == "ok"
+    assert info["sweeps"] == ref["sweeps"]
+    assert abs(info["relres"] - ref["relres"]) <= 1e-12 * ref["relres"]
+    assert np.array_equal(host(ug), ref["u"])
+    # the plan's own kappa_min for the weighted grid is the oracle's
+    p2 = srj.srj_plan(n, h, P=4)
+    assert math.isclose(srj.srj_plan_describe(p2)["kappa_min"], km, rel_tol=1e-13)
+    for fmt in ("f32", "f64"):
+        refi = sweeps.solve_ir(u0, f, h, wseq, 1e-10, 1, 200, fmt)
+        pi = srj.srj_plan(n, h, omega=w, q=q, sequence=seq, dtype=fmt)
+        ug = dev(u0)
+        ii = srj.srj_solve_ir(pi, ug, dev(f), 1e-10, 1, 200)
+        assert refi["status"] == "ok" and ii["status"] == "ok" and ii["cycles"] == refi["outer"]
+        assert np.array_equal(host(ug), refi["u"]), fmt
+
+
+def test_weighted_adjoint_matches_dense_gradient():
+    from paper_1511_04292_amd.autograd import srj_solve_diff
+
+    n, h = (11, 8), (1.0 / 12, 1.0 / 4.5)
+    rng = np.random.default_rng(12)
+    full = (n[1] + 2, n[0] + 2)
+    g = workloads.random_ring(full, rng)
+    f = np.zeros(full)
+    f[1:-1, 1:-1] = rng.standard_normal((n[1], n[0]))
+    ut = rng.standard_normal(full) * 0.1
+    km = S.kappa_min_dirichlet(n, h)
+    w, q, seq = sched(3, km)
+    plan = srj.srj_plan(n, h, omega=w, q=q, sequence=seq)
+    ft = dev(f).requires_grad_(True)
+    gt = dev(g).requires_grad_(True)
+    u = srj_solve_diff(ft, gt, plan, tol=1e-13, tol_backward=1e-13)
+    L = 0.5 * ((u - dev(ut))[1:-1, 1:-1] ** 2).sum()
+    L.backward()
+    df_ref, dg_ref = OA.grad_dense(f, g, ut, h)
+    assert np.max(np.abs(ft.grad.cpu().numpy() - df_ref)) <= 1e-9 * np.max(np.abs(df_ref))
+    assert np.max(np.abs(gt.grad.cpu().numpy() - dg_ref)) <= 1e-9 * np.max(np.abs(dg_ref))
+
+
+# ------------------------------------------------------------ the Sec. 5.1 case study
+
+@pytest.fixture(scope="module")
+def case():
+    return workloads.exp_xy_unit_square(585, 280)
+
+
+def test_case_study_product_planner_rows(case, golden_dir):
+    """The plan's own schedules for the two Neumann rows the paper names: N = 550 reproduces
+    the printed counts, cycle length, three largest weights and rho; N = 250 gives the
+    oracle's counts."""
+    d = {}
+    for line in open(f"{golden_dir}/worked_example.txt"):
+        if line.strip() and not line.startswith("#"):
+            k, *v = line.split()
+            d[k] = v
+    p550 = srj.srj_plan(case["n"], case["h"], P=10, n_eff=550)
+    ds = srj.srj_plan_describe(p550)
+    assert list(ds["q"]) == [int(x) for x in d["q"]] and ds["M"] == int(d["M"][0])
+    assert [float(f"{x:.6g}") for x in ds["omega"][:3]] == [float(x) for x in d["omega_head"]]
+    assert round(float(np.sum(ds["omega"] * ds["beta"])), 2) == float(d["rho"][0])
+    p250 = srj.srj_plan(case["n"], case["h"], P=10, n_eff=250)
+    o = S.optimal(10, S.kappa_min_neumann(250))
+    assert np.array_equal(srj.srj_plan_describe(p250)["q"], S.q_floor(o["beta"]))
+
+
+def test_case_study_solves_bitwise(case):
+    """SRJ P = 10 with the N = 550 and N = 250 rows on the 585 x 280 unit square: GPU and
+    oracle solves (relres 1e-10, checked at cycle ends) agree bit for bit; both converge
+    to within the discretisation error of u = -e^(xy)."""
+    hx, hy = case["h"]
+    sweeps_of = {}
+    for N in (550, 250):
+        km = S.kappa_min_neumann(N)
+        w, q, seq = sched(10, km)
+        ref = sweeps.solve(case["u0"], case["f"], case["h"], np.asarray(w)[seq], 1e-10, 10 ** 6)
+        p = srj.srj_plan(case["n"], case["h"], omega=w, q=q, sequence=seq)
+        ug = dev(case["u0"])
+        info = srj.srj_solve(p, ug, dev(case["f"]), 1e-10, 10 ** 6)
+        assert info["status"] == "ok" and info["sweeps"] == ref["sweeps"], (N, info, ref["sweeps"])
+        got = host(ug)
+        assert np.array_equal(got, ref["u"]), N
+        err = float(np.max(np.abs(got - case["u_exact"])))
+        assert err <= (hx * hx + hy * hy) * math.e / 96 + 1e-6, (N, err)
+        sweeps_of[N] = info["sweeps"]
+    assert sweeps_of[250] < sweeps_of[550]
+
+
+def test_case_study_jacobi_window_bitwise(case):
+    p = srj.srj_plan(case["n"], case["h"], omega=[1.0], q=[1])
+    ug = dev(case["u0"])
+    srj.srj_sweeps(p, ug, dev(case["f"]), 0, 500)
+    wt = sweeps.axis_weights(case["h"], 2)
+    ref = sweeps.run(case["u0"], sweeps.rhs(case["f"], case["h"]), sweeps.coefficients([1.0], 2, wt), 500, wt=wt)
+    assert np.array_equal(host(ug), ref)
+
+
+@pytest.mark.parametrize("mode", [1, 2, 3])
+def test_q_rounding_plans(mode):
+    """Plans built with the other integer conversions of Sec. 4.3 carry the oracle's counts
+    and solve to tolerance -- or, when the counts make the cycle factor exceed 1 somewhere on
+    the grid's spectrum (Sec. 4.3: the scheme then diverges; the ceiling does at P = 6,
+    N = 256, near kappa = 2), the plan is refused with SRJ_ESCHEDULE."""
+    wl = workloads.small_2d(100, seed=6)
+    km = S.kappa_min_neumann(256)
+    o = S.optimal(6, km)
+    q = S.q_counts(o["beta"], mode, o["w"], km)
+    kmax = 2.0 * math.cos(math.pi / 202) ** 2
+    grid = np.exp(np.linspace(math.log(km), math.log(kmax), 100001))
+    if np.max(np.abs(spectral.cycle_factor(o["w"], q, grid))) >= 1.0:
+        with pytest.raises(srj.SrjError) as e:
+            srj.srj_plan(wl["n"], wl["h"], P=6, n_eff=256, q_rounding=mode)
+        assert e.value.status == 4
+        return
+    p = srj.srj_plan(wl["n"], wl["h"], P=6, n_eff=256, q_rounding=mode)
+    assert np.array_equal(srj.srj_plan_describe(p)["q"], q)
+    ug = dev(wl["u0"])
+    info = srj.srj_solve(p, ug, dev(wl["f"]), 1e-10, 10 ** 6)
+    assert info["status"] == "ok"

@@ -270,3 +270,39 @@ def test_regular_row_optimality_in_extended_precision(golden_dir):
     _, _, max_p, _ = _mp_optimality(row[2], row[3], km)
     assert sp_o < 1e-11 and res_o < 1e-16 and min(mu_o) > 0
     assert max_o <= max_p <= max_o * (1 - 1e-3)
+
+
+def test_q_counts_simple_modes():
+    """Sec. 4.3's conversions on fractions worked by hand: ratios 1, 3.49, 7.51, 88."""
+    beta = [0.01, 0.0349, 0.0751, 0.88]
+    assert list(S.q_counts(beta, 0)) == [1, 3, 7, 88]
+    assert list(S.q_counts(beta, 1)) == [1, 3, 8, 88]
+    assert list(S.q_counts(beta, 2)) == [1, 4, 8, 88]
+    assert list(S.q_counts(beta, 0)) == list(S.q_floor(beta))
+
+
+def test_q_counts_best_combination_is_the_exhaustive_minimum():
+    """Mode 3 against an independent exhaustive search (numpy over a dense grid): no other
+    floor/ceiling combination has a smaller per-step factor, and its factor is at most
+    floor's, ceiling's and nearest's."""
+    import itertools
+
+    km = S.kappa_min_neumann(256)
+    o = S.optimal(5, km)
+    w, beta = o["w"], o["beta"]
+    best = S.q_counts(beta, 3, w, km)
+    grid = np.exp(np.linspace(math.log(km), math.log(2.0), 4096))
+    grid[0], grid[-1] = km, 2.0
+    L = np.log(np.abs(1.0 - np.asarray(w)[:, None] * grid[None, :]))
+
+    def rate(q):
+        q = np.asarray(q, dtype=np.float64)
+        return float(np.max(q @ L)) / float(np.sum(q))
+
+    r = beta / beta[0]
+    choices = [[1]] + [sorted({int(math.floor(x)), int(math.ceil(x))}) for x in r[1:]]
+    rates = {qs: rate(qs) for qs in itertools.product(*choices)}
+    assert rate(best) <= min(rates.values()) * (1 - 1e-12) or math.isclose(rate(best), min(rates.values()),
+                                                                              rel_tol=1e-12)
+    for mode in (0, 1, 2):
+        assert rate(best) <= rate(S.q_counts(beta, mode)) + 1e-15

@@ -290,3 +290,157 @@ def test_lo_sweep_matches_matrix_form(fmt, shape):
     ring = np.ones(full, bool)
     ring[inner] = False
     assert np.array_equal(out[ring], u_s[ring])
+
+
+# ------------------------------------------------------- unequal spacings (Sec. 5.1 case)
+
+H2 = (1.0 / 12, 1.0 / 7)         # h_x, h_y
+H3 = (1.0 / 6, 1.0 / 9, 1.0 / 4)  # h_x, h_y, h_z
+
+
+def _weighted_dense_by_hand(shape_interior_xyz, h):
+    """-lap_h * h_x^2 assembled from its definition, one coupling at a time (independent of
+    spectral.dense_matrix): off-diagonals -(h_x/h_i)^2 on axis i, diagonal their sum twice."""
+    nd = len(shape_interior_xyz)
+    n = int(np.prod(shape_interior_xyz))
+    A = np.zeros((n, n))
+
+    def idx(p):  # p = (x, y[, z]) -> row-major index with x fastest
+        k = 0
+        for a in reversed(range(nd)):
+            k = k * shape_interior_xyz[a] + p[a]
+        return k
+
+    for flat in range(n):
+        p, r = [], flat
+        for a in range(nd):
+            p.append(r % shape_interior_xyz[a])
+            r //= shape_interior_xyz[a]
+        for a in range(nd):
+            wa = (h[0] / h[a]) ** 2
+            A[flat, flat] += 2 * wa
+            for d in (-1, 1):
+                q = list(p)
+                q[a] += d
+                if 0 <= q[a] < shape_interior_xyz[a]:
+                    A[flat, idx(q)] -= wa
+    return A
+
+
+@pytest.mark.parametrize("h", [H2, H3])
+def test_weighted_matrix_and_weights(h):
+    nd = len(h)
+    shape_xyz = (5, 4) if nd == 2 else (3, 4, 2)
+    wt = sweeps.axis_weights(h, nd)
+    A = spectral.dense_matrix(tuple(reversed(shape_xyz)), wt)
+    np.testing.assert_allclose(A, _weighted_dense_by_hand(shape_xyz, h), rtol=1e-14, atol=1e-14)
+    # equal spacings give unit weights and the diagonal 2d exactly
+    assert list(sweeps.axis_weights(0.125, nd)) == [1.0, 1.0, 2.0 * nd]
+
+
+@pytest.mark.parametrize("h", [H2, H3])
+def test_weighted_sweep_matches_matrix_form(h):
+    nd = len(h)
+    shape = (6, 11) if nd == 2 else (5, 4, 6)  # array order (z,) y, x
+    rng = np.random.default_rng(21)
+    full = tuple(n + 2 for n in shape)
+    u = rng.uniform(-1, 1, size=full)
+    f = rng.uniform(-1, 1, size=full)
+    wt = sweeps.axis_weights(h, nd)
+    b = sweeps.rhs(f, h)
+    c = 37.5 / wt[2]
+    out = sweeps.sweep(u, b, c, wt)
+    inner = tuple(slice(1, -1) for _ in shape)
+    x = u[inner].ravel()
+    ref = x + c * (spectral.load_vector(u, b, wt).ravel() - spectral.dense_matrix(shape, wt) @ x)
+    scale = np.max(np.abs(u)) * (1 + 2 * wt[2] * abs(c)) + abs(c) * np.max(np.abs(b))
+    assert np.max(np.abs(out[inner].ravel() - ref)) <= 8e-16 * scale
+    # the residual loops agree with the matrix form
+    r = sweeps.residual_field(u, b, wt)
+    rr = spectral.load_vector(u, b, wt).ravel() - spectral.dense_matrix(shape, wt) @ x
+    assert np.max(np.abs(r[inner].ravel() - rr)) <= 8e-16 * scale / abs(c)
+    r2, rmax = sweeps.residual_norms(u, b, wt)
+    assert math.isclose(r2, float(np.sum(rr * rr)), rel_tol=1e-13)
+    assert math.isclose(rmax, float(np.max(np.abs(rr))), rel_tol=1e-13)
+
+
+@pytest.mark.parametrize("h", [H2, H3])
+def test_weighted_dst_solve_equals_dense_lu_and_kappa_min(h):
+    nd = len(h)
+    shape = (9, 12) if nd == 2 else (4, 6, 5)
+    u, f = _rand_problem(shape, 22)
+    wt = sweeps.axis_weights(h, nd)
+    b = sweeps.rhs(f, h)
+    a = spectral.exact_solve(u, b, wt)
+    d = spectral.dense_solve(u, b, wt)
+    assert np.max(np.abs(a - d)) <= 1e-12 * np.max(np.abs(d))
+    ev = np.linalg.eigvalsh(spectral.dense_matrix(shape, wt))
+    np.testing.assert_allclose(np.sort(spectral.eigenvalues(shape, wt).ravel()), ev, rtol=1e-12, atol=1e-12)
+    n_xyz = tuple(reversed(shape))
+    assert math.isclose(schedule.kappa_min_dirichlet(n_xyz, h), ev[0] / wt[2], rel_tol=1e-12)
+
+
+def test_weighted_cycles_follow_exact_modal_trajectory():
+    shape = (13, 19)
+    u, f = _rand_problem(shape, 23)
+    wt = sweeps.axis_weights(H2, 2)
+    b = sweeps.rhs(f, H2)
+    omega = [60.0, 6.0, 0.8]
+    q = [1, 3, 12]
+    seq = [0, 2, 2, 2, 1, 2, 2, 2, 2, 1, 2, 2, 2, 2, 1, 2]
+    c = sweeps.coefficients(np.array(omega)[seq], 2, wt)
+    for m in (1, 3):
+        got = sweeps.run(u, b, c, m * len(seq), wt=wt)
+        ref = spectral.predicted_state(u, b, omega, q, m, wt)
+        assert np.max(np.abs(got - ref)) <= 1e-11 * np.max(np.abs(ref))
+
+
+def test_case_study_discretisation_is_second_order():
+    """Sec. 5.1: -lap u = (x^2 + y^2) e^(xy) on the unit square with u = -e^(xy) on the
+    boundary.  The exact discrete solution on 585 x 280 zones differs from -e^(xy) by
+    O(h_x^2 + h_y^2): at most (h_x^2 + h_y^2) e / 96 (truncation error at most
+    (h_x^2 + h_y^2) e / 12, discrete Laplacian inverse at most 1/8 in the max norm on the unit
+    square), and halving both spacings divides the error by 4."""
+    errs = []
+    for zones in ((146, 70), (292, 140), (585, 280)):
+        wl = workloads.exp_xy_unit_square(*zones)
+        wt = sweeps.axis_weights(wl["h"], 2)
+        us = spectral.exact_solve(wl["u0"], sweeps.rhs(wl["f"], wl["h"]), wt)
+        err = float(np.max(np.abs(us - wl["u_exact"])))
+        hx, hy = wl["h"]
+        assert err <= (hx * hx + hy * hy) * math.e / 96
+        errs.append(err)
+    assert 3.95 < errs[0] / errs[1] < 4.05
+
+
+@pytest.mark.parametrize("fmt", ["f32", "bf16"])
+def test_weighted_lo_sweep_matches_matrix_form(fmt):
+    rng = np.random.default_rng(24)
+    shape = (7, 10)
+    full = tuple(n + 2 for n in shape)
+    u = rng.uniform(-1, 1, size=full)
+    b = rng.uniform(-1e-3, 1e-3, size=full)
+    wt = sweeps.axis_weights(H2, 2)
+    w32 = wt.astype(np.float32).astype(np.float64)
+    c32 = np.float32(1234.5 / wt[2])
+    c = float(c32)
+    inner = (slice(1, -1), slice(1, -1))
+    if fmt == "f32":
+        u_s, b_s = u.astype(np.float32), b.astype(np.float32)
+        x, bx = u_s.astype(np.float64), b_s.astype(np.float64)
+    else:
+        u_s, b_s = sweeps.to_bf16_bits(u.astype(np.float32)), sweeps.to_bf16_bits(b.astype(np.float32))
+        x, bx = sweeps.from_bf16_bits(u_s).astype(np.float64), sweeps.from_bf16_bits(b_s).astype(np.float64)
+    out = sweeps.sweep_lo(u_s, b_s, c32, fmt, wt)
+    got = out.astype(np.float64) if fmt == "f32" else sweeps.from_bf16_bits(out).astype(np.float64)
+    A = spectral.dense_matrix(shape, w32)
+    ref = (x[inner].ravel() + c * (spectral.load_vector(x, bx, w32).ravel() - A @ x[inner].ravel())).reshape(shape)
+    a = np.abs(x)
+    nb = (a[1:-1, :-2] + a[1:-1, 2:]) + w32[0] * (a[:-2, 1:-1] + a[2:, 1:-1])
+    bound = 8 * 2.0 ** -24 * (a[inner] + abs(c) * (nb + np.abs(bx[inner]) + w32[2] * a[inner]))
+    if fmt == "f32":
+        assert np.all(np.abs(got[inner] - ref) <= bound)
+    else:
+        lo = sweeps.from_bf16_bits(sweeps.to_bf16_bits((ref - bound).astype(np.float32))).astype(np.float64)
+        hi = sweeps.from_bf16_bits(sweeps.to_bf16_bits((ref + bound).astype(np.float32))).astype(np.float64)
+        assert np.all((lo <= got[inner]) & (got[inner] <= hi))

@@ -51,7 +51,7 @@ def test_static_residual_rejects_grids_beyond_its_scratch():
     g = srj._Grid()
     g.ndim = 2
     g.n[0], g.n[1] = 4, 600000  # 600000 rows > 524288 the scratch holds
-    g.h = 1e-6
+    g.h[0] = g.h[1] = 1e-6
     g.dtype = 0
     import ctypes
 
