@@ -205,6 +205,16 @@ ld maxabs(int n, const ld* v)
     return m;
 }
 
+// Trust region of both solvers: no unknown moves by more than 1 per step (the unknowns are
+// logits of positions inside their intervals; a longer step can swap the order of weights
+// and land near another, spurious root).
+inline void clamp_step(int n, ld* d)
+{
+    const ld m = maxabs(n, d);
+    if (m > 1.0L)
+        for (int i = 0; i < n; ++i) d[i] /= m;
+}
+
 // Levenberg-Marquardt on F(z) = 0 with a forward-difference Jacobian.
 bool levmar(const Sys& s, ld* z, ld tol, int maxit)
 {
@@ -249,6 +259,7 @@ bool levmar(const Sys& s, ld* z, ld tol, int maxit)
                 d[a] = -JtF[a];
             }
             if (linsolve(n, M, d)) {
+                clamp_step(n, d);
                 for (int a = 0; a < n; ++a) zt[a] = z[a] + d[a];
                 if (residual(s, zt, Ft, &ev)) {
                     ld ft = 0.0L;
@@ -293,6 +304,7 @@ bool newton(const Sys& s, ld* z, ld tol, int maxit)
         ld d[2 * SRJ_PLAN_MAXP];
         for (int i = 0; i < n; ++i) d[i] = -F[i];
         if (!linsolve(n, J, d)) return false;
+        clamp_step(n, d);
         ld lam = 1.0L; bool acc = false;
         for (int ls = 0; ls < 30; ++ls) {
             for (int a = 0; a < n; ++a) zt[a] = z[a] + lam * d[a];
@@ -354,6 +366,41 @@ bool solve_from_weights(Sys& s, const ld* wguess, ld* z, Eval* ev)
 
 }  // namespace
 
+// Carry a solved P-level system from s.km to target by continuation in log km (the unknowns
+// are positions relative to the interval, so the previous solution is the starting point at
+// the next km); steps are halved on failure, and more than 40 consecutive halvings give up.
+static bool continue_to(Sys& s, ld* z, Eval* ev, ld target)
+{
+    const int P = s.P;
+    ld cur = logl(s.km), tgt = logl(target);
+    int nst = std::max(1, (int)ceill(fabsl(tgt - cur) / 0.25L));
+    ld step = (tgt - cur) / nst;
+    int fails = 0;
+    ld zs[2 * SRJ_PLAN_MAXP];
+    while (fabsl(tgt - cur) > 1e-15L) {
+        ld nxt = cur + step;
+        if ((step > 0 && nxt > tgt) || (step < 0 && nxt < tgt)) nxt = tgt;
+        Sys s2 = s;
+        s2.km = expl(nxt);
+        if (nxt == tgt) s2.km = target;
+        s2.a = logl(s2.km);
+        std::memcpy(zs, z, sizeof(ld) * (2 * P - 1));
+        Eval ev2;
+        if (!newton(s2, zs, 1e-14L, 60)) levmar(s2, zs, 1e-14L, 100);
+        if (!valid(s2, zs, &ev2)) {
+            step *= 0.5L;
+            if (++fails > 40) return false;
+            continue;
+        }
+        fails = 0;
+        std::memcpy(z, zs, sizeof(ld) * (2 * P - 1));
+        *ev = ev2;
+        s = s2;
+        cur = nxt;
+    }
+    return true;
+}
+
 bool optimal_schedule(int P, double km_d, double kM_d, Optimum* out, std::string* err)
 {
     if (P < 1 || P > SRJ_PLAN_MAXP) {
@@ -371,8 +418,12 @@ bool optimal_schedule(int P, double km_d, double kM_d, Optimum* out, std::string
         out->kappa.clear();
         return true;
     }
-    // grow levels at a moderate resolution (N = 100 of Eq. boundaries)
-    const ld kb = powl(sinl(3.14159265358979323846264338327950288L / 200.0L), 2);
+    const ld pi = 3.14159265358979323846264338327950288L;
+    // grow levels at a moderate resolution (N = 100 of Eq. boundaries), or at N = 2000 when
+    // more than 12 are wanted (few levels fit a coarse interval: Sec. 4.2 reports the same
+    // limit); the 2-level solution is carried there by continuation
+    const ld kb = powl(sinl(pi / 200.0L), 2);
+    const ld kseed = P > 12 ? powl(sinl(pi / 4000.0L), 2) : kb;
     Sys s;
     s.kM = kM;
     s.c = logl(kM);
@@ -386,10 +437,22 @@ bool optimal_schedule(int P, double km_d, double kM_d, Optimum* out, std::string
         if (err) *err = "optimiser failed for 2 levels at the seed resolution";
         return false;
     }
+    if (kseed != kb && !continue_to(s, z, &ev, kseed)) {
+        if (err) *err = "continuation to the seed resolution failed";
+        return false;
+    }
+    // log w_1 and log(w_P - 1/2) of the levels solved so far, for the extrapolated guess
+    std::vector<ld> hist_first{logl(ev.w[0])}, hist_last{logl(ev.w[1] - 0.5L)};
+    auto extrapolate = [](const std::vector<ld>& v) {
+        const size_t m = v.size();
+        if (m == 1) return v[0];
+        if (m == 2) return 2.0L * v[1] - v[0];
+        return v[m - 3] - 3.0L * v[m - 2] + 3.0L * v[m - 1];  // parabola through the last three
+    };
     for (int p = 3; p <= P; ++p) {
         ld t[SRJ_PLAN_MAXP], t2[SRJ_PLAN_MAXP], wg[SRJ_PLAN_MAXP];
-        tpos(ev.w, p - 1, kb, kM, t);
-        // resample the (p-1)-level shape at p points, pulling both ends outwards
+        tpos(ev.w, p - 1, s.km, kM, t);
+        // first guess: the (p-1)-level shape resampled at p points, both ends pulled outwards
         for (int i = 0; i < p; ++i) {
             ld x = (ld)i / (ld)(p - 1) * (ld)(p - 2);
             int i0 = std::min((int)floorl(x), p - 3);
@@ -399,43 +462,33 @@ bool optimal_schedule(int P, double km_d, double kM_d, Optimum* out, std::string
         ld f = powl((ld)(p - 1) / (ld)p, 2);
         t2[0] = t[0] * f;
         t2[p - 1] = 1.0L - (1.0L - t[p - 2]) * f;
-        from_t(t2, p, kb, kM, wg);
-        s.P = p;
-        if (!solve_from_weights(s, wg, z, &ev)) {
+        from_t(t2, p, s.km, kM, wg);
+        Sys sp = s;
+        sp.P = p;
+        ld zp[2 * SRJ_PLAN_MAXP];
+        Eval evp;
+        bool ok = solve_from_weights(sp, wg, zp, &evp);
+        if (!ok) {
+            // second guess (Sec. 3.3): both end weights extrapolated in P from the levels
+            // solved so far, inverse weights spread logarithmically between them
+            const ld w1 = std::min(expl(extrapolate(hist_first)), 0.999L / s.km);
+            const ld wP = 0.5L + expl(extrapolate(hist_last));
+            for (int i = 0; i < p; ++i) wg[i] = expl(logl(w1) + (ld)i / (ld)(p - 1) * (logl(wP) - logl(w1)));
+            ok = solve_from_weights(sp, wg, zp, &evp);
+        }
+        if (!ok) {
             if (err) *err = "optimiser failed while adding level " + std::to_string(p);
             return false;
         }
+        s = sp;
+        std::memcpy(z, zp, sizeof(z));
+        ev = evp;
+        hist_first.push_back(logl(ev.w[0]));
+        hist_last.push_back(logl(ev.w[p - 1] - 0.5L));
     }
-    // continuation in log km (the unknowns are positions relative to the interval, so the
-    // previous solution is the starting point at the next km)
-    ld cur = logl(kb), tgt = logl(km);
-    int nst = std::max(1, (int)ceill(fabsl(tgt - cur) / 0.25L));
-    ld step = (tgt - cur) / nst;
-    int fails = 0;
-    ld zs[2 * SRJ_PLAN_MAXP];
-    while (fabsl(tgt - cur) > 1e-15L) {
-        ld nxt = cur + step;
-        if ((step > 0 && nxt > tgt) || (step < 0 && nxt < tgt)) nxt = tgt;
-        Sys s2 = s;
-        s2.km = expl(nxt);
-        if (nxt == tgt) s2.km = km;
-        s2.a = logl(s2.km);
-        std::memcpy(zs, z, sizeof(ld) * (2 * P - 1));
-        Eval ev2;
-        if (!newton(s2, zs, 1e-14L, 60)) levmar(s2, zs, 1e-14L, 100);
-        const bool ok = valid(s2, zs, &ev2);
-        if (!ok) {
-            step *= 0.5L;
-            if (++fails > 40) {
-                if (err) *err = "continuation to the target kappa_min failed";
-                return false;
-            }
-            continue;
-        }
-        std::memcpy(z, zs, sizeof(ld) * (2 * P - 1));
-        ev = ev2;
-        s = s2;
-        cur = nxt;
+    if (!continue_to(s, z, &ev, km)) {
+        if (err) *err = "continuation to the target kappa_min failed";
+        return false;
     }
     out->w.assign(P, 0.0);
     out->beta.assign(P, 0.0);

@@ -306,3 +306,24 @@ def test_q_counts_best_combination_is_the_exhaustive_minimum():
                                                                               rel_tol=1e-12)
     for mode in (0, 1, 2):
         assert rate(best) <= rate(S.q_counts(beta, mode)) + 1e-15
+
+
+@pytest.mark.parametrize("P,N", [(15, 64), (14, 4096)])
+def test_p14_p15_oracle_rows_solve_the_system(golden_dir, P, N):
+    """The oracle's P = 14 / 15 schemes (Tables 2-3 resolutions) satisfy the optimality
+    system of Sec. 3.2 in 30-digit arithmetic, with a lower maximum of Gamma than the printed
+    row; its rho exceeds the printed one by less than 1%."""
+    rows = []
+    for line in open(os.path.join(golden_dir, "table2_3.txt")):
+        if line.strip() and not line.startswith("#"):
+            a = line.split("|")
+            if tuple(map(int, a[0].split())) == (P, N):
+                rows.append((np.array(list(map(float, a[1].split()))), np.array(list(map(float, a[2].split()))),
+                             float(a[3])))
+    w_p, b_p, rho_p = rows[0]
+    km = S.kappa_min_neumann(N)
+    o = S.optimal(P, km)
+    sp, res, mx, mu = _mp_optimality(o["w"], o["beta"], km)
+    assert sp < 1e-10 and res < 1e-16 and min(mu) > 0, (sp, res, mu)
+    assert mx <= _mp_optimality(w_p, b_p, km)[2]
+    assert rho_p <= S.rho(o["w"], o["beta"]) <= 1.01 * rho_p
