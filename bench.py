@@ -368,6 +368,7 @@ def main():
         torch.cuda.empty_cache()
         other = {}
         for name, fn in (("small_2d_64", bench_small_2d), ("case_study_585x280", bench_case_study),
+                         ("neumann_calibration_256", bench_neumann_calibration),
                          ("smooth3d_512", bench_3d), ("batch_1024", bench_batch),
                          ("adjoint_2048", bench_adjoint), ("huge_2d_32768", bench_huge_2d)):
             print(f"bench: {name} ...", file=sys.stderr, flush=True)
@@ -543,6 +544,44 @@ def bench_case_study(torch, srj, workloads, tol=1e-10):
         out[name]["measured_acceleration_vs_jacobi"] = round(out["jacobi"]["sweeps"] / out[name]["sweeps"], 2)
     out["N250_fewer_sweeps_than_N550_pct"] = round(
         100.0 * (1.0 - out["srj_N250"]["sweeps"] / out["srj_N550"]["sweeps"]), 2)
+    return out
+
+
+def bench_neumann_calibration(torch, srj, workloads, n=256, tol=1e-10):
+    """The calibration of Sec. 4.1 on the paper's own model problem (Eq. Laplace: homogeneous
+    Neumann, 256^2 cells, as in Fig. 2): SRJ P = 2..5 with the Neumann table rows for N = 256
+    against plain Jacobi, from a seeded random start (U(-1,1)), to ||r|| <= 1e-10 ||r_0||
+    (checked at cycle ends, every sweep for Jacobi).  Measured acceleration (Jacobi sweeps /
+    SRJ sweeps) beside rho (Eq. rho) and the asymptotic rate ratio of the slowest mode."""
+    import numpy as np
+
+    rng = np.random.default_rng(0)
+    u0h = rng.uniform(-1.0, 1.0, (n + 2, n + 2))
+    u0 = torch.from_numpy(u0h).to("cuda:0")
+    f = torch.zeros_like(u0)
+    out = {"workload": f"Eq. Laplace, homogeneous Neumann, {n}^2 cells, random start U(-1,1), "
+                       f"relres {tol:g} against the initial residual"}
+    runs = {"jacobi": dict(omega=[1.0], q=[1])}
+    for P in (2, 3, 4, 5):
+        runs[f"srj_P{P}"] = dict(P=P, n_eff=float(n))
+    for name, kw in runs.items():
+        plan = srj.srj_plan((n, n), 1.0 / n, bc="neumann", **kw)
+        d = srj.srj_plan_describe(plan)
+        u = u0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = srj.srj_solve(plan, u, f, tol, 10 ** 8)
+        torch.cuda.synchronize()
+        r = {"seconds": round(time.perf_counter() - t0, 4), "sweeps": int(info["sweeps"]),
+             "relres": info["relres"], "status": info["status"], "M": int(d["M"])}
+        if name != "jacobi":
+            km = d["kappa_min"]
+            r.update(rho=round(float(np.sum(d["omega"] * d["beta"])), 3), q=[int(x) for x in d["q"]],
+                     rate_ratio_slowest_mode=round(math.log(d["gamma_q_max"]) / math.log(1.0 - km), 3))
+        out[name] = r
+        del plan
+    for P in (2, 3, 4, 5):
+        out[f"srj_P{P}"]["measured_acceleration"] = round(out["jacobi"]["sweeps"] / out[f"srj_P{P}"]["sweeps"], 3)
     return out
 
 

@@ -65,6 +65,18 @@ typedef struct {
     int64_t n[3];     /* interior points per axis, n[0] = x (fastest); n[2] unused in 2D */
     double h[3];      /* spacing per axis, h[0] = x (unit box: 1 / (n_i + 1)); h[2] unused in 2D */
     int32_t dtype;    /* srj_dtype of the sweeps */
+    int32_t bc;       /* 0: Dirichlet, the ring holds the boundary values.  1: homogeneous
+                         Neumann on a cell-centred grid of n_i >= 2 cells per axis (Sec. 3.1,
+                         Eq. Laplace; unit box: h_i = 1 / n_i): the ring is a row of ghost
+                         cells mirroring their neighbours and is never read, a neighbour
+                         across the boundary being the cell itself.  Neumann plans are binary64
+                         and run one sweep per launch; the operator is singular (constants
+                         solve A u = 0), so the source must have zero mean and srj_solve
+                         measures relres against the initial residual ||r(u_0)|| (u_0
+                         returned unchanged if that is 0).  The schedule's default
+                         interval starts at the smallest nonzero symbol, (2/d) sin^2(pi / 2N)
+                         with N = max n_i for equal spacings (Eq. boundaries1D3D).  Not for
+                         srj_solve_ir, srj_adjoint, batches or srj_residual_static. */
 } srj_grid;
 
 /* Schedule request (Sec. 2-4).
@@ -155,7 +167,8 @@ srj_status srj_sweeps(srj_plan_t plan, double* u, const double* f, int64_t k0, i
                       double* stats);
 
 /* norms[0] = ||r||_2, norms[1] = max |r|, norms[2] = ||b~||_2, norms[3] = relres, for
- * r = b - A u in binary64.  r_out (device, full-grid layout, ring set to 0) may be NULL. */
+ * r = b - A u in binary64.  r_out (device, full-grid layout, ring set to 0) may be NULL.
+ * (Neumann grids: b~ = b, the residual of the zero state.) */
 srj_status srj_residual(srj_plan_t plan, const double* u, const double* f, double* r_out,
                         double norms[4]);
 

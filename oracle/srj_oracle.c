@@ -308,3 +308,102 @@ void or_sweep3d_bf16(int64_t nx, int64_t ny, int64_t nz, const uint16_t* u, cons
                 out[I3(k, i, j)] = bf_store(uc + c * t);
             }
 }
+
+/* ------------------------------------------- homogeneous Neumann (Sec. 3.1 model problem) */
+/* Cell-centred grid of n_i cells per axis; the ring holds ghost cells that mirror the
+ * adjacent cell (zero normal derivative), so a neighbour across the boundary is the cell
+ * itself.  The ring is never read.  Weights and association as the Dirichlet step. */
+
+static inline double nb2(const double* u, int64_t nx, int64_t ny, int64_t i, int64_t j, int64_t di, int64_t dj)
+{
+    int64_t ii = i + di, jj = j + dj;
+    if (ii < 1 || ii > ny) ii = i;
+    if (jj < 1 || jj > nx) jj = j;
+    return u[I2(ii, jj)];
+}
+
+static inline double nb3(const double* u, int64_t nx, int64_t ny, int64_t nz, int64_t k, int64_t i, int64_t j,
+                         int64_t dk, int64_t di, int64_t dj)
+{
+    int64_t kk = k + dk, ii = i + di, jj = j + dj;
+    if (kk < 1 || kk > nz) kk = k;
+    if (ii < 1 || ii > ny) ii = i;
+    if (jj < 1 || jj > nx) jj = j;
+    return u[I3(kk, ii, jj)];
+}
+
+void or_sweep2d_neu(int64_t nx, int64_t ny, const double* u, const double* b, const double* wt, double c,
+                    double* out)
+{
+    const double wy = wt[0], dg = wt[2];
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 1; i <= ny; ++i)
+        for (int64_t j = 1; j <= nx; ++j) {
+            double s = (nb2(u, nx, ny, i, j, 0, -1) + nb2(u, nx, ny, i, j, 0, 1)) +
+                       wy * (nb2(u, nx, ny, i, j, -1, 0) + nb2(u, nx, ny, i, j, 1, 0));
+            double t = (s + b[I2(i, j)]) - dg * u[I2(i, j)];
+            out[I2(i, j)] = u[I2(i, j)] + c * t;
+        }
+}
+
+void or_sweep3d_neu(int64_t nx, int64_t ny, int64_t nz, const double* u, const double* b, const double* wt,
+                    double c, double* out)
+{
+    const double wy = wt[0], wz = wt[1], dg = wt[2];
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 1; k <= nz; ++k)
+        for (int64_t i = 1; i <= ny; ++i)
+            for (int64_t j = 1; j <= nx; ++j) {
+                double s = ((nb3(u, nx, ny, nz, k, i, j, 0, 0, -1) + nb3(u, nx, ny, nz, k, i, j, 0, 0, 1)) +
+                            wy * (nb3(u, nx, ny, nz, k, i, j, 0, -1, 0) + nb3(u, nx, ny, nz, k, i, j, 0, 1, 0))) +
+                           wz * (nb3(u, nx, ny, nz, k, i, j, -1, 0, 0) + nb3(u, nx, ny, nz, k, i, j, 1, 0, 0));
+                double t = (s + b[I3(k, i, j)]) - dg * u[I3(k, i, j)];
+                out[I3(k, i, j)] = u[I3(k, i, j)] + c * t;
+            }
+}
+
+/* r = b - A u with the mirrored neighbours; field (ring 0) and, in out, sum r^2 (compensated
+ * per line, then over lines) and max |r|. */
+void or_residual_neu(int64_t nx, int64_t ny, int64_t nz, int ndim, const double* u, const double* b,
+                     const double* wt, double* r, double* out, double* rowsum, double* rowmax)
+{
+    const double wy = wt[0], wz = wt[1], dg = wt[2];
+    const int64_t planes = ndim == 3 ? nz : 1;
+    memset(r, 0, sizeof(double) * (size_t)(nx + 2) * (size_t)(ny + 2) * (size_t)(ndim == 3 ? nz + 2 : 1));
+#pragma omp parallel for schedule(static)
+    for (int64_t line = 0; line < planes * ny; ++line) {
+        const int64_t k = ndim == 3 ? line / ny + 1 : 0, i = line % ny + 1;
+        kahan_t acc = {0.0, 0.0};
+        double m = 0.0;
+        for (int64_t j = 1; j <= nx; ++j) {
+            double s, uc, rv;
+            size_t p;
+            if (ndim == 3) {
+                s = ((nb3(u, nx, ny, nz, k, i, j, 0, 0, -1) + nb3(u, nx, ny, nz, k, i, j, 0, 0, 1)) +
+                     wy * (nb3(u, nx, ny, nz, k, i, j, 0, -1, 0) + nb3(u, nx, ny, nz, k, i, j, 0, 1, 0))) +
+                    wz * (nb3(u, nx, ny, nz, k, i, j, -1, 0, 0) + nb3(u, nx, ny, nz, k, i, j, 1, 0, 0));
+                p = I3(k, i, j);
+            } else {
+                s = (nb2(u, nx, ny, i, j, 0, -1) + nb2(u, nx, ny, i, j, 0, 1)) +
+                    wy * (nb2(u, nx, ny, i, j, -1, 0) + nb2(u, nx, ny, i, j, 1, 0));
+                p = I2(i, j);
+            }
+            uc = u[p];
+            rv = (s + b[p]) - dg * uc;
+            r[p] = rv;
+            kadd(&acc, rv * rv);
+            double a = fabs(rv);
+            if (a > m || a != a) m = a;
+        }
+        rowsum[line] = acc.s;
+        rowmax[line] = m;
+    }
+    kahan_t tot = {0.0, 0.0};
+    double m = 0.0;
+    for (int64_t line = 0; line < planes * ny; ++line) {
+        kadd(&tot, rowsum[line]);
+        if (rowmax[line] > m || rowmax[line] != rowmax[line]) m = rowmax[line];
+    }
+    out[0] = tot.s;
+    out[1] = m;
+}

@@ -50,13 +50,13 @@ namespace srj {
 srj_status report(srj_status s, const std::string& msg) { return fail(s, msg); }
 
 srj_status make_schedule(int d, const int64_t* n, const double* wt, const srj_schedule* sc, bool peaks,
-                         SchedOut* out, std::string* err)
+                         SchedOut* out, std::string* err, bool neumann)
 {
     auto bad = [&](srj_status st, const std::string& m) {
         *err = m;
         return st;
     };
-    const double kmax_grid = grid_kappa_max(d, n, wt);
+    const double kmax_grid = neumann ? neumann_kappa_max(d, n, wt) : grid_kappa_max(d, n, wt);
     if (sc->kappa_min > 0 && sc->n_eff > 0) return bad(SRJ_EINVAL, "give kappa_min or n_eff, not both");
     if (sc->kappa_min < 0 || sc->n_eff < 0 || !std::isfinite(sc->kappa_min) || !std::isfinite(sc->n_eff))
         return bad(SRJ_EINVAL, "kappa_min and n_eff must be finite and >= 0");
@@ -68,7 +68,7 @@ srj_status make_schedule(int d, const int64_t* n, const double* wt, const srj_sc
         const double v = std::sin(3.14159265358979323846 / (2.0 * sc->n_eff));
         out->kappa_min = v * v;
     } else {
-        out->kappa_min = grid_kappa_min(d, n, wt);
+        out->kappa_min = neumann ? neumann_kappa_min(d, n, wt) : grid_kappa_min(d, n, wt);
     }
     out->kappa_max = 2.0;
     if (!(out->kappa_min < out->kappa_max)) return bad(SRJ_EINVAL, "kappa_min must be below 2");
@@ -192,7 +192,7 @@ srj_status build_schedule(srj_plan_t p, const srj_schedule* sc)
     SchedOut o;
     std::string err;
     const double wt[3] = {p->geo.wy, p->geo.wz, p->geo.dg};
-    srj_status st = make_schedule(p->grid.ndim, p->grid.n, p->iso ? nullptr : wt, sc, true, &o, &err);
+    srj_status st = make_schedule(p->grid.ndim, p->grid.n, p->iso ? nullptr : wt, sc, true, &o, &err, p->geo.bc == 1);
     if (st != SRJ_OK) return fail(st, err);
     p->P = o.P;
     std::memcpy(p->omega, o.omega, sizeof(o.omega));
@@ -282,8 +282,10 @@ void fill_info(srj_solve_info* info, int64_t sweeps, int64_t cycles, double relr
 srj_status solve_fields(srj_plan_t p, double tol, int64_t max_sweeps, DField** cur, int64_t* k_out,
                         int64_t* cycles_out, double* rr_out, srj_status* result)
 {
+    // reference norm: ||b~|| (the residual of the zero interior); with Neumann boundaries the
+    // operator is singular and the reference is the initial residual
     double bt2, bmax;
-    srj_status st = residual_now(p, p->A.origin, p->fmt, 1, &bt2, &bmax);
+    srj_status st = residual_now(p, p->A.origin, p->fmt, p->geo.bc == 1 ? 0 : 1, &bt2, &bmax);
     if (st != SRJ_OK) return st;
     *cur = &p->A;
     DField* nxt = &p->B;
@@ -294,8 +296,9 @@ srj_status solve_fields(srj_plan_t p, double tol, int64_t max_sweeps, DField** c
         *result = SRJ_EDIVERGED;
         rr = NAN;
     } else if (bt2 == 0.0) {
-        // zero source and zero boundary: u = 0 is exact
-        HIPCHK(launch_zero(p->fmt, (*cur)->origin, p->geo, p->stream));
+        // Dirichlet: zero source and zero boundary, u = 0 is exact; Neumann: the initial
+        // state already has a zero residual and is returned as it is
+        if (p->geo.bc == 0) HIPCHK(launch_zero(p->fmt, (*cur)->origin, p->geo, p->stream));
         rr = 0.0;
     } else {
         for (;;) {
@@ -364,6 +367,11 @@ srj_status srj_plan(const srj_grid* grid, const srj_schedule* schedule, void* st
         if (!(grid->h[i] > 0) || !is_finite(grid->h[i])) return fail(SRJ_EINVAL, "every h[i] must be positive");
     }
     if (grid->dtype < 0 || grid->dtype > 2) return fail(SRJ_EINVAL, "dtype must be 0, 1 or 2");
+    if (grid->bc != 0 && grid->bc != 1) return fail(SRJ_EINVAL, "bc must be 0 (Dirichlet) or 1 (Neumann)");
+    if (grid->bc == 1 && grid->dtype != 0) return fail(SRJ_EINVAL, "Neumann grids are binary64 only");
+    if (grid->bc == 1)
+        for (int i = 0; i < grid->ndim; ++i)
+            if (grid->n[i] < 2) return fail(SRJ_EINVAL, "a Neumann grid needs at least 2 cells per axis");
     srj_plan_t p = new (std::nothrow) srj_plan_s();
     if (!p) return fail(SRJ_ENOMEM, "host allocation failed");
     p->grid = *grid;
@@ -379,6 +387,7 @@ srj_status srj_plan(const srj_grid* grid, const srj_schedule* schedule, void* st
     g.ny = grid->n[1];
     g.nz = grid->ndim == 3 ? grid->n[2] : 1;
     geo_set_weights(g, p->grid.h, &p->iso);
+    g.bc = grid->bc;
     p->hh = p->grid.h[0] * p->grid.h[0];
     srj_status st = build_schedule(p, schedule);
     if (st != SRJ_OK) {
@@ -420,7 +429,7 @@ srj_status srj_plan(const srj_grid* grid, const srj_schedule* schedule, void* st
     // 3D: 5 sweeps per launch for the 4- and 2-byte formats, 4 for binary64 (at 5 its
     // registers spill and the launch is slower per sweep); unequal spacings: one sweep per
     // launch (the temporally blocked kernels implement the equal-spacing operator only)
-    p->fuse = !p->iso ? 0
+    p->fuse = (!p->iso || g.bc != 0) ? 0
                       : (g.ndim == 2) ? kMaxFuse
                                       : (fused3d_fits(g, p->fmt) ? (p->fmt == FMT_F64 ? kMaxFuse3d - 1 : kMaxFuse3d) : 0);
     *out = p;
@@ -468,6 +477,7 @@ srj_status srj_plan_set_fusion(srj_plan_t p, int32_t fused, int32_t seg_rows)
     if (fused < 0 || fused > kMaxFuse) return fail(SRJ_EINVAL, "fusion depth must be in [0, 10]");
     if (p->geo.ndim == 3 && fused > kMaxFuse3d) return fail(SRJ_EINVAL, "3D fusion depth must be in [0, 5]");
     if (fused > 0 && !p->iso) return fail(SRJ_EINVAL, "fused sweeps need equal spacings on every axis");
+    if (fused > 0 && p->geo.bc != 0) return fail(SRJ_EINVAL, "fused sweeps need Dirichlet boundaries");
     if (p->geo.ndim == 3 && fused > 0 && !fused3d_fits(p->geo, p->fmt))
         return fail(SRJ_EINVAL, "z planes too large for the fused 3D kernel (1 GiB per plane at most)");
     if (seg_rows < 0 || seg_rows > (1 << 20)) return fail(SRJ_EINVAL, "segment rows must be in [0, 2^20]");
@@ -528,8 +538,8 @@ srj_status srj_plan_tune(srj_plan_t p, srj_tune_info* info)
     };
     std::vector<Cand> cands;
     cands.push_back({p->fuse, p->seg_rows});  // the configuration in place, timed first
-    if (!p->iso) {
-        // unequal spacings: the unfused kernel is the only one
+    if (!p->iso || p->geo.bc != 0) {
+        // unequal spacings or Neumann boundaries: the unfused kernel is the only one
     } else if (p->geo.ndim == 2) {
         for (int T : {10, 8, 6, 4})
             for (int H : {0, 24, 32, 48, 64, 96, 128}) cands.push_back({T, H});
@@ -625,6 +635,7 @@ srj_status srj_adjoint(srj_plan_t p, const double* grad_u, double tol, int64_t m
     fill_info(info, 0, 0, NAN, 0, SRJ_EINVAL);
     if (!p || !grad_u) return fail(SRJ_EINVAL, "null argument");
     if (p->fmt != FMT_F64) return fail(SRJ_EINVAL, "the adjoint solve needs an FP64 plan");
+    if (p->geo.bc != 0) return fail(SRJ_EINVAL, "the adjoint solve needs Dirichlet boundaries");
     if (!(tol >= 0) || max_sweeps < 0) return fail(SRJ_EINVAL, "bad tolerance or sweep budget");
     HIPCHK(hipEventRecord(p->ev0, p->stream));
     HIPCHK(launch_zero(p->fmt, p->A.origin, p->geo, p->stream));
@@ -649,6 +660,7 @@ srj_status srj_solve_ir(srj_plan_t p, double* u, const double* f, double tol, in
     fill_info(info, 0, 0, NAN, 0, SRJ_EINVAL);
     if (!p || !u || !f) return fail(SRJ_EINVAL, "null argument");
     if (!(tol >= 0) || inner_cycles < 1 || max_outer < 0) return fail(SRJ_EINVAL, "bad IR parameters");
+    if (p->geo.bc != 0) return fail(SRJ_EINVAL, "refinement needs Dirichlet boundaries");
     const double hh = p->hh;
     srj_status st;
     // the binary64 iterate lives in the plan's x64 field, b in b64; A/B hold the correction d

@@ -135,6 +135,7 @@ srj_status srj_batch_plan(int32_t count, const srj_grid* grids, const srj_schedu
             return report(SRJ_EINVAL, "n must be in [1, 2^20]");
         if (!(g.h[0] > 0) || !std::isfinite(g.h[0])) return report(SRJ_EINVAL, "h must be positive");
         if (g.h[1] != g.h[0]) return report(SRJ_EINVAL, "batched problems need equal spacings (h[0] == h[1])");
+        if (g.bc != 0) return report(SRJ_EINVAL, "batched problems need Dirichlet boundaries");
         if (g.dtype != dt || dt < 0 || dt > 2) return report(SRJ_EINVAL, "one storage format per batch");
     }
     srj_batch_t b = new (std::nothrow) srj_batch_s();
@@ -189,6 +190,7 @@ srj_status srj_batch_plan(int32_t count, const srj_grid* grids, const srj_schedu
         g.py = g.ny + 2;
         g.wy = g.wz = 1.0;  // equal spacings
         g.dg = 4.0;
+        g.bc = 0;
         const size_t elems = (size_t)(g.px * g.py);
         off_u0[j] = carve(elems, 8);
         off_u1[j] = carve(elems, 8);

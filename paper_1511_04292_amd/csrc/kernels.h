@@ -22,6 +22,9 @@ struct Geo {
     // wy = h_x^2 / h_y^2, wz = h_x^2 / h_z^2 (1 in 2D), diagonal dg = 2 (1 + wy) in 2D and
     // 2 ((1 + wy) + wz) in 3D; equal spacings give 1, 1 and 2d
     double wy, wz, dg;
+    // boundary: 0 Dirichlet (the ring holds the data), 1 homogeneous Neumann (cell-centred:
+    // a neighbour across the boundary is the cell itself; the ring is never read)
+    int bc;
 };
 
 // Geo's operator weights for spacings h[0..ndim); iso is set when they are all equal.
@@ -53,7 +56,7 @@ hipError_t launch_sweep_unfused(Fmt f, const void* in, void* out, const void* b,
 // T consecutive 2D sweeps in -> out in one launch with coefficients co.c[0..T), row
 // segments of H output rows per wave.  flip (0 or 1) reverses the direction every segment
 // streams in; callers alternate it from launch to launch (it changes no result).
-// (The temporally blocked kernels implement the equal-spacing operator only.)
+// (The temporally blocked kernels implement the equal-spacing Dirichlet operator only.)
 hipError_t launch_sweep_fused(Fmt f, const void* in, void* out, const void* b, const Geo& g,
                               const Coefs& co, int T, int H, int flip, hipStream_t s);
 // T <= kMaxFuse3d sweeps (coefficients co.c[0..T)) of a 3D grid in one launch: x-y tiles of

@@ -93,7 +93,9 @@ __global__ __launch_bounds__(256) void k_zero(S* __restrict__ f, int64_t n)
 // ------------------------------------------------------------- unfused sweeps
 
 // One sweep, one thread per interior point (reference kernel; also small grids).
-template <class S>
+// NEU: homogeneous Neumann boundaries (Sec. 3.1 model problem): a neighbour across the
+// boundary is the cell itself.
+template <class S, bool NEU>
 __global__ __launch_bounds__(256) void k_sweep2d(const S* __restrict__ u, S* __restrict__ o,
                                                  const S* __restrict__ b, int64_t px, int nx, int ny,
                                                  double wy64, double dg64, double c64)
@@ -104,8 +106,10 @@ __global__ __launch_bounds__(256) void k_sweep2d(const S* __restrict__ u, S* __r
     if (j > nx || i > ny) return;
     const Cm c = (Cm)c64, wy = (Cm)wy64, dg = (Cm)dg64;
     const int64_t p = (int64_t)i * px + j;
+    const int64_t pw = (NEU && j == 1) ? p : p - 1, pe = (NEU && j == nx) ? p : p + 1;
+    const int64_t ps = (NEU && i == 1) ? p : p - px, pn = (NEU && i == ny) ? p : p + px;
     Cm m = Tr<S>::ld(u[p]);
-    Cm s = (Tr<S>::ld(u[p - 1]) + Tr<S>::ld(u[p + 1])) + wy * (Tr<S>::ld(u[p - px]) + Tr<S>::ld(u[p + px]));
+    Cm s = (Tr<S>::ld(u[pw]) + Tr<S>::ld(u[pe])) + wy * (Tr<S>::ld(u[ps]) + Tr<S>::ld(u[pn]));
     Cm t = (s + Tr<S>::ld(b[p])) - dg * m;
     o[p] = Tr<S>::st(m + c * t);
 }
@@ -116,7 +120,7 @@ __global__ __launch_bounds__(256) void k_sweep2d(const S* __restrict__ u, S* __r
 // fetch fewer extra rows from HBM.  The z loop is branch-free (clamped plane index; the
 // stores of planes past the run are dropped by the range check of a buffer resource that
 // covers the run) so the loads of the next D planes stay in flight while a plane computes.
-template <class S, int D>
+template <class S, int D, bool NEU>
 __global__ __launch_bounds__(1024) void k_sweep3d(const S* __restrict__ u, S* __restrict__ o,
                                                   const S* __restrict__ b, int64_t px, int64_t py,
                                                   int nx, int ny, int nz, int zrun, double wy64, double wz64,
@@ -144,9 +148,12 @@ __global__ __launch_bounds__(1024) void k_sweep3d(const S* __restrict__ u, S* __
             const int k = kb + s;
             const int64_t p = (int64_t)min(k, nz) * pl + col;
             const Cm up = Q[s];
-            const Cm sm = ((Tr<S>::ld(u[p - 1]) + Tr<S>::ld(u[p + 1])) +
-                           wy * (Tr<S>::ld(u[p - px]) + Tr<S>::ld(u[p + px]))) +
-                          wz * (dn + up);
+            const int64_t pw = (NEU && j == 1) ? p : p - 1, pe = (NEU && j == nx) ? p : p + 1;
+            const int64_t ps = (NEU && i == 1) ? p : p - px, pn = (NEU && i == ny) ? p : p + px;
+            const Cm dnv = (NEU && k == 1) ? m : dn, upv = (NEU && k >= nz) ? m : up;
+            const Cm sm = ((Tr<S>::ld(u[pw]) + Tr<S>::ld(u[pe])) +
+                           wy * (Tr<S>::ld(u[ps]) + Tr<S>::ld(u[pn]))) +
+                          wz * (dnv + upv);
             const Cm t = (sm + Tr<S>::ld(b[p])) - dg * m;
             // planes k >= k1 land at or past the record count and are dropped
             tb_store(Tr<S>::st(m + c * t), rs, (int)(((int64_t)(k - k0) * pl + col) * (int64_t)sizeof(S)));
@@ -171,12 +178,19 @@ __device__ __forceinline__ double res_at(const S* u, const double* b64, int64_t 
                                          int64_t pl, int ndim, int i, int j, int k, const Geo& g,
                                          bool zi)
 {
-    const bool zl = zi && j - 1 >= 1, zr = zi && j + 1 <= g.nx;
-    const bool zs = zi && i - 1 >= 1, zn = zi && i + 1 <= g.ny;
-    double s = (ldz(u, p - 1, zl) + ldz(u, p + 1, zr)) + g.wy * (ldz(u, p - px, zs) + ldz(u, p + px, zn));
+    // Neumann: a neighbour across the boundary is the point itself (read as 0 with zi too)
+    const bool neu = g.bc == 1;
+    const bool inl = j - 1 >= 1, inr = j + 1 <= g.nx, ins = i - 1 >= 1, inn = i + 1 <= g.ny;
+    const int64_t pw = (neu && !inl) ? p : p - 1, pe = (neu && !inr) ? p : p + 1;
+    const int64_t ps = (neu && !ins) ? p : p - px, pn = (neu && !inn) ? p : p + px;
+    const bool zl = zi && (inl || neu), zr = zi && (inr || neu);
+    const bool zs = zi && (ins || neu), zn = zi && (inn || neu);
+    double s = (ldz(u, pw, zl) + ldz(u, pe, zr)) + g.wy * (ldz(u, ps, zs) + ldz(u, pn, zn));
     if (ndim == 3) {
-        const bool zd = zi && k - 1 >= 1, zu = zi && k + 1 <= g.nz;
-        s = s + g.wz * (ldz(u, p - pl, zd) + ldz(u, p + pl, zu));
+        const bool ind = k - 1 >= 1, inu = k + 1 <= g.nz;
+        const int64_t pd = (neu && !ind) ? p : p - pl, pu = (neu && !inu) ? p : p + pl;
+        const bool zd = zi && (ind || neu), zu = zi && (inu || neu);
+        s = s + g.wz * (ldz(u, pd, zd) + ldz(u, pu, zu));
     }
     return (s + b64[p]) - g.dg * ldz(u, p, zi);
 }
@@ -379,8 +393,12 @@ hipError_t launch_sweep_unfused(Fmt f, const void* in, void* out, const void* b,
 {
     if (g.ndim == 2) {
         dim3 grid((unsigned)((g.nx + 63) / 64), (unsigned)((g.ny + 3) / 4));
-        SRJ_DISPATCH(f, hipLaunchKernelGGL(k_sweep2d<S>, grid, dim3(64, 4), 0, s, (const S*)in, (S*)out,
-                                           (const S*)b, g.px, (int)g.nx, (int)g.ny, g.wy, g.dg, c));
+        if (g.bc == 1)
+            SRJ_DISPATCH(f, hipLaunchKernelGGL((k_sweep2d<S, true>), grid, dim3(64, 4), 0, s, (const S*)in, (S*)out,
+                                               (const S*)b, g.px, (int)g.nx, (int)g.ny, g.wy, g.dg, c))
+        else
+            SRJ_DISPATCH(f, hipLaunchKernelGGL((k_sweep2d<S, false>), grid, dim3(64, 4), 0, s, (const S*)in,
+                                               (S*)out, (const S*)b, g.px, (int)g.nx, (int)g.ny, g.wy, g.dg, c))
     } else {
         // 64 x 4 threads per block, runs of 32 z planes, 2 planes loaded ahead
         constexpr int kZrun = 32, kBy = 4;
@@ -389,9 +407,14 @@ hipError_t launch_sweep_unfused(Fmt f, const void* in, void* out, const void* b,
         const int zrun = (int)std::max<int64_t>(1, std::min<int64_t>(kZrun, zmax));
         dim3 grid((unsigned)((g.nx + 63) / 64), (unsigned)((g.ny + kBy - 1) / kBy), (unsigned)((g.nz + zrun - 1) / zrun));
         dim3 blk(64, kBy);
-        SRJ_DISPATCH(f, hipLaunchKernelGGL((k_sweep3d<S, 2>), grid, blk, 0, s, (const S*)in, (S*)out, (const S*)b,
-                                           g.px, g.py, (int)g.nx, (int)g.ny, (int)g.nz, zrun, g.wy, g.wz, g.dg,
-                                           c));
+        if (g.bc == 1)
+            SRJ_DISPATCH(f, hipLaunchKernelGGL((k_sweep3d<S, 2, true>), grid, blk, 0, s, (const S*)in, (S*)out,
+                                               (const S*)b, g.px, g.py, (int)g.nx, (int)g.ny, (int)g.nz, zrun, g.wy,
+                                               g.wz, g.dg, c))
+        else
+            SRJ_DISPATCH(f, hipLaunchKernelGGL((k_sweep3d<S, 2, false>), grid, blk, 0, s, (const S*)in, (S*)out,
+                                               (const S*)b, g.px, g.py, (int)g.nx, (int)g.ny, (int)g.nz, zrun, g.wy,
+                                               g.wz, g.dg, c))
     }
     return hipGetLastError();
 }

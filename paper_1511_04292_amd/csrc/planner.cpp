@@ -57,6 +57,29 @@ double grid_kappa_min(int ndim, const int64_t* n, const double* wt) { return gri
 
 double grid_kappa_max(int ndim, const int64_t* n, const double* wt) { return grid_kappa(ndim, n, wt, false); }
 
+double neumann_kappa_min(int ndim, const int64_t* n, const double* wt)
+{
+    double m = 0.0;
+    for (int i = 0; i < ndim; ++i) {
+        const double v = std::sin(kPi / (2.0 * (double)n[i]));
+        const double axis = (!wt || i == 0) ? 1.0 : wt[i - 1];
+        const double t = axis * (v * v);
+        if (i == 0 || t < m) m = t;
+    }
+    return wt ? (4.0 * m) / wt[2] : (2.0 / (double)ndim) * m;
+}
+
+double neumann_kappa_max(int ndim, const int64_t* n, const double* wt)
+{
+    double s = 0.0;
+    for (int i = 0; i < ndim; ++i) {
+        const double v = std::cos(kPi / (2.0 * (double)n[i]));
+        const double axis = (!wt || i == 0) ? 1.0 : wt[i - 1];
+        s = s + (wt ? axis * (v * v) : v * v);
+    }
+    return wt ? (4.0 * s) / wt[2] : (2.0 / (double)ndim) * s;
+}
+
 // ----------------------------------------------------------------- the system
 
 namespace {

@@ -22,6 +22,12 @@ struct Optimum {
 double grid_kappa_min(int ndim, const int64_t* n, const double* wt = nullptr);
 // Largest Jacobi symbol of the Dirichlet grid: the same with cos^2.
 double grid_kappa_max(int ndim, const int64_t* n, const double* wt = nullptr);
+// The same for a cell-centred grid of n_i cells with homogeneous Neumann boundaries (Sec. 3.1,
+// Eq. boundaries1D3D): symbols 4 sum_i a_i sin^2(k_i pi / (2 n_i)) / dg, k_i = 0..n_i - 1; the
+// smallest nonzero one is 4 min_i a_i sin^2(pi / (2 n_i)) / dg ((2/d) sin^2(pi / 2N) with
+// equal spacings), the largest 4 sum_i a_i cos^2(pi / (2 n_i)) / dg.
+double neumann_kappa_min(int ndim, const int64_t* n, const double* wt = nullptr);
+double neumann_kappa_max(int ndim, const int64_t* n, const double* wt = nullptr);
 
 // Minimax-optimal P-level scheme on [km, kM]; false (with a message) if the solve fails.
 bool optimal_schedule(int P, double km, double kM, Optimum* out, std::string* err);

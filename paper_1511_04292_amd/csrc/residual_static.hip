@@ -155,6 +155,7 @@ extern "C" srj_status srj_residual_static(const srj_grid* grid, const double* u,
 {
     if (!grid || !u || !f || !norms) return report(SRJ_EINVAL, "null argument");
     if (grid->ndim != 2 && grid->ndim != 3) return report(SRJ_EINVAL, "ndim must be 2 or 3");
+    if (grid->bc != 0) return report(SRJ_EINVAL, "Dirichlet grids only");
     for (int i = 0; i < grid->ndim; ++i) {
         if (grid->n[i] < 1 || grid->n[i] > (1 << 20)) return report(SRJ_EINVAL, "n must be in [1, 2^20]");
         if (!(grid->h[i] > 0) || !std::isfinite(grid->h[i])) return report(SRJ_EINVAL, "every h[i] must be positive");

@@ -21,9 +21,10 @@ struct SchedOut {
     double kappa_min = 0, kappa_max = 0, rho = 0, gamma_q = 0, pre = 0, suf = 0;
 };
 
-// ndim, n: the grid; wt: its axis weights {wy, wz, dg} (null: equal spacings).  With
-// peaks = false the prefix / suffix peaks are not computed.
+// ndim, n: the grid; wt: its axis weights {wy, wz, dg} (null: equal spacings); neumann: a
+// cell-centred grid with homogeneous Neumann boundaries.  With peaks = false the prefix /
+// suffix peaks are not computed.
 srj_status make_schedule(int ndim, const int64_t* n, const double* wt, const srj_schedule* sc, bool peaks,
-                         SchedOut* out, std::string* err);
+                         SchedOut* out, std::string* err, bool neumann = false);
 
 }  // namespace srj

@@ -27,7 +27,7 @@ class SrjError(RuntimeError):
 
 class _Grid(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_int32), ("n", ctypes.c_int64 * 3), ("h", ctypes.c_double * 3),
-                ("dtype", ctypes.c_int32)]
+                ("dtype", ctypes.c_int32), ("bc", ctypes.c_int32)]
 
 
 class _Schedule(ctypes.Structure):
@@ -38,8 +38,13 @@ class _Schedule(ctypes.Structure):
                 ("M", ctypes.c_int64)]
 
 
-def _fill_grid(g, n, h, dtype):
-    """n = (n_x, n_y[, n_z]); h one spacing for every axis or one per axis (h_x, h_y[, h_z])."""
+BCS = {"dirichlet": 0, "neumann": 1}
+
+
+def _fill_grid(g, n, h, dtype, bc="dirichlet"):
+    """n = (n_x, n_y[, n_z]); h one spacing for every axis or one per axis (h_x, h_y[, h_z]);
+    bc 'dirichlet' or 'neumann'."""
+    g.bc = BCS[bc] if isinstance(bc, str) else int(bc)
     g.ndim = len(n)
     for i, v in enumerate(n):
         g.n[i] = int(v)
@@ -169,7 +174,7 @@ class Plan:
 
 
 def srj_plan(n, h, P=None, omega=None, q=None, kappa_min=0.0, ordering=0, sequence=None,
-             dtype="f64", stream=None, n_eff=0.0, q_rounding=0):
+             dtype="f64", stream=None, n_eff=0.0, q_rounding=0, bc="dirichlet"):
     """Create a plan for a grid of interior sizes n = (n_x, n_y[, n_z]) and spacing h (one
     number, or one per axis).
 
@@ -179,7 +184,7 @@ def srj_plan(n, h, P=None, omega=None, q=None, kappa_min=0.0, ordering=0, sequen
     """
     L = lib()
     g = _Grid()
-    _fill_grid(g, n, h, dtype)
+    _fill_grid(g, n, h, dtype, bc)
     s = _Schedule()
     keep = []
     if omega is not None:
