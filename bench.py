@@ -369,6 +369,7 @@ def main():
         other = {}
         for name, fn in (("small_2d_64", bench_small_2d), ("case_study_585x280", bench_case_study),
                          ("neumann_calibration_256", bench_neumann_calibration),
+                         ("grad_shafranov_300", bench_grad_shafranov),
                          ("smooth3d_512", bench_3d), ("batch_1024", bench_batch),
                          ("adjoint_2048", bench_adjoint), ("huge_2d_32768", bench_huge_2d)):
             print(f"bench: {name} ...", file=sys.stderr, flush=True)
@@ -582,6 +583,37 @@ def bench_neumann_calibration(torch, srj, workloads, n=256, tol=1e-10):
         del plan
     for P in (2, 3, 4, 5):
         out[f"srj_P{P}"]["measured_acceleration"] = round(out["jacobi"]["sweeps"] / out[f"srj_P{P}"]["sweeps"], 3)
+    return out
+
+
+def bench_grad_shafranov(torch, srj, workloads, n=298, tol=1e-12):
+    """Sec. 5.3: the linear Grad-Shafranov equation on the paper's 300 x 300 points, test A
+    (dipole boundary data) and test B (masked region), for several C, solved with the P = 14,
+    N = 300 scheme to relres 1e-12 (the Jacobi-scaled residual, cycle ends), binary64, one
+    sweep per launch.  The paper's Table 4 iteration counts are quoted as context (its own
+    residual and stopping rule)."""
+    import numpy as np
+
+    table4 = {("A", 0.0): 5350, ("A", 0.2): 4660, ("A", 0.34): 49080, ("B", 0.0): 3450, ("B", 1.0): 3550,
+              ("B", 1.47): 11620}
+    out = {"workload": "Sec. 5.3 Grad-Shafranov, 300 x 300 points, P = 14 / N = 300 scheme, relres 1e-12"}
+    for (test, C), printed in table4.items():
+        wl = workloads.grad_shafranov(n, C, test)
+        coef = torch.from_numpy(wl["coef"]).to("cuda:0")
+        mask = torch.from_numpy(wl["mask"]).to("cuda:0") if wl["mask"] is not None else None
+        plan = srj.srj_plan_operator(wl["n"], coef, mask, P=14, n_eff=300)
+        u = torch.from_numpy(wl["u0"]).to("cuda:0")
+        f = torch.from_numpy(wl["f"]).to("cuda:0")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = srj.srj_solve(plan, u, f, tol, 10 ** 6)
+        torch.cuda.synchronize()
+        r = {"sweeps": int(info["sweeps"]), "seconds": round(time.perf_counter() - t0, 4), "relres": info["relres"],
+             "status": info["status"], "paper_iterations": printed}
+        if "u_exact" in wl:
+            r["max_err_vs_dipole"] = float(np.max(np.abs(u.cpu().numpy() - wl["u_exact"])))
+        out[f"test{test}_C{C}"] = r
+        del plan, coef, mask
     return out
 
 

@@ -172,6 +172,25 @@ srj_status srj_sweeps(srj_plan_t plan, double* u, const double* f, int64_t k0, i
 srj_status srj_residual(srj_plan_t plan, const double* u, const double* f, double* r_out,
                         double norms[4]);
 
+/* A plan for a variable-coefficient operator given point by point (Sec. 5.3's Grad-Shafranov
+ * operator with its C^2 Psi term and masked region, Sec. 5.2's variable-coefficient stencils):
+ *     (A u)_P = a_P u_P - sum over the 2d neighbours of a_nb u_nb = f_P
+ * at every interior point whose mask is 0; the ring and masked points hold fixed values.
+ * coef: DEVICE, 2d + 1 consecutive arrays of the full-grid ABI layout, a_P, a_W, a_E, a_S,
+ * a_N (, a_D, a_U) -- W/E along x, S/N along y, D/U along z -- read once here (a_P nonzero at
+ * the free points).  mask: DEVICE uint8 array of the same layout (nonzero = fixed point), or
+ * NULL.  The operator is Jacobi-scaled once, w_nb = a_nb / a_P and b = f / a_P (one IEEE
+ * division each), and one step with weight w is
+ *     s = (w_W W + w_E E) + (w_S S + w_N N) [+ (w_D D + w_U U)];  t = (s + b) - u;  u' = u + w t,
+ * evaluated in that association; relres is the same Jacobi-scaled residual t measured against
+ * t of the state whose free points are zero.  grid->h is ignored (the coefficients carry the
+ * scaling), grid->dtype must be SRJ_F64 and grid->bc 0.  The schedule must be explicit or give
+ * kappa_min or n_eff (the operator's spectrum is not known to the library).  Such plans run
+ * one sweep per launch and serve srj_solve, srj_sweeps and srj_residual (norms of t); not
+ * srj_solve_ir or srj_adjoint. */
+srj_status srj_plan_operator(const srj_grid* grid, const srj_schedule* schedule, const double* coef,
+                             const uint8_t* mask, void* stream, srj_plan_t* out);
+
 /* For callers that cannot allocate device memory (code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc): the residual norms of srj_residual for a
  * grid described by grid (ndim, n, h; dtype ignored), computed from the caller's DEVICE

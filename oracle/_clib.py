@@ -50,6 +50,9 @@ def lib():
         "or_sweep2d_neu": [i64, i64, vp, vp, vp, dbl, vp],
         "or_sweep3d_neu": [i64, i64, i64, vp, vp, vp, dbl, vp],
         "or_residual_neu": [i64, i64, i64, ctypes.c_int, vp, vp, vp, vp, vp, vp, vp],
+        "or_op_scale": [i64, ctypes.c_int, vp, vp, vp, vp],
+        "or_op_sweep": [i64, i64, i64, ctypes.c_int, vp, vp, vp, vp, dbl, vp],
+        "or_op_residual": [i64, i64, i64, ctypes.c_int, vp, vp, vp, vp, ctypes.c_int, vp, vp, vp, vp, vp],
         "or_f32_to_bf16": [i64, vp, vp],
         "or_bf16_to_f32": [i64, vp, vp],
     }

@@ -407,3 +407,99 @@ void or_residual_neu(int64_t nx, int64_t ny, int64_t nz, int ndim, const double*
     out[0] = tot.s;
     out[1] = m;
 }
+
+/* ------------------------------------- variable-coefficient operators with a mask (Sec. 5.3) */
+/* The operator (A u)_P = a_P u_P - sum_nb a_nb u_nb, given per point.  Jacobi-scaled: every
+ * neighbour weight is w_nb = a_nb / a_P and the source is bs = f / a_P (one IEEE division
+ * each), so one step with weight omega is
+ *     s = (w_W W + w_E E) + (w_S S + w_N N)   [ + (w_D D + w_U U) in 3D ]
+ *     t = (s + bs) - u ;   u' = u + omega * t
+ * at every interior point whose mask is 0; masked points (mask != 0) and the ring keep their
+ * values (Dirichlet data on an arbitrarily shaped boundary).  wts holds the 2d neighbour
+ * weight arrays one after the other (W, E, S, N[, D, U]), each of the full-grid size. */
+
+void or_op_scale(int64_t n, int nnb, const double* coef, double* wts, const double* f, double* bs)
+{
+    /* coef: a_P then the nnb neighbour arrays; f may be NULL */
+    for (int64_t i = 0; i < n; ++i) {
+        const double ap = coef[i];
+        for (int k = 0; k < nnb; ++k) wts[(size_t)k * (size_t)n + (size_t)i] = coef[(size_t)(k + 1) * (size_t)n + (size_t)i] / ap;
+        if (f) bs[i] = f[i] / ap;
+    }
+}
+
+static inline double op_t(int ndim, int64_t nx, int64_t ny, int64_t nz, size_t p, const double* u, const double* wts,
+                          const double* bs)
+{
+    const size_t n = (size_t)(nx + 2) * (size_t)(ny + 2) * (size_t)(ndim == 3 ? nz + 2 : 1);
+    const size_t px = (size_t)(nx + 2), pl = px * (size_t)(ny + 2);
+    double s = (wts[p] * u[p - 1] + wts[n + p] * u[p + 1]) + (wts[2 * n + p] * u[p - px] + wts[3 * n + p] * u[p + px]);
+    if (ndim == 3) s = s + (wts[4 * n + p] * u[p - pl] + wts[5 * n + p] * u[p + pl]);
+    return (s + bs[p]) - u[p];
+}
+
+void or_op_sweep(int64_t nx, int64_t ny, int64_t nz, int ndim, const double* u, const double* wts, const double* bs,
+                 const uint8_t* mask, double omega, double* out)
+{
+    const int64_t planes = ndim == 3 ? nz : 1;
+#pragma omp parallel for schedule(static)
+    for (int64_t line = 0; line < planes * ny; ++line) {
+        const int64_t k = ndim == 3 ? line / ny + 1 : 0, i = line % ny + 1;
+        for (int64_t j = 1; j <= nx; ++j) {
+            const size_t p = ndim == 3 ? I3(k, i, j) : I2(i, j);
+            if (mask && mask[p]) {
+                out[p] = u[p];
+                continue;
+            }
+            out[p] = u[p] + omega * op_t(ndim, nx, ny, nz, p, u, wts, bs);
+        }
+    }
+}
+
+/* Jacobi-scaled residual t (0 at masked points and on the ring) into r (may be NULL), with
+ * out[0] = sum t^2 (compensated per line) and out[1] = max |t|.  zero_free: read u as 0 at the
+ * interior points the sweep updates (giving the scaled source plus boundary terms). */
+void or_op_residual(int64_t nx, int64_t ny, int64_t nz, int ndim, const double* u, const double* wts,
+                    const double* bs, const uint8_t* mask, int zero_free, double* r, double* out, double* rowsum,
+                    double* rowmax, double* scratch)
+{
+    const int64_t planes = ndim == 3 ? nz : 1;
+    const size_t n = (size_t)(nx + 2) * (size_t)(ny + 2) * (size_t)(ndim == 3 ? nz + 2 : 1);
+    const double* v = u;
+    if (zero_free) {
+        memcpy(scratch, u, sizeof(double) * n);
+        for (int64_t line = 0; line < planes * ny; ++line) {
+            const int64_t k = ndim == 3 ? line / ny + 1 : 0, i = line % ny + 1;
+            for (int64_t j = 1; j <= nx; ++j) {
+                const size_t p = ndim == 3 ? I3(k, i, j) : I2(i, j);
+                if (!(mask && mask[p])) scratch[p] = 0.0;
+            }
+        }
+        v = scratch;
+    }
+    if (r) memset(r, 0, sizeof(double) * n);
+#pragma omp parallel for schedule(static)
+    for (int64_t line = 0; line < planes * ny; ++line) {
+        const int64_t k = ndim == 3 ? line / ny + 1 : 0, i = line % ny + 1;
+        kahan_t acc = {0.0, 0.0};
+        double m = 0.0;
+        for (int64_t j = 1; j <= nx; ++j) {
+            const size_t p = ndim == 3 ? I3(k, i, j) : I2(i, j);
+            const double t = (mask && mask[p]) ? 0.0 : op_t(ndim, nx, ny, nz, p, v, wts, bs);
+            if (r) r[p] = t;
+            kadd(&acc, t * t);
+            const double a = fabs(t);
+            if (a > m || a != a) m = a;
+        }
+        rowsum[line] = acc.s;
+        rowmax[line] = m;
+    }
+    kahan_t tot = {0.0, 0.0};
+    double m = 0.0;
+    for (int64_t line = 0; line < planes * ny; ++line) {
+        kadd(&tot, rowsum[line]);
+        if (rowmax[line] > m || rowmax[line] != rowmax[line]) m = rowmax[line];
+    }
+    out[0] = tot.s;
+    out[1] = m;
+}

@@ -50,13 +50,14 @@ namespace srj {
 srj_status report(srj_status s, const std::string& msg) { return fail(s, msg); }
 
 srj_status make_schedule(int d, const int64_t* n, const double* wt, const srj_schedule* sc, bool peaks,
-                         SchedOut* out, std::string* err, bool neumann)
+                         SchedOut* out, std::string* err, SpecKind kind)
 {
+    const bool neumann = kind == SPEC_NEUMANN;
     auto bad = [&](srj_status st, const std::string& m) {
         *err = m;
         return st;
     };
-    const double kmax_grid = neumann ? neumann_kappa_max(d, n, wt) : grid_kappa_max(d, n, wt);
+    const double kmax_grid = kind == SPEC_OPERATOR ? 2.0 : neumann ? neumann_kappa_max(d, n, wt) : grid_kappa_max(d, n, wt);
     if (sc->kappa_min > 0 && sc->n_eff > 0) return bad(SRJ_EINVAL, "give kappa_min or n_eff, not both");
     if (sc->kappa_min < 0 || sc->n_eff < 0 || !std::isfinite(sc->kappa_min) || !std::isfinite(sc->n_eff))
         return bad(SRJ_EINVAL, "kappa_min and n_eff must be finite and >= 0");
@@ -67,6 +68,8 @@ srj_status make_schedule(int d, const int64_t* n, const double* wt, const srj_sc
         // the Neumann table row for resolution N (Eq. boundaries): sin^2(pi / (2N))
         const double v = std::sin(3.14159265358979323846 / (2.0 * sc->n_eff));
         out->kappa_min = v * v;
+    } else if (kind == SPEC_OPERATOR) {
+        return bad(SRJ_EINVAL, "an operator's schedule needs kappa_min, n_eff or explicit weights");
     } else {
         out->kappa_min = neumann ? neumann_kappa_min(d, n, wt) : grid_kappa_min(d, n, wt);
     }
@@ -158,6 +161,10 @@ struct srj_plan_s {
     DField A, B, blo;  // iterate pair, b (or the refinement's inner right-hand side) in the sweep format
     DField b64f, x64;  // binary64 b, and the binary64 iterate of refinement / residual evaluation
     double* b64 = nullptr;  // b64f.origin
+    // variable-coefficient operator plans: scaled weights, a_P and the mask (padded fields)
+    DField opw[6], opap;
+    void* opmask_alloc = nullptr;
+    uint8_t* opmask = nullptr;
     double* partials = nullptr;
     double* dres = nullptr;   // device {sum, max}
     double* hres = nullptr;   // pinned host copy
@@ -192,7 +199,8 @@ srj_status build_schedule(srj_plan_t p, const srj_schedule* sc)
     SchedOut o;
     std::string err;
     const double wt[3] = {p->geo.wy, p->geo.wz, p->geo.dg};
-    srj_status st = make_schedule(p->grid.ndim, p->grid.n, p->iso ? nullptr : wt, sc, true, &o, &err, p->geo.bc == 1);
+    const SpecKind kind = p->geo.op ? SPEC_OPERATOR : (p->geo.bc == 1 ? SPEC_NEUMANN : SPEC_DIRICHLET);
+    srj_status st = make_schedule(p->grid.ndim, p->grid.n, p->iso ? nullptr : wt, sc, true, &o, &err, kind);
     if (st != SRJ_OK) return fail(st, err);
     p->P = o.P;
     std::memcpy(p->omega, o.omega, sizeof(o.omega));
@@ -219,6 +227,9 @@ void destroy(srj_plan_t p)
     free_field(&p->blo);
     free_field(&p->b64f);
     free_field(&p->x64);
+    for (auto& f : p->opw) free_field(&f);
+    free_field(&p->opap);
+    if (p->opmask_alloc) (void)hipFree(p->opmask_alloc);
     if (p->partials) (void)hipFree(p->partials);
     if (p->dres) (void)hipFree(p->dres);
     if (p->hres) (void)hipHostFree(p->hres);
@@ -265,6 +276,19 @@ srj_status run_sweeps(srj_plan_t p, DField** cur, DField** nxt, const void* b, i
         std::swap(*cur, *nxt);
     }
     return SRJ_OK;
+}
+
+// b from the user's f: h_x^2 f (Poisson plans) or f / a_P (operator plans), in the sweep
+// format (blo) and in binary64 (b64)
+hipError_t load_rhs(srj_plan_t p, const double* f)
+{
+    if (p->geo.op) {
+        hipError_t e = launch_op_rhs(f, (const double*)p->opap.origin, p->b64, p->geo, p->stream);
+        if (e != hipSuccess) return e;
+        return hipMemcpyAsync(p->blo.origin, p->b64, sizeof(double) * p->field_elems - sizeof(double) * (kAlignBytes / 8 - 1),
+                              hipMemcpyDeviceToDevice, p->stream);
+    }
+    return launch_rhs(p->fmt, f, p->hh, p->blo.origin, p->b64, p->geo, p->stream);
 }
 
 void fill_info(srj_solve_info* info, int64_t sweeps, int64_t cycles, double relres, double sec, srj_status st)
@@ -357,7 +381,14 @@ const char* srj_status_string(srj_status s)
 
 const char* srj_last_error(void) { return g_err.c_str(); }
 
-srj_status srj_plan(const srj_grid* grid, const srj_schedule* schedule, void* stream, srj_plan_t* out)
+}  // extern "C"
+
+namespace {
+
+// A plan for the Poisson operator (coef == null) or for a variable-coefficient operator
+// given by the user's coefficient arrays and mask (srj_plan_operator).
+srj_status create_plan(const srj_grid* grid, const srj_schedule* schedule, void* stream, const double* coef,
+                       const uint8_t* mask, srj_plan_t* out)
 {
     if (!grid || !schedule || !out) return fail(SRJ_EINVAL, "null argument");
     *out = nullptr;
@@ -372,6 +403,12 @@ srj_status srj_plan(const srj_grid* grid, const srj_schedule* schedule, void* st
     if (grid->bc == 1)
         for (int i = 0; i < grid->ndim; ++i)
             if (grid->n[i] < 2) return fail(SRJ_EINVAL, "a Neumann grid needs at least 2 cells per axis");
+    if (coef) {
+        if (grid->dtype != 0 || grid->bc != 0)
+            return fail(SRJ_EINVAL, "operator plans are binary64 with fixed (Dirichlet) boundary values");
+        if (!schedule->omega && !(schedule->kappa_min > 0) && !(schedule->n_eff > 0))
+            return fail(SRJ_EINVAL, "operator plans need explicit weights, kappa_min or n_eff");
+    }
     srj_plan_t p = new (std::nothrow) srj_plan_s();
     if (!p) return fail(SRJ_ENOMEM, "host allocation failed");
     p->grid = *grid;
@@ -389,6 +426,14 @@ srj_status srj_plan(const srj_grid* grid, const srj_schedule* schedule, void* st
     geo_set_weights(g, p->grid.h, &p->iso);
     g.bc = grid->bc;
     p->hh = p->grid.h[0] * p->grid.h[0];
+    if (coef) {
+        // the operator carries its own scaling: unit weights, b = f / a_P, c_k = w_k
+        g.op = 1;
+        g.wy = g.wz = 1.0;
+        g.dg = 1.0;
+        p->iso = false;
+        p->hh = 1.0;
+    }
     srj_status st = build_schedule(p, schedule);
     if (st != SRJ_OK) {
         destroy(p);
@@ -412,6 +457,34 @@ srj_status srj_plan(const srj_grid* grid, const srj_schedule* schedule, void* st
         return st;
     }
     p->b64 = (double*)p->b64f.origin;
+    if (coef) {
+        const int nnb = 2 * g.ndim;
+        double* wp[6] = {nullptr};
+        for (int m = 0; m < nnb; ++m) {
+            if ((st = alloc_field(p, FMT_F64, &p->opw[m])) != SRJ_OK) {
+                destroy(p);
+                return st;
+            }
+            wp[m] = (double*)p->opw[m].origin;
+            g.w[m] = wp[m];
+        }
+        if ((st = alloc_field(p, FMT_F64, &p->opap)) != SRJ_OK) {
+            destroy(p);
+            return st;
+        }
+        if (mask) {
+            if (hipMalloc(&p->opmask_alloc, p->field_elems) != hipSuccess) {
+                destroy(p);
+                return fail(SRJ_ENOMEM, "allocation of the mask field failed");
+            }
+            p->opmask = (uint8_t*)p->opmask_alloc + (kAlignBytes - 1);
+        }
+        g.mask = p->opmask;
+        if (launch_op_setup(coef, mask, wp, (double*)p->opap.origin, p->opmask, g, p->stream) != hipSuccess) {
+            destroy(p);
+            return fail(SRJ_EHIP, "operator setup failed");
+        }
+    }
     const int nb = residual_blocks(g);
     if (hipMalloc(&p->partials, sizeof(double) * 2 * (size_t)nb) != hipSuccess ||
         hipMalloc(&p->dres, sizeof(double) * 4) != hipSuccess ||
@@ -434,6 +507,22 @@ srj_status srj_plan(const srj_grid* grid, const srj_schedule* schedule, void* st
                                       : (fused3d_fits(g, p->fmt) ? (p->fmt == FMT_F64 ? kMaxFuse3d - 1 : kMaxFuse3d) : 0);
     *out = p;
     return SRJ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+srj_status srj_plan(const srj_grid* grid, const srj_schedule* schedule, void* stream, srj_plan_t* out)
+{
+    return create_plan(grid, schedule, stream, nullptr, nullptr, out);
+}
+
+srj_status srj_plan_operator(const srj_grid* grid, const srj_schedule* schedule, const double* coef,
+                             const uint8_t* mask, void* stream, srj_plan_t* out)
+{
+    if (!coef) return fail(SRJ_EINVAL, "null coefficients");
+    return create_plan(grid, schedule, stream, coef, mask, out);
 }
 
 void srj_plan_destroy(srj_plan_t plan)
@@ -477,7 +566,7 @@ srj_status srj_plan_set_fusion(srj_plan_t p, int32_t fused, int32_t seg_rows)
     if (fused < 0 || fused > kMaxFuse) return fail(SRJ_EINVAL, "fusion depth must be in [0, 10]");
     if (p->geo.ndim == 3 && fused > kMaxFuse3d) return fail(SRJ_EINVAL, "3D fusion depth must be in [0, 5]");
     if (fused > 0 && !p->iso) return fail(SRJ_EINVAL, "fused sweeps need equal spacings on every axis");
-    if (fused > 0 && p->geo.bc != 0) return fail(SRJ_EINVAL, "fused sweeps need Dirichlet boundaries");
+    if (fused > 0 && (p->geo.bc != 0 || p->geo.op)) return fail(SRJ_EINVAL, "fused sweeps need the Dirichlet Poisson operator");
     if (p->geo.ndim == 3 && fused > 0 && !fused3d_fits(p->geo, p->fmt))
         return fail(SRJ_EINVAL, "z planes too large for the fused 3D kernel (1 GiB per plane at most)");
     if (seg_rows < 0 || seg_rows > (1 << 20)) return fail(SRJ_EINVAL, "segment rows must be in [0, 2^20]");
@@ -489,11 +578,10 @@ srj_status srj_plan_set_fusion(srj_plan_t p, int32_t fused, int32_t seg_rows)
 srj_status srj_residual(srj_plan_t p, const double* u, const double* f, double* r_out, double norms[4])
 {
     if (!p || !u || !f || !norms) return fail(SRJ_EINVAL, "null argument");
-    const double hh = p->hh;
     srj_status st;
     // u goes to the plan's binary64 iterate field; b to b64 (and blo, as a solve would)
     HIPCHK(launch_copy_in(FMT_F64, u, p->x64.origin, p->geo, p->stream));
-    HIPCHK(launch_rhs(p->fmt, f, hh, p->blo.origin, p->b64, p->geo, p->stream));
+    HIPCHK(load_rhs(p, f));
     double s0, m0, s1, m1;
     if ((st = residual_now(p, p->x64.origin, FMT_F64, 1, &s0, &m0)) != SRJ_OK) return st;
     if (r_out) HIPCHK(launch_residual_out((const double*)p->x64.origin, p->b64, r_out, p->geo, p->stream));
@@ -509,10 +597,9 @@ srj_status srj_sweeps(srj_plan_t p, double* u, const double* f, int64_t k0, int6
 {
     if (!p || !u || !f) return fail(SRJ_EINVAL, "null argument");
     if (k0 < 0 || n < 0) return fail(SRJ_EINVAL, "k0 and nsweeps must be >= 0");
-    const double hh = p->hh;
     HIPCHK(launch_copy_in(p->fmt, u, p->A.origin, p->geo, p->stream));
     HIPCHK(launch_copy_in(p->fmt, u, p->B.origin, p->geo, p->stream));
-    HIPCHK(launch_rhs(p->fmt, f, hh, p->blo.origin, p->b64, p->geo, p->stream));
+    HIPCHK(load_rhs(p, f));
     DField *cur = &p->A, *nxt = &p->B;
     int64_t launches = 0;
     HIPCHK(hipEventRecord(p->ev0, p->stream));
@@ -614,11 +701,10 @@ srj_status srj_solve(srj_plan_t p, double* u, const double* f, double tol, int64
     fill_info(info, 0, 0, NAN, 0, SRJ_EINVAL);
     if (!p || !u || !f) return fail(SRJ_EINVAL, "null argument");
     if (!(tol >= 0) || max_sweeps < 0) return fail(SRJ_EINVAL, "bad tolerance or sweep budget");
-    const double hh = p->hh;
     HIPCHK(hipEventRecord(p->ev0, p->stream));
     HIPCHK(launch_copy_in(p->fmt, u, p->A.origin, p->geo, p->stream));
     HIPCHK(launch_copy_in(p->fmt, u, p->B.origin, p->geo, p->stream));
-    HIPCHK(launch_rhs(p->fmt, f, hh, p->blo.origin, p->b64, p->geo, p->stream));
+    HIPCHK(load_rhs(p, f));
     DField* cur = nullptr;
     int64_t k = 0, cycles = 0;
     double rr = 0;
@@ -635,7 +721,7 @@ srj_status srj_adjoint(srj_plan_t p, const double* grad_u, double tol, int64_t m
     fill_info(info, 0, 0, NAN, 0, SRJ_EINVAL);
     if (!p || !grad_u) return fail(SRJ_EINVAL, "null argument");
     if (p->fmt != FMT_F64) return fail(SRJ_EINVAL, "the adjoint solve needs an FP64 plan");
-    if (p->geo.bc != 0) return fail(SRJ_EINVAL, "the adjoint solve needs Dirichlet boundaries");
+    if (p->geo.bc != 0 || p->geo.op) return fail(SRJ_EINVAL, "the adjoint solve needs the Dirichlet Poisson operator");
     if (!(tol >= 0) || max_sweeps < 0) return fail(SRJ_EINVAL, "bad tolerance or sweep budget");
     HIPCHK(hipEventRecord(p->ev0, p->stream));
     HIPCHK(launch_zero(p->fmt, p->A.origin, p->geo, p->stream));
@@ -660,7 +746,7 @@ srj_status srj_solve_ir(srj_plan_t p, double* u, const double* f, double tol, in
     fill_info(info, 0, 0, NAN, 0, SRJ_EINVAL);
     if (!p || !u || !f) return fail(SRJ_EINVAL, "null argument");
     if (!(tol >= 0) || inner_cycles < 1 || max_outer < 0) return fail(SRJ_EINVAL, "bad IR parameters");
-    if (p->geo.bc != 0) return fail(SRJ_EINVAL, "refinement needs Dirichlet boundaries");
+    if (p->geo.bc != 0 || p->geo.op) return fail(SRJ_EINVAL, "refinement needs the Dirichlet Poisson operator");
     const double hh = p->hh;
     srj_status st;
     // the binary64 iterate lives in the plan's x64 field, b in b64; A/B hold the correction d

@@ -25,6 +25,12 @@ struct Geo {
     // boundary: 0 Dirichlet (the ring holds the data), 1 homogeneous Neumann (cell-centred:
     // a neighbour across the boundary is the cell itself; the ring is never read)
     int bc;
+    // variable-coefficient operator (op = 1): Jacobi-scaled neighbour weights a_nb / a_P as
+    // padded fields w[0..2d) (W, E, S, N[, D, U]) and an optional mask field (nonzero: a
+    // fixed point); the step is u' = u + w_k ((s + b) - u) with s the weighted neighbour sum
+    int op;
+    const double* w[6];
+    const uint8_t* mask;
 };
 
 // Geo's operator weights for spacings h[0..ndim); iso is set when they are all equal.
@@ -85,6 +91,14 @@ hipError_t launch_update(Fmt f, double* u64, const void* d, const Geo& g, hipStr
 // be null
 hipError_t launch_adjoint_out(const double* lam, const double* grad_u, double hh, double* df, double* dg,
                               const Geo& g, hipStream_t s);
+// Variable-coefficient operator: from the user's coefficient arrays coef (2d + 1 consecutive
+// full-grid arrays a_P, a_W, a_E, a_S, a_N[, a_D, a_U]) write the scaled weights
+// w[k] = a_{k+1} / a_P and a_P itself into padded fields (interior points; 0 on the ring),
+// and the user's mask (may be null) into a padded uint8 field.
+hipError_t launch_op_setup(const double* coef, const uint8_t* mask_user, double* const* w, double* ap,
+                           uint8_t* mask, const Geo& g, hipStream_t s);
+// b = f / a_P at the free interior points (0 elsewhere), into b64 (padded, binary64)
+hipError_t launch_op_rhs(const double* user_f, const double* ap, double* b64, const Geo& g, hipStream_t s);
 // set every element of the field (ring included) to zero with a fill kernel
 hipError_t launch_zero(Fmt f, void* field, const Geo& g, hipStream_t s);
 

@@ -164,6 +164,29 @@ __global__ __launch_bounds__(1024) void k_sweep3d(const S* __restrict__ u, S* __
     }
 }
 
+// One step of a variable-coefficient operator (Jacobi-scaled weights in g.w, Sec. 5.3's
+// operators): s = (wW W + wE E) + (wS S + wN N) [+ (wD D + wU U)], t = (s + b) - u,
+// u' = u + c t at every interior point whose mask is 0; masked points keep their value.
+// One thread per interior point, binary64.
+__global__ __launch_bounds__(256) void k_op_sweep(const double* __restrict__ u, double* __restrict__ o,
+                                                  const double* __restrict__ b, Geo g, double c)
+{
+    const int j = blockIdx.x * 64 + threadIdx.x + 1;
+    const int i = blockIdx.y * 4 + threadIdx.y + 1;
+    const int k = g.ndim == 3 ? (int)blockIdx.z + 1 : 0;
+    if (j > g.nx || i > g.ny) return;
+    const int64_t pl = g.px * g.py;
+    const int64_t p = (int64_t)k * pl + (int64_t)i * g.px + j;
+    if (g.mask && g.mask[p]) {
+        o[p] = u[p];
+        return;
+    }
+    double s = (g.w[0][p] * u[p - 1] + g.w[1][p] * u[p + 1]) + (g.w[2][p] * u[p - g.px] + g.w[3][p] * u[p + g.px]);
+    if (g.ndim == 3) s = s + (g.w[4][p] * u[p - pl] + g.w[5][p] * u[p + pl]);
+    const double t = (s + b[p]) - u[p];
+    o[p] = u[p] + c * t;
+}
+
 // ------------------------------------------------------------------ residuals
 
 template <class S>
@@ -178,6 +201,19 @@ __device__ __forceinline__ double res_at(const S* u, const double* b64, int64_t 
                                          int64_t pl, int ndim, int i, int j, int k, const Geo& g,
                                          bool zi)
 {
+    if (g.op) {
+        // variable-coefficient operator: the Jacobi-scaled residual, 0 at masked points; with
+        // zi the free interior points read as 0 (masked points and the ring keep their values)
+        if (g.mask && g.mask[p]) return 0.0;
+        auto rd = [&](int64_t q, bool interior) {
+            const bool z = zi && interior && !(g.mask && g.mask[q]);
+            return z ? 0.0 : (double)Tr<S>::ld(u[q]);
+        };
+        double s = (g.w[0][p] * rd(p - 1, j - 1 >= 1) + g.w[1][p] * rd(p + 1, j + 1 <= g.nx)) +
+                   (g.w[2][p] * rd(p - px, i - 1 >= 1) + g.w[3][p] * rd(p + px, i + 1 <= g.ny));
+        if (ndim == 3) s = s + (g.w[4][p] * rd(p - pl, k - 1 >= 1) + g.w[5][p] * rd(p + pl, k + 1 <= g.nz));
+        return (s + b64[p]) - (zi ? 0.0 : (double)Tr<S>::ld(u[p]));
+    }
     // Neumann: a neighbour across the boundary is the point itself (read as 0 with zi too)
     const bool neu = g.bc == 1;
     const bool inl = j - 1 >= 1, inr = j + 1 <= g.nx, ins = i - 1 >= 1, inn = i + 1 <= g.ny;
@@ -391,6 +427,13 @@ hipError_t launch_zero(Fmt f, void* field, const Geo& g, hipStream_t s)
 hipError_t launch_sweep_unfused(Fmt f, const void* in, void* out, const void* b, const Geo& g,
                                 double c, hipStream_t s)
 {
+    if (g.op) {
+        if (f != FMT_F64) return hipErrorInvalidValue;
+        dim3 grid((unsigned)((g.nx + 63) / 64), (unsigned)((g.ny + 3) / 4), (unsigned)(g.ndim == 3 ? g.nz : 1));
+        hipLaunchKernelGGL(k_op_sweep, grid, dim3(64, 4), 0, s, (const double*)in, (double*)out, (const double*)b, g,
+                           c);
+        return hipGetLastError();
+    }
     if (g.ndim == 2) {
         dim3 grid((unsigned)((g.nx + 63) / 64), (unsigned)((g.ny + 3) / 4));
         if (g.bc == 1)
@@ -449,6 +492,59 @@ hipError_t launch_residual_out(const double* u64, const double* b64, double* r_u
 {
     int64_t n = (g.ndim == 3 ? g.nz + 2 : 1) * (g.ny + 2) * (g.nx + 2);
     hipLaunchKernelGGL(k_residual_out, grid1d(n), dim3(256), 0, s, u64, b64, r_user, g);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_op_setup(const double* __restrict__ coef, const uint8_t* __restrict__ mu,
+                                                  Geo g, double* w0, double* w1, double* w2, double* w3, double* w4,
+                                                  double* w5, double* __restrict__ ap, uint8_t* __restrict__ mask)
+{
+    const int64_t nxw = g.nx + 2, nyw = g.ny + 2, nzw = (g.ndim == 3 ? g.nz + 2 : 1);
+    const int64_t n = nxw * nyw * nzw;
+    double* w[6] = {w0, w1, w2, w3, w4, w5};
+    const int nnb = 2 * g.ndim;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = idx % nxw, t = idx / nxw, i = t % nyw, k = t / nyw;
+        const int64_t p = (k * g.py + i) * g.px + j;
+        const bool inside = j >= 1 && j <= g.nx && i >= 1 && i <= g.ny && (g.ndim != 3 || (k >= 1 && k <= g.nz));
+        const double a = coef[idx];
+        for (int m = 0; m < nnb; ++m) w[m][p] = inside ? coef[(int64_t)(m + 1) * n + idx] / a : 0.0;
+        ap[p] = inside ? a : 0.0;
+        if (mask) mask[p] = mu ? mu[idx] : 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_op_rhs(const double* __restrict__ uf, const double* __restrict__ ap,
+                                                double* __restrict__ b, Geo g)
+{
+    const int64_t planes = (g.ndim == 3 ? g.nz : 1);
+    const int64_t n = planes * g.ny * g.nx;
+    const int64_t w = g.nx + 2;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = idx % g.nx + 1, t = idx / g.nx, i = t % g.ny + 1;
+        const int64_t k = (g.ndim == 3) ? t / g.ny + 1 : 0;
+        const int64_t row = k * g.py + i, p = row * g.px + j;
+        const bool fixed = g.mask && g.mask[p];
+        b[p] = fixed ? 0.0 : uf[row * w + j] / ap[p];
+    }
+}
+
+hipError_t launch_op_setup(const double* coef, const uint8_t* mask_user, double* const* w, double* ap,
+                           uint8_t* mask, const Geo& g, hipStream_t s)
+{
+    int64_t n = (g.ndim == 3 ? g.nz + 2 : 1) * (g.ny + 2) * (g.nx + 2);
+    double* ww[6] = {w[0], w[1], w[2], w[3], g.ndim == 3 ? w[4] : w[0], g.ndim == 3 ? w[5] : w[0]};
+    hipLaunchKernelGGL(k_op_setup, grid1d(n), dim3(256), 0, s, coef, mask_user, g, ww[0], ww[1], ww[2], ww[3], ww[4],
+                       ww[5], ap, mask);
+    return hipGetLastError();
+}
+
+hipError_t launch_op_rhs(const double* user_f, const double* ap, double* b64, const Geo& g, hipStream_t s)
+{
+    int64_t n = (g.ndim == 3 ? g.nz : 1) * g.ny * g.nx;
+    hipLaunchKernelGGL(k_op_rhs, grid1d(n), dim3(256), 0, s, user_f, ap, b64, g);
     return hipGetLastError();
 }
 

@@ -21,10 +21,16 @@ struct SchedOut {
     double kappa_min = 0, kappa_max = 0, rho = 0, gamma_q = 0, pre = 0, suf = 0;
 };
 
-// ndim, n: the grid; wt: its axis weights {wy, wz, dg} (null: equal spacings); neumann: a
-// cell-centred grid with homogeneous Neumann boundaries.  With peaks = false the prefix /
-// suffix peaks are not computed.
+// The spectrum the schedule is built and checked on.
+enum SpecKind {
+    SPEC_DIRICHLET = 0,  // Poisson operator, Dirichlet ring: the grid's exact symbols
+    SPEC_NEUMANN = 1,    // Poisson operator, homogeneous Neumann (cell-centred) boundaries
+    SPEC_OPERATOR = 2,   // a user's operator: [kappa_min as requested, 2] (Eq. boundaries' kappa_M)
+};
+
+// ndim, n: the grid; wt: its axis weights {wy, wz, dg} (null: equal spacings).  With
+// peaks = false the prefix / suffix peaks are not computed.
 srj_status make_schedule(int ndim, const int64_t* n, const double* wt, const srj_schedule* sc, bool peaks,
-                         SchedOut* out, std::string* err, bool neumann = false);
+                         SchedOut* out, std::string* err, SpecKind kind = SPEC_DIRICHLET);
 
 }  // namespace srj

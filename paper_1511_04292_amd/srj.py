@@ -81,7 +81,7 @@ EXPORTS = ["srj_plan", "srj_plan_destroy", "srj_plan_describe", "srj_plan_sequen
            "srj_plan_set_fusion", "srj_solve", "srj_sweeps", "srj_residual", "srj_solve_ir",
            "srj_schedule_optimal", "srj_schedule_order", "srj_status_string", "srj_last_error",
            "srj_adjoint", "srj_batch_plan", "srj_batch_solve", "srj_batch_destroy", "srj_plan_tune",
-           "srj_batch_tune", "srj_residual_static", "srj_schedule_counts"]
+           "srj_batch_tune", "srj_residual_static", "srj_schedule_counts", "srj_plan_operator"]
 
 
 def lib():
@@ -93,6 +93,7 @@ def lib():
     L = ctypes.CDLL(SO)
     vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     L.srj_plan.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Schedule), vp, ctypes.POINTER(vp)]
+    L.srj_plan_operator.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Schedule), vp, vp, vp, ctypes.POINTER(vp)]
     L.srj_plan_destroy.argtypes = [vp]
     L.srj_plan_destroy.restype = None
     L.srj_plan_describe.argtypes = [vp, ctypes.POINTER(_Desc)]
@@ -124,7 +125,7 @@ def lib():
     for name in ["srj_plan", "srj_plan_describe", "srj_plan_sequence", "srj_plan_set_fusion", "srj_solve",
                  "srj_sweeps", "srj_residual", "srj_solve_ir", "srj_schedule_optimal", "srj_schedule_order",
                  "srj_adjoint", "srj_batch_plan", "srj_batch_solve", "srj_plan_tune", "srj_batch_tune",
-                 "srj_residual_static", "srj_schedule_counts"]:
+                 "srj_residual_static", "srj_schedule_counts", "srj_plan_operator"]:
         getattr(L, name).restype = i32
     _lib = L
     return L
@@ -173,20 +174,9 @@ class Plan:
             self.handle = None
 
 
-def srj_plan(n, h, P=None, omega=None, q=None, kappa_min=0.0, ordering=0, sequence=None,
-             dtype="f64", stream=None, n_eff=0.0, q_rounding=0, bc="dirichlet"):
-    """Create a plan for a grid of interior sizes n = (n_x, n_y[, n_z]) and spacing h (one
-    number, or one per axis).
-
-    Either P (optimised schedule) or omega/q (explicit) is given; ordering 0 balanced,
-    1 even spread, 2 explicit sequence; n_eff > 0 optimises for the Neumann table row of
-    resolution n_eff; q_rounding 0 floor, 1 nearest, 2 ceiling, 3 best per level.
-    """
-    L = lib()
-    g = _Grid()
-    _fill_grid(g, n, h, dtype, bc)
-    s = _Schedule()
-    keep = []
+def _fill_schedule(s, P, omega, q, kappa_min, ordering, sequence, n_eff, q_rounding, keep):
+    """Fill an srj_schedule; arrays it points to are appended to keep (the caller holds them
+    until the call returns)."""
     if omega is not None:
         w = np.ascontiguousarray(omega, dtype=np.float64)
         qq = np.ascontiguousarray(q, dtype=np.int64)
@@ -206,9 +196,56 @@ def srj_plan(n, h, P=None, omega=None, q=None, kappa_min=0.0, ordering=0, sequen
         s.sequence = sq.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
         s.M = len(sq)
         s.ordering = 2
+
+
+def srj_plan(n, h, P=None, omega=None, q=None, kappa_min=0.0, ordering=0, sequence=None,
+             dtype="f64", stream=None, n_eff=0.0, q_rounding=0, bc="dirichlet"):
+    """Create a plan for a grid of interior sizes n = (n_x, n_y[, n_z]) and spacing h (one
+    number, or one per axis).
+
+    Either P (optimised schedule) or omega/q (explicit) is given; ordering 0 balanced,
+    1 even spread, 2 explicit sequence; n_eff > 0 optimises for the Neumann table row of
+    resolution n_eff; q_rounding 0 floor, 1 nearest, 2 ceiling, 3 best per level.
+    """
+    L = lib()
+    g = _Grid()
+    _fill_grid(g, n, h, dtype, bc)
+    s = _Schedule()
+    keep = []
+    _fill_schedule(s, P, omega, q, kappa_min, ordering, sequence, n_eff, q_rounding, keep)
     out = ctypes.c_void_p()
     st = stream if stream is not None else _stream_handle()
     _check(L.srj_plan(ctypes.byref(g), ctypes.byref(s), st, ctypes.byref(out)))
+    return Plan(out, n, len(n))
+
+
+def srj_plan_operator(n, coef, mask=None, P=None, omega=None, q=None, kappa_min=0.0, ordering=0,
+                      sequence=None, stream=None, n_eff=0.0, q_rounding=0):
+    """Plan for a variable-coefficient operator: coef a float64 CUDA tensor of shape
+    (2d + 1,) + full grid holding a_P, a_W, a_E, a_S, a_N (, a_D, a_U); mask an optional uint8
+    CUDA tensor of the full-grid shape (nonzero = fixed point)."""
+    import torch
+
+    L = lib()
+    g = _Grid()
+    _fill_grid(g, n, 1.0, "f64", "dirichlet")
+    full = tuple(x + 2 for x in reversed(tuple(n)))
+    if not (isinstance(coef, torch.Tensor) and coef.is_cuda and coef.dtype == torch.float64 and coef.is_contiguous()
+            and tuple(coef.shape) == (2 * len(n) + 1,) + full):
+        raise TypeError(f"coef must be a contiguous float64 CUDA tensor of shape {(2 * len(n) + 1,) + full}")
+    mp = None
+    if mask is not None:
+        if not (isinstance(mask, torch.Tensor) and mask.is_cuda and mask.dtype == torch.uint8 and mask.is_contiguous()
+                and tuple(mask.shape) == full):
+            raise TypeError("mask must be a contiguous uint8 CUDA tensor of the full-grid shape")
+        mp = ctypes.c_void_p(mask.data_ptr())
+    s = _Schedule()
+    keep = []
+    _fill_schedule(s, P, omega, q, kappa_min, ordering, sequence, n_eff, q_rounding, keep)
+    out = ctypes.c_void_p()
+    st = stream if stream is not None else _stream_handle()
+    _check(L.srj_plan_operator(ctypes.byref(g), ctypes.byref(s), ctypes.c_void_p(coef.data_ptr()), mp, st,
+                               ctypes.byref(out)))
     return Plan(out, n, len(n))
 
 

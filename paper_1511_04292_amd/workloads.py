@@ -194,3 +194,59 @@ def exp_xy_unit_square(nx_zones=585, ny_zones=280):
     u0 = ue.copy()
     u0[1:-1, 1:-1] = 0.0
     return dict(n=(nx, ny), h=(hx, hy), u0=u0, f=f, u_exact=ue)
+
+
+def grad_shafranov(n=298, C=0.0, test="A"):
+    """The linear Grad-Shafranov problem of Sec. 5.3, Delta* Psi + C^2 Psi = 0 with
+    Delta* = d_rr + r^-2 d_thth - cot(th) r^-2 d_th, on r in [1, 10], th in [0, pi], with
+    n x n interior points (n + 2 equispaced points per axis including the boundaries: the
+    paper's 300 x 300 grid is n = 298).  x (the fastest axis) is r, y is theta.
+
+    Written as A Psi = 0 with A = -(Delta* + C^2) discretised by second-order central
+    differences: a_W = a_E = 1/h_r^2, a_S = 1/(r^2 h_th^2) + cot(th)/(2 r^2 h_th),
+    a_N = 1/(r^2 h_th^2) - cot(th)/(2 r^2 h_th), a_P = 2/h_r^2 + 2/(r^2 h_th^2) - C^2.
+    Test A: Psi = sin^2(th)/r at r = 1 and r = 10, 0 at th = 0, pi (exact solution for C = 0:
+    sin^2(th)/r).  Test B: the same operator solved only inside the region r < R(th) of
+    Eq. shape_b with the disk (r sin th - 4)^2 + (r cos th - 1.6)^2 < 1 removed; Psi = 0 outside
+    it (a mask) and on the outer boundaries, Psi = sin^2(pi (th - th1)/(th2 - th1)) on r = 1 for
+    th1 = 0.3037 <= th <= th2 = 2.8903.  The start is 0 everywhere inside.
+    Returns n, coef (5, n+2, n+2), u0, f (zeros), mask (uint8 or None), r, theta and, for test
+    A, u_exact."""
+    m = n + 2
+    r = 1.0 + 9.0 * np.arange(m, dtype=np.float64) / (m - 1)
+    th = math.pi * np.arange(m, dtype=np.float64) / (m - 1)
+    hr, ht = 9.0 / (m - 1), math.pi / (m - 1)
+    R, TH = np.meshgrid(r, th, indexing="xy")
+    coef = np.zeros((5, m, m))
+    with np.errstate(divide="ignore", invalid="ignore"):
+        cot = np.cos(TH) / np.sin(TH)
+    inv_r2 = 1.0 / (R * R)
+    coef[0] = 2.0 / (hr * hr) + 2.0 * inv_r2 / (ht * ht) - C * C
+    coef[1] = 1.0 / (hr * hr)
+    coef[2] = 1.0 / (hr * hr)
+    coef[3] = inv_r2 / (ht * ht) + cot * inv_r2 / (2.0 * ht)
+    coef[4] = inv_r2 / (ht * ht) - cot * inv_r2 / (2.0 * ht)
+    ring = np.ones((m, m), bool)
+    ring[1:-1, 1:-1] = False
+    coef[:, ring] = 0.0
+    coef[0, ring] = 1.0
+    u0 = np.zeros((m, m))
+    out = dict(n=(n, n), coef=coef, f=np.zeros((m, m)), r=r, theta=th, mask=None)
+    if test == "A":
+        u0[:, 0] = np.sin(th) ** 2 / r[0]
+        u0[:, -1] = np.sin(th) ** 2 / r[-1]
+        u0[0, :] = u0[-1, :] = 0.0
+        out["u_exact"] = np.sin(TH) ** 2 / R
+    else:
+        shape = (4.5 * np.sin(TH) ** 2 + 2.5 * np.sin(2 * TH) ** 2) * (
+            1 - 0.4 * np.cos(3 * TH) + 0.3 * np.cos(5 * TH) + 0.05 * np.sin(25 * TH))
+        disk = (R * np.sin(TH) - 4.0) ** 2 + (R * np.cos(TH) - 1.6) ** 2 < 1.0
+        inside = (R < shape) & ~disk
+        th1, th2 = 0.3037, 2.8903
+        on = (th >= th1) & (th <= th2)
+        u0[:, 0] = np.where(on, np.sin((th - th1) / (th2 - th1) * math.pi) ** 2, 0.0)
+        mask = np.zeros((m, m), np.uint8)
+        mask[1:-1, 1:-1] = (~inside[1:-1, 1:-1]).astype(np.uint8)
+        out["mask"] = mask
+    out["u0"] = u0
+    return out
