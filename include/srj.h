@@ -120,6 +120,7 @@ typedef struct {
     double prefix_peak_log10;      /* largest partial product of the ordered cycle, log10 */
     double suffix_peak_log10;
     int32_t fused_sweeps;          /* sweeps fused per launch by the 2D/3D kernels */
+    int32_t resident;              /* 1: srj_solve runs in one workgroup with the grid in LDS */
 } srj_plan_desc;
 
 typedef struct {
@@ -144,7 +145,10 @@ void srj_plan_destroy(srj_plan_t plan);
 srj_status srj_plan_describe(srj_plan_t plan, srj_plan_desc* out);
 /* Copy the ordered level indices of one cycle (cap >= M) into seq. */
 srj_status srj_plan_sequence(srj_plan_t plan, int32_t* seq, int64_t cap);
-/* Override the number of sweeps fused per launch (0 = unfused reference kernel; at most
+/* Small binary64 2D Dirichlet grids (at most 6656 points with the ring, e.g. 79 x 79 interior)
+ * are solved by srj_solve in one launch of one workgroup holding the grid in LDS (resident = 1
+ * in srj_plan_desc); srj_plan_set_fusion turns that off.
+ * Override the number of sweeps fused per launch (0 = unfused reference kernel; at most
  * 10 in 2D, 5 in 3D; the default is the largest, except 4 for binary64 in 3D)
  * and the output rows each wave of the fused 2D kernel computes (seg_rows = 0, the
  * default: chosen per launch so that the grid of waves fills the device's resident wave

@@ -155,6 +155,8 @@ struct srj_plan_s {
     double kappa_min = 0, kappa_max = 0, rho = 0, gamma_q = 0, pre = 0, suf = 0;
     int fuse = 8;
     int seg_rows = 0;  // output rows per wave in the fused 2D kernel (0: from the occupancy)
+    bool resident = false;      // srj_solve runs in one workgroup with the grid in LDS
+    double* cseq_d = nullptr;   // the cycle's coefficients on the device (resident solves)
     uint32_t fused_launches = 0;  // 2D launches so far: their parity alternates the stream direction
 
     // device buffers
@@ -177,9 +179,11 @@ srj_status alloc_field(srj_plan_t p, Fmt f, DField* d)
 {
     size_t es = fmt_size(f);
     size_t bytes = p->field_elems * es;
-    if (hipMalloc(&d->alloc, bytes) != hipSuccess) {
+    const hipError_t e = hipMalloc(&d->alloc, bytes);
+    if (e != hipSuccess) {
         d->alloc = nullptr;
-        return fail(SRJ_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+        return fail(SRJ_ENOMEM,
+                    "device allocation of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
     }
     int64_t off = kAlignBytes / (int64_t)es - 1;
     d->origin = (char*)d->alloc + off * es;
@@ -230,6 +234,7 @@ void destroy(srj_plan_t p)
     for (auto& f : p->opw) free_field(&f);
     free_field(&p->opap);
     if (p->opmask_alloc) (void)hipFree(p->opmask_alloc);
+    if (p->cseq_d) (void)hipFree(p->cseq_d);
     if (p->partials) (void)hipFree(p->partials);
     if (p->dres) (void)hipFree(p->dres);
     if (p->hres) (void)hipHostFree(p->hres);
@@ -306,6 +311,20 @@ void fill_info(srj_solve_info* info, int64_t sweeps, int64_t cycles, double relr
 srj_status solve_fields(srj_plan_t p, double tol, int64_t max_sweeps, DField** cur, int64_t* k_out,
                         int64_t* cycles_out, double* rr_out, srj_status* result)
 {
+    if (p->resident) {
+        // the whole solve in one launch, the grid in LDS; one synchronisation
+        HIPCHK(launch_small_solve((const double*)p->A.origin, (const double*)p->blo.origin, (double*)p->B.origin,
+                                  p->geo, p->cseq_d, p->M, tol, max_sweeps, p->dres, p->stream));
+        HIPCHK(hipMemcpyAsync(p->hres, p->dres, 4 * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+        HIPCHK(hipStreamSynchronize(p->stream));
+        *cur = &p->B;
+        *k_out = (int64_t)p->hres[0];
+        *cycles_out = (int64_t)p->hres[1];
+        *rr_out = p->hres[2];
+        const int stt = (int)p->hres[3];
+        *result = stt == 5 ? SRJ_ENOCONV : (stt == 6 ? SRJ_EDIVERGED : SRJ_OK);
+        return SRJ_OK;
+    }
     // reference norm: ||b~|| (the residual of the zero interior); with Neumann boundaries the
     // operator is singular and the reference is the initial residual
     double bt2, bmax;
@@ -505,6 +524,15 @@ srj_status create_plan(const srj_grid* grid, const srj_schedule* schedule, void*
     p->fuse = (!p->iso || g.bc != 0) ? 0
                       : (g.ndim == 2) ? kMaxFuse
                                       : (fused3d_fits(g, p->fmt) ? (p->fmt == FMT_F64 ? kMaxFuse3d - 1 : kMaxFuse3d) : 0);
+    // small binary64 2D grids: srj_solve keeps the grid in one compute unit's LDS
+    if (p->fmt == FMT_F64 && small_solve_fits(g)) {
+        if (hipMalloc(&p->cseq_d, sizeof(double) * (size_t)p->M) != hipSuccess ||
+            hipMemcpy(p->cseq_d, p->cseq.data(), sizeof(double) * (size_t)p->M, hipMemcpyHostToDevice) != hipSuccess) {
+            destroy(p);
+            return fail(SRJ_ENOMEM, "allocation of the coefficient table failed");
+        }
+        p->resident = true;
+    }
     *out = p;
     return SRJ_OK;
 }
@@ -549,6 +577,7 @@ srj_status srj_plan_describe(srj_plan_t p, srj_plan_desc* out)
     out->prefix_peak_log10 = p->pre;
     out->suffix_peak_log10 = p->suf;
     out->fused_sweeps = p->fuse;
+    out->resident = p->resident ? 1 : 0;
     return SRJ_OK;
 }
 
@@ -572,6 +601,7 @@ srj_status srj_plan_set_fusion(srj_plan_t p, int32_t fused, int32_t seg_rows)
     if (seg_rows < 0 || seg_rows > (1 << 20)) return fail(SRJ_EINVAL, "segment rows must be in [0, 2^20]");
     p->fuse = fused;
     p->seg_rows = seg_rows;
+    p->resident = false;  // an explicit launch shape: srj_solve runs the sweep kernels
     return SRJ_OK;
 }
 

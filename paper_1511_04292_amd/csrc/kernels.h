@@ -99,6 +99,15 @@ hipError_t launch_op_setup(const double* coef, const uint8_t* mask_user, double*
                            uint8_t* mask, const Geo& g, hipStream_t s);
 // b = f / a_P at the free interior points (0 elsewhere), into b64 (padded, binary64)
 hipError_t launch_op_rhs(const double* user_f, const double* ap, double* b64, const Geo& g, hipStream_t s);
+// Whole solves of small 2D grids in one workgroup with the grid in LDS (binary64 Dirichlet
+// Poisson plans of at most kSmallPoints points including the ring): iterate pair and source
+// in LDS, residual checks at k = 0 and every cycle end, as srj_solve.  in/b/out are padded
+// fields, cseq the M coefficients of a cycle (device), res receives {sweeps, cycles, relres,
+// status} (device, 4 doubles).
+constexpr int kSmallPoints = 6656;
+bool small_solve_fits(const Geo& g);
+hipError_t launch_small_solve(const double* in, const double* b, double* out, const Geo& g, const double* cseq,
+                              int64_t M, double tol, int64_t max_sweeps, double* res, hipStream_t s);
 // set every element of the field (ring included) to zero with a fill kernel
 hipError_t launch_zero(Fmt f, void* field, const Geo& g, hipStream_t s);
 

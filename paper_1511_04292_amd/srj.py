@@ -62,7 +62,8 @@ class _Desc(ctypes.Structure):
                 ("q", ctypes.c_int64 * MAX_LEVELS), ("kappa_min", ctypes.c_double),
                 ("kappa_max", ctypes.c_double), ("rho", ctypes.c_double),
                 ("gamma_q_max", ctypes.c_double), ("prefix_peak_log10", ctypes.c_double),
-                ("suffix_peak_log10", ctypes.c_double), ("fused_sweeps", ctypes.c_int32)]
+                ("suffix_peak_log10", ctypes.c_double), ("fused_sweeps", ctypes.c_int32),
+                ("resident", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -90,6 +91,11 @@ def lib():
         return _lib
     if not os.path.exists(SO):
         raise ImportError(f"libsrj.so is not built ({SO}); run __graft_entry__.build()")
+    # The tensors handed to the library come from torch's HIP runtime.  Loading torch first
+    # makes libsrj's libamdhip64.so.7 dependency resolve to that same, already mapped
+    # runtime; loaded the other way round the process would hold two HIP (and two HSA)
+    # runtimes, and the second one to reach the device fails its allocations.
+    import torch  # noqa: F401
     L = ctypes.CDLL(SO)
     vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     L.srj_plan.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Schedule), vp, ctypes.POINTER(vp)]
@@ -256,7 +262,7 @@ def srj_plan_describe(plan):
     return dict(P=P, M=d.M, omega=np.array(d.omega[:P]), beta=np.array(d.beta[:P]),
                 q=np.array(d.q[:P], dtype=np.int64), kappa_min=d.kappa_min, kappa_max=d.kappa_max,
                 rho=d.rho, gamma_q_max=d.gamma_q_max, prefix_peak_log10=d.prefix_peak_log10,
-                suffix_peak_log10=d.suffix_peak_log10, fused_sweeps=d.fused_sweeps)
+                suffix_peak_log10=d.suffix_peak_log10, fused_sweeps=d.fused_sweeps, resident=d.resident)
 
 
 def srj_plan_sequence(plan):

@@ -29,6 +29,22 @@ def test_library_exports_every_declared_symbol():
     assert sorted(srj.EXPORTS) == names, (sorted(srj.EXPORTS), names)
 
 
+def test_library_shares_torchs_hip_runtime():
+    """Whatever the import order, the process maps one HIP runtime: the library binds to
+    the one torch loaded (a second runtime's device allocations fail)."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_1511_04292_amd import srj\n"
+            "srj.lib()\n"
+            "import torch\n"
+            "maps = {l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}\n"
+            "print(len(maps))\n") % ROOT
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1", out.stdout
+
+
 def test_status_strings():
     L = srj.lib()
     assert L.srj_status_string(0) == b"ok"

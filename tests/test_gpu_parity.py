@@ -202,8 +202,9 @@ def test_solve_small_2d_srj_matches_oracle():
     w, q, seq = oracle_schedule(2, wl["n"])
     wseq = np.array(w)[seq]
     ref = sweeps.solve(wl["u0"], wl["f"], wl["h"], wseq, 1e-10, 10 ** 5)
-    for fuse in (0, 8):
+    for fuse in (None, 0, 8):  # None: the default, one workgroup with the grid in LDS
         p = explicit_plan(wl["n"], wl["h"], w, q, seq, fuse=fuse)
+        assert srj.srj_plan_describe(p)["resident"] == (1 if fuse is None else 0)
         ug = dev(wl["u0"])
         info = srj.srj_solve(p, ug, dev(wl["f"]), 1e-10, 10 ** 5)
         assert info["status"] == "ok" and ref["status"] == "ok"
@@ -219,11 +220,41 @@ def test_solve_small_2d_srj_matches_oracle():
 def test_solve_jacobi_matches_oracle():
     wl = workloads.small_2d(20, seed=1)
     ref = sweeps.solve(wl["u0"], wl["f"], wl["h"], [1.0], 1e-6, 10 ** 5)
-    p = srj.srj_plan(wl["n"], wl["h"], omega=[1.0], q=[1])
-    ug = dev(wl["u0"])
-    info = srj.srj_solve(p, ug, dev(wl["f"]), 1e-6, 10 ** 5)
-    assert info["sweeps"] == ref["sweeps"]
+    for resident in (True, False):
+        p = srj.srj_plan(wl["n"], wl["h"], omega=[1.0], q=[1])
+        if not resident:
+            srj.srj_plan_set_fusion(p, 10)
+        ug = dev(wl["u0"])
+        info = srj.srj_solve(p, ug, dev(wl["f"]), 1e-6, 10 ** 5)
+        assert info["sweeps"] == ref["sweeps"]
+        assert abs(info["relres"] - ref["relres"]) <= 1e-12 * ref["relres"]
+        assert np.array_equal(host(ug), ref["u"])
+
+
+@pytest.mark.parametrize("n,h", [((79, 79), None), ((1, 1), None), ((3, 200), None), ((61, 47), (1.0 / 62, 1.0 / 20))])
+def test_resident_small_solve_matches_oracle(n, h):
+    """Grids up to 6656 points with the ring are solved in one workgroup with the grid in LDS:
+    the same stopping sweep and iterate as the oracle (equal and unequal spacings, the largest
+    such square, degenerate shapes)."""
+    hh = h if h is not None else 1.0 / (max(n) + 1)
+    rng = np.random.default_rng(17)
+    full = (n[1] + 2, n[0] + 2)
+    u0 = workloads.random_ring(full, rng)
+    f = rng.standard_normal(full)
+    km = S.kappa_min_dirichlet(n, h)
+    o = S.optimal(3, km)
+    q = S.q_floor(o["beta"])
+    seq = S.order_balanced(o["w"], q, km)
+    ref = sweeps.solve(u0, f, hh, np.asarray(o["w"])[seq], 1e-11, 10 ** 6)
+    p = srj.srj_plan(n, hh, omega=o["w"], q=q, sequence=seq)
+    assert srj.srj_plan_describe(p)["resident"] == 1
+    ug = dev(u0)
+    info = srj.srj_solve(p, ug, dev(f), 1e-11, 10 ** 6)
+    assert info["status"] == ref["status"] == "ok" and info["sweeps"] == ref["sweeps"]
+    assert abs(info["relres"] - ref["relres"]) <= 1e-12 * max(ref["relres"], 1e-300)
     assert np.array_equal(host(ug), ref["u"])
+    big = srj.srj_plan((80, 80), 1.0 / 81, omega=[1.0], q=[1])
+    assert srj.srj_plan_describe(big)["resident"] == 0
 
 
 def test_solve_3d_matches_oracle():
