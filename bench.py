@@ -212,7 +212,9 @@ def main():
                     help="print per-kernel, per-grid launch statistics of a rocprofv3 --kernel-trace run")
     ap.add_argument("--kernel-only", action="store_true",
                     help="counter-collection run: one 1 GiB read / 1 GiB write calibration kernel, then "
-                         "20 fused and 20 unfused sweep launches on the workload; prints no JSON")
+                         "20 fused and 20 unfused sweep launches on the workload, 20 fused launches in "
+                         "binary32 and bfloat16, and 20 sweeps of the 512^3 grid in each format; prints "
+                         "no JSON")
     args = ap.parse_args()
     if args.ingest_counters:
         print(ingest_counters(*args.ingest_counters))
@@ -267,11 +269,19 @@ def main():
         srj.srj_sweeps(plan, u, f, 0, 20)
         torch.cuda.synchronize()
         if args.workloads == "all":
+            # the binary32 and bfloat16 fused 2D sweeps on the same grid (their default depth)
+            for fmt in ("f32", "bf16"):
+                pl = srj.srj_plan(wl["n"], wl["h"], P=args.levels, dtype=fmt)
+                fl = int(srj.srj_plan_describe(pl)["fused_sweeps"])
+                u.copy_(u0)
+                srj.srj_sweeps(pl, u, f, 0, 20 * fl)
+                del pl
+            torch.cuda.synchronize()
             del plan, u, u0, f
             w3 = workloads.smooth_3d(512, seed=0)
             u3 = torch.from_numpy(w3["u0"]).to(dev)
             f3 = torch.from_numpy(w3["f"]).to(dev)
-            for fmt in ("f64", "f32"):
+            for fmt in ("f64", "f32", "bf16"):
                 p3 = srj.srj_plan(w3["n"], w3["h"], P=8, dtype=fmt)
                 srj.srj_sweeps(p3, u3.clone(), f3, 0, 20)
                 del p3

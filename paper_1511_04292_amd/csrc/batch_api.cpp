@@ -93,7 +93,8 @@ struct srj_batch_s {
     double* bt2_d = nullptr;  // 2 doubles per problem
     int* remaining_d = nullptr;
     uint64_t* t0_d = nullptr;
-    int* remaining_h = nullptr;
+    int* remaining_h = nullptr;  // two pinned slots: counts read back after alternate replays
+    hipEvent_t ev[2] = {nullptr, nullptr};
     int* nitems_h = nullptr;  // pinned staging of the work-list length
     int items_h_len = 0;
     int hmax = 128;           // largest tile height (srj_batch_tune may change it)
@@ -113,6 +114,8 @@ void destroy_batch(srj_batch_t b)
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (b->remaining_h) (void)hipHostFree(b->remaining_h);
+    for (hipEvent_t e : b->ev)
+        if (e) (void)hipEventDestroy(e);
     if (b->nitems_h) (void)hipHostFree(b->nitems_h);
     if (b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
@@ -240,7 +243,9 @@ srj_status srj_batch_plan(int32_t count, const srj_grid* grids, const srj_schedu
               hipMalloc(&b->bt2_d, sizeof(double) * 2 * count) == hipSuccess &&
               hipMalloc(&b->remaining_d, sizeof(int)) == hipSuccess &&
               hipMalloc(&b->t0_d, sizeof(uint64_t)) == hipSuccess &&
-              hipHostMalloc(&b->remaining_h, sizeof(int), hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc(&b->remaining_h, 2 * sizeof(int), hipHostMallocDefault) == hipSuccess &&
+              hipEventCreateWithFlags(&b->ev[0], hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&b->ev[1], hipEventDisableTiming) == hipSuccess &&
               hipHostMalloc(&b->nitems_h, sizeof(int), hipHostMallocDefault) == hipSuccess &&
               hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) == hipSuccess;
     if (!ok) {
@@ -414,6 +419,7 @@ srj_status srj_batch_solve(srj_batch_t b, double* const* u, const double* const*
     const int tiles_target = kTilesTarget;
     std::vector<BItem> items;
     items.reserve(b->nitems);
+    std::vector<int> order;
     auto running = [](const BState& x) { return x.phase == BP_SWEEP || x.phase == BP_RESIDUAL; };
     // returns true if some running problem changed its tile height
     auto build_items = [&](const std::vector<BState>& cur) {
@@ -429,6 +435,7 @@ srj_status srj_batch_solve(srj_batch_t b, double* const* u, const double* const*
         }
         bool changed = false;
         items.clear();
+        order.clear();
         for (int j = 0; j < b->count; ++j) {
             if (!running(cur[j])) continue;
             BProb& P = b->probs[j];
@@ -438,8 +445,19 @@ srj_status srj_batch_solve(srj_batch_t b, double* const* u, const double* const*
                 P.ntiles = tiles_of(b->geos[j], SW, Hj);
                 changed = true;
             }
-            for (int t = 0; t < P.ntiles; ++t) items.push_back(BItem{j, t});
+            order.push_back(j);
         }
+        // Longest tiles first: a wave's time on a tile grows with the rows it streams (the
+        // tile's output rows plus 2T), so listing the tallest tiles first lets the short ones
+        // fill in behind them and ends each launch sooner (longest-processing-time-first).
+        auto tile_rows = [&](int j) { return std::min<int64_t>(b->probs[j].H, b->geos[j].ny); };
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+            const int64_t rx = tile_rows(x), ry = tile_rows(y);
+            if (rx != ry) return rx > ry;
+            return b->geos[x].nx > b->geos[y].nx;
+        });
+        for (int j : order)
+            for (int t = 0; t < b->probs[j].ntiles; ++t) items.push_back(BItem{j, t});
         b->items_h_len = (int)items.size();
         return changed;
     };
@@ -460,28 +478,40 @@ srj_status srj_batch_solve(srj_batch_t b, double* const* u, const double* const*
     run.coef = b->coef_d;
     run.partials = b->partials_d;
     run.remaining = b->remaining_d;
-    const int gs = std::max(1, std::min((b->nitems + 3) / 4, 2048));
-    // one graph = G launches
+    // One graph = G launches over a grid of gs blocks (4 waves each, grid-stride over the
+    // work list).  The graph is captured again with a smaller grid whenever the work list has
+    // shrunk to less than half of what the current grid covers, so that launches near the end
+    // do not start thousands of waves that find no tile.
     const int G = 16;
-    if (b->exec) {
-        (void)hipGraphExecDestroy(b->exec);
-        b->exec = nullptr;
-    }
-    if (b->graph) {
-        (void)hipGraphDestroy(b->graph);
-        b->graph = nullptr;
-    }
-    BCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    for (int it = 0; it < G; ++it) {
-        if (launch_batch_step(b->fmt, b->probs_d, b->st_d, run, gs, s) != hipSuccess) {
-            hipGraph_t g0 = nullptr;
-            (void)hipStreamEndCapture(s, &g0);
-            if (g0) (void)hipGraphDestroy(g0);
-            return report(SRJ_EHIP, "batch launch during capture failed");
+    auto grid_for = [](int nitems) { return std::max(1, std::min((nitems + 3) / 4, 2048)); };
+    int gs = 0;
+    auto capture = [&](int blocks) -> srj_status {
+        if (b->exec) {
+            (void)hipGraphExecDestroy(b->exec);
+            b->exec = nullptr;
         }
+        if (b->graph) {
+            (void)hipGraphDestroy(b->graph);
+            b->graph = nullptr;
+        }
+        BCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        for (int it = 0; it < G; ++it) {
+            if (launch_batch_step(b->fmt, b->probs_d, b->st_d, run, blocks, s) != hipSuccess) {
+                hipGraph_t g0 = nullptr;
+                (void)hipStreamEndCapture(s, &g0);
+                if (g0) (void)hipGraphDestroy(g0);
+                return report(SRJ_EHIP, "batch launch during capture failed");
+            }
+        }
+        BCHK(hipStreamEndCapture(s, &b->graph));
+        BCHK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+        gs = blocks;
+        return SRJ_OK;
+    };
+    {
+        const srj_status cs = capture(grid_for(b->items_h_len));
+        if (cs != SRJ_OK) return cs;
     }
-    BCHK(hipStreamEndCapture(s, &b->graph));
-    BCHK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
     // launches needed at most: every outer step of the longest problem (its sweeps and its
     // residual) plus the first residual
     int64_t max_inner = 0;
@@ -489,16 +519,35 @@ srj_status srj_batch_solve(srj_batch_t b, double* const* u, const double* const*
     const int64_t cap_launches = ((int64_t)max_outer + 1) * ((max_inner + T - 1) / T + 1) + 2;
     const int64_t cap_replays = cap_launches / G + 2;
     BCHK(launch_batch_start(b->t0_d, s));
+    // The host keeps one replay queued behind the one whose count of running problems it
+    // reads: each replay is followed by a copy of that count into its own pinned slot and an
+    // event, and the host waits on the previous replay's event only, so the device never
+    // idles between replays.  At most one replay more than needed runs; its launches find
+    // every problem finished and return at once.
     int64_t replays = 0;
     int listed = remaining;  // running problems when the work list was last built
+    int slot = 0;
+    bool pending = false;    // a replay is queued whose count has not been read yet
     while (remaining > 0 && replays < cap_replays) {
         BCHK(hipGraphLaunch(b->exec, s));
-        BCHK(hipMemcpyAsync(b->remaining_h, b->remaining_d, sizeof(int), hipMemcpyDeviceToHost, s));
-        BCHK(hipStreamSynchronize(s));
-        remaining = *b->remaining_h;
+        BCHK(hipMemcpyAsync(b->remaining_h + slot, b->remaining_d, sizeof(int), hipMemcpyDeviceToHost, s));
+        BCHK(hipEventRecord(b->ev[slot], s));
         replays += 1;
+        if (!pending) {
+            pending = true;
+            slot ^= 1;
+            continue;
+        }
+        // read the previous replay's count while this one runs
+        BCHK(hipEventSynchronize(b->ev[slot ^ 1]));
+        remaining = b->remaining_h[slot ^ 1];
+        slot ^= 1;
         if (remaining > 0 && 4 * remaining <= 3 * listed) {
-            // drop finished problems from the work list
+            // drop finished problems from the work list (after the queued replay)
+            BCHK(hipStreamSynchronize(s));
+            pending = false;
+            remaining = b->remaining_h[slot ^ 1];
+            if (remaining == 0) break;
             BCHK(hipMemcpyAsync(st.data(), b->st_d, sizeof(BState) * b->count, hipMemcpyDeviceToHost, s));
             BCHK(hipStreamSynchronize(s));
             if (build_items(st))
@@ -508,8 +557,13 @@ srj_status srj_batch_solve(srj_batch_t b, double* const* u, const double* const*
             BCHK(hipMemcpyAsync(b->nitems_d, b->nitems_h, sizeof(int), hipMemcpyHostToDevice, s));
             BCHK(hipStreamSynchronize(s));
             listed = remaining;
+            if (2 * grid_for(b->items_h_len) <= gs) {
+                const srj_status cs = capture(grid_for(b->items_h_len));
+                if (cs != SRJ_OK) return cs;
+            }
         }
     }
+    BCHK(hipStreamSynchronize(s));
     BCHK(hipMemcpyAsync(st.data(), b->st_d, sizeof(BState) * b->count, hipMemcpyDeviceToHost, s));
     uint64_t t0 = 0;
     BCHK(hipMemcpyAsync(&t0, b->t0_d, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
