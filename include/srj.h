@@ -163,6 +163,32 @@ srj_status srj_plan_set_fusion(srj_plan_t plan, int32_t fused_sweeps, int32_t se
 srj_status srj_solve(srj_plan_t plan, double* u, const double* f, double tol, int64_t max_sweeps,
                      srj_solve_info* info);
 
+/* Options of srj_solve_ex; zero-initialise, then set what is used. */
+typedef struct {
+    double tol;             /* as srj_solve */
+    int64_t max_sweeps;     /* sweeps this call may apply */
+    int64_t start_offset;   /* 0 <= start_offset < M: u is the iterate after start_offset sweeps
+                               of a cycle (a checkpoint taken mid-cycle, e.g. after srj_sweeps);
+                               the solve first applies the cycle's remaining M - start_offset
+                               sweeps and checks at that cycle end */
+    double* history;        /* host array or NULL: relres of every check, in order */
+    int64_t history_cap;    /* entries history holds (the first history_cap checks are kept) */
+    int64_t history_len;    /* out: checks made (can exceed history_cap) */
+} srj_solve_opts;
+
+/* srj_solve with a start offset and a record of the residual at every check (the history
+ * the paper plots against sweeps, Sec. 4, and the state a resumed solve needs: u and the
+ * step index k mod M).  A solve resumed from the iterate after k_c sweeps of an interrupted
+ * solve, with start_offset = k_c mod M, applies the same sweeps, stops at the same sweep
+ * (counted from k_c) and returns the same bits as the uninterrupted one, provided that one
+ * had not stopped before k_c.  With Neumann boundaries the reference of relres is the
+ * residual of the state passed in.  If the budget does not reach the end of the started
+ * cycle, u is returned unchanged with SRJ_ENOCONV, 0 sweeps and the relres of u.
+ * A solve with a history or a start offset runs the multi-launch path even on a plan that
+ * srj_solve would solve in LDS (same results).  Other arguments and status as srj_solve. */
+srj_status srj_solve_ex(srj_plan_t plan, double* u, const double* f, srj_solve_opts* opts,
+                        srj_solve_info* info);
+
 /* Apply exactly nsweeps scheduled sweeps to u, the first one being step k0 (mod M) of the
  * cycle.  No convergence checks.  If stats is not NULL, stats[0] receives the device time
  * in seconds of the sweep launches alone (HIP events on the plan's stream around them) and
@@ -280,6 +306,21 @@ typedef struct {
 } srj_tune_info;
 srj_status srj_plan_tune(srj_plan_t plan, srj_tune_info* info);
 srj_status srj_batch_tune(srj_batch_t batch, srj_tune_info* info);
+/* srj_plan_tune through an on-disk cache (a text file at path, created if missing, one line
+ * per tuned configuration).  The key is the device (architecture name and compute-unit
+ * count), ndim, n, the storage format, the boundary kind, equal or unequal spacings and
+ * operator plans.  On a hit the stored launch shape is applied without timing anything
+ * (info->candidates = 0, both times = the stored time); on a miss the plan is tuned and a
+ * line is appended.  Entries that the plan could not run are ignored.  SRJ_EINVAL for a
+ * null path, SRJ_EHIP if the file cannot be written after tuning (the plan is tuned
+ * anyway). */
+srj_status srj_plan_tune_cached(srj_plan_t plan, const char* path, srj_tune_info* info);
+
+/* Debugging aid: fill every device buffer the plan owns, padding and alignment slack
+ * included, with all-one bytes (a NaN in binary64, binary32 and bfloat16).  Later calls
+ * write the points they use before reading them, so a kernel that read outside its
+ * stencil's points would turn results into NaN; results must stay bit-identical. */
+srj_status srj_plan_poison(srj_plan_t plan);
 
 /* Host-only schedule computations (no device needed). */
 /* Optimal P-level weights/fractions on [kappa_min, kappa_max] (Sec. 3) and counts

@@ -308,10 +308,25 @@ void fill_info(srj_solve_info* info, int64_t sweeps, int64_t cycles, double relr
 
 // Solve on the plan's fields: A and B hold the initial state (ring included), blo/b64 the
 // scaled source.  On return *cur points at the field with the returned state.
+// Where a solve records the relres of its checks (host memory, first cap entries kept).
+struct History {
+    double* out = nullptr;
+    int64_t cap = 0;
+    int64_t len = 0;
+    void push(double rr)
+    {
+        if (len < cap) out[len] = rr;
+        len += 1;
+    }
+};
+
+// k0 (0 <= k0 < M): the state in A/B is the iterate after k0 sweeps of a cycle; the solve
+// completes that cycle before its first check.  hist (may be null) receives every check.
 srj_status solve_fields(srj_plan_t p, double tol, int64_t max_sweeps, DField** cur, int64_t* k_out,
-                        int64_t* cycles_out, double* rr_out, srj_status* result)
+                        int64_t* cycles_out, double* rr_out, srj_status* result, int64_t k0 = 0,
+                        History* hist = nullptr)
 {
-    if (p->resident) {
+    if (p->resident && k0 == 0 && !hist) {
         // the whole solve in one launch, the grid in LDS; one synchronisation
         HIPCHK(launch_small_solve((const double*)p->A.origin, (const double*)p->blo.origin, (double*)p->B.origin,
                                   p->geo, p->cseq_d, p->M, tol, max_sweeps, p->dres, p->stream));
@@ -338,26 +353,65 @@ srj_status solve_fields(srj_plan_t p, double tol, int64_t max_sweeps, DField** c
     if (!is_finite(bt2)) {
         *result = SRJ_EDIVERGED;
         rr = NAN;
+        if (hist) hist->push(rr);
     } else if (bt2 == 0.0) {
         // Dirichlet: zero source and zero boundary, u = 0 is exact; Neumann: the initial
         // state already has a zero residual and is returned as it is
         if (p->geo.bc == 0) HIPCHK(launch_zero(p->fmt, (*cur)->origin, p->geo, p->stream));
         rr = 0.0;
     } else {
+        // Binary64 plans whose sweeps run one per launch (and single-sweep cycles) take each
+        // check from the cycle's first sweep: that sweep forms the residual of the state it
+        // starts from, bit for bit as a separate evaluation would, and writes its result to
+        // the other field, so a converged state is still in *cur.  Blocked launches carry a
+        // whole cycle's sweeps per pass over the grid, where a separate check costs less
+        // than an extra unblocked sweep.
+        const bool fused_check = p->fmt == FMT_F64 && (p->fuse <= 0 || p->M == 1);
+        if (k0 > 0) {
+            // a resumed solve: the rest of the cycle first (a mid-cycle state is not checked)
+            if (p->M - k0 > max_sweeps) {
+                double r2, rmax;
+                if ((st = residual_now(p, (*cur)->origin, p->fmt, 0, &r2, &rmax)) != SRJ_OK) return st;
+                *k_out = 0;
+                *cycles_out = 0;
+                *rr_out = std::sqrt(r2) / std::sqrt(bt2);
+                *result = SRJ_ENOCONV;
+                return SRJ_OK;
+            }
+            if ((st = run_sweeps(p, cur, &nxt, p->blo.origin, k0, p->M - k0)) != SRJ_OK) return st;
+            k = p->M - k0;
+            cycles = 1;
+        }
         for (;;) {
             double r2, rmax;
-            if ((st = residual_now(p, (*cur)->origin, p->fmt, 0, &r2, &rmax)) != SRJ_OK) return st;
+            const bool room = k + p->M <= max_sweeps;  // k counts this call's sweeps
+            if (fused_check && room) {
+                HIPCHK(launch_sweep_residual((const double*)(*cur)->origin, (double*)nxt->origin, p->b64, p->geo,
+                                             p->cseq[0], p->partials, p->dres, p->stream));
+                HIPCHK(hipMemcpyAsync(p->hres, p->dres, 2 * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+                HIPCHK(hipStreamSynchronize(p->stream));
+                r2 = p->hres[0];
+                rmax = p->hres[1];
+            } else if ((st = residual_now(p, (*cur)->origin, p->fmt, 0, &r2, &rmax)) != SRJ_OK) {
+                return st;
+            }
             rr = std::sqrt(r2) / std::sqrt(bt2);
+            if (hist) hist->push(rr);
             if (!is_finite(rr)) {
                 *result = SRJ_EDIVERGED;
                 break;
             }
             if (rr <= tol) break;
-            if (k + p->M > max_sweeps) {
+            if (!room) {
                 *result = SRJ_ENOCONV;
                 break;
             }
-            if ((st = run_sweeps(p, cur, &nxt, p->blo.origin, 0, p->M)) != SRJ_OK) return st;
+            if (fused_check) {
+                std::swap(*cur, nxt);  // the cycle's first sweep is done
+                if ((st = run_sweeps(p, cur, &nxt, p->blo.origin, 1, p->M - 1)) != SRJ_OK) return st;
+            } else if ((st = run_sweeps(p, cur, &nxt, p->blo.origin, 0, p->M)) != SRJ_OK) {
+                return st;
+            }
             k += p->M;
             cycles += 1;
         }
@@ -647,16 +701,21 @@ srj_status srj_sweeps(srj_plan_t p, double* u, const double* f, int64_t k0, int6
     return SRJ_OK;
 }
 
-srj_status srj_plan_tune(srj_plan_t p, srj_tune_info* info)
+}  // extern "C"
+
+namespace {
+
+struct Cand {
+    int T, H;
+};
+
+// Launch shapes the tuner times for a plan, the one in place first.
+std::vector<Cand> tune_candidates(srj_plan_t p)
 {
-    if (!p) return fail(SRJ_EINVAL, "null plan");
-    struct Cand {
-        int T, H;
-    };
     std::vector<Cand> cands;
-    cands.push_back({p->fuse, p->seg_rows});  // the configuration in place, timed first
-    if (!p->iso || p->geo.bc != 0) {
-        // unequal spacings or Neumann boundaries: the unfused kernel is the only one
+    cands.push_back({p->fuse, p->seg_rows});
+    if (!p->iso || p->geo.bc != 0 || p->geo.op) {
+        // unequal spacings, Neumann boundaries, operators: the unfused kernel is the only one
     } else if (p->geo.ndim == 2) {
         for (int T : {10, 8, 6, 4})
             for (int H : {0, 24, 32, 48, 64, 96, 128}) cands.push_back({T, H});
@@ -665,6 +724,37 @@ srj_status srj_plan_tune(srj_plan_t p, srj_tune_info* info)
             for (int T : {5, 4, 3, 2, 1}) cands.push_back({T, 0});
         cands.push_back({0, 0});
     }
+    return cands;
+}
+
+// Cache key of a plan's tuning: device, grid, format, boundary kind, spacing kind, operator.
+srj_status tune_key(srj_plan_t p, std::string* key)
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipGetDeviceProperties(&prop, dev));
+    std::string arch(prop.gcnArchName);
+    for (char& c : arch)
+        if (c == ' ' || c == '\t' || c == '\n') c = '_';
+    if (arch.empty()) arch = "unknown";
+    *key = arch + " " + std::to_string(prop.multiProcessorCount) + " " + std::to_string(p->geo.ndim) + " " +
+           std::to_string(p->geo.nx) + " " + std::to_string(p->geo.ny) + " " + std::to_string(p->geo.nz) + " " +
+           std::to_string((int)p->fmt) + " " + std::to_string(p->geo.bc) + " " + std::to_string(p->iso ? 1 : 0) +
+           " " + std::to_string(p->geo.op ? 1 : 0);
+    return SRJ_OK;
+}
+
+constexpr const char* kTuneTag = "srj-tune-v1";
+
+}  // namespace
+
+extern "C" {
+
+srj_status srj_plan_tune(srj_plan_t p, srj_tune_info* info)
+{
+    if (!p) return fail(SRJ_EINVAL, "null plan");
+    std::vector<Cand> cands = tune_candidates(p);
     HIPCHK(launch_zero(p->fmt, p->A.origin, p->geo, p->stream));
     HIPCHK(launch_zero(p->fmt, p->B.origin, p->geo, p->stream));
     // device time per sweep of a configuration: a unit of sweeps that is a whole number of
@@ -723,6 +813,107 @@ srj_status srj_plan_tune(srj_plan_t p, srj_tune_info* info)
         info->us_per_sweep_before = before;
     }
     return SRJ_OK;
+}
+
+srj_status srj_plan_tune_cached(srj_plan_t p, const char* path, srj_tune_info* info)
+{
+    if (!p || !path) return fail(SRJ_EINVAL, "null argument");
+    std::string key;
+    srj_status st = tune_key(p, &key);
+    if (st != SRJ_OK) return st;
+    const std::vector<Cand> allowed = tune_candidates(p);
+    // the last line for this key wins
+    bool hit = false;
+    Cand got{0, 0};
+    double got_us = 0;
+    if (FILE* fp = std::fopen(path, "r")) {
+        char line[1024];
+        const std::string head = std::string(kTuneTag) + " " + key + " ";
+        while (std::fgets(line, sizeof line, fp)) {
+            const std::string l(line);
+            if (l.compare(0, head.size(), head) != 0) continue;
+            int T = 0, H = 0;
+            double us = 0;
+            if (std::sscanf(l.c_str() + head.size(), "%d %d %lf", &T, &H, &us) != 3) continue;
+            bool ok = false;
+            for (const Cand& c : allowed) ok = ok || (c.T == T && c.H == H);
+            if (!ok) continue;
+            hit = true;
+            got = {T, H};
+            got_us = us;
+        }
+        std::fclose(fp);
+    }
+    if (hit) {
+        p->fuse = got.T;
+        p->seg_rows = got.H;
+        if (info) {
+            info->fused_sweeps = got.T;
+            info->seg_rows = got.H;
+            info->candidates = 0;
+            info->us_per_sweep = got_us;
+            info->us_per_sweep_before = got_us;
+        }
+        return SRJ_OK;
+    }
+    srj_tune_info ti;
+    if ((st = srj_plan_tune(p, &ti)) != SRJ_OK) return st;
+    if (info) *info = ti;
+    FILE* fp = std::fopen(path, "a");
+    if (!fp) return fail(SRJ_EHIP, std::string("cannot append to the tune cache ") + path);
+    const int n = std::fprintf(fp, "%s %s %d %d %.6g\n", kTuneTag, key.c_str(), ti.fused_sweeps, ti.seg_rows,
+                               ti.us_per_sweep);
+    const bool closed = std::fclose(fp) == 0;
+    if (n <= 0 || !closed) return fail(SRJ_EHIP, std::string("cannot append to the tune cache ") + path);
+    return SRJ_OK;
+}
+
+srj_status srj_plan_poison(srj_plan_t p)
+{
+    if (!p) return fail(SRJ_EINVAL, "null plan");
+    const size_t lo = p->field_elems * fmt_size(p->fmt), hi = p->field_elems * sizeof(double);
+    const struct {
+        void* ptr;
+        size_t bytes;
+    } bufs[] = {{p->A.alloc, lo},
+                {p->B.alloc, lo},
+                {p->blo.alloc, lo},
+                {p->b64f.alloc, hi},
+                {p->x64.alloc, hi},
+                {p->partials, sizeof(double) * 2 * (size_t)residual_blocks(p->geo)}};
+    for (const auto& b : bufs)
+        if (b.ptr) HIPCHK(hipMemsetAsync(b.ptr, 0xFF, b.bytes, p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));
+    return SRJ_OK;
+}
+
+srj_status srj_solve_ex(srj_plan_t p, double* u, const double* f, srj_solve_opts* opts, srj_solve_info* info)
+{
+    fill_info(info, 0, 0, NAN, 0, SRJ_EINVAL);
+    if (!p || !u || !f || !opts) return fail(SRJ_EINVAL, "null argument");
+    opts->history_len = 0;
+    if (!(opts->tol >= 0) || opts->max_sweeps < 0) return fail(SRJ_EINVAL, "bad tolerance or sweep budget");
+    if (opts->start_offset < 0 || opts->start_offset >= p->M)
+        return fail(SRJ_EINVAL, "start_offset must be in [0, M)");
+    if (opts->history_cap < 0 || (opts->history_cap > 0 && !opts->history))
+        return fail(SRJ_EINVAL, "history needs a buffer of history_cap entries");
+    HIPCHK(hipEventRecord(p->ev0, p->stream));
+    HIPCHK(launch_copy_in(p->fmt, u, p->A.origin, p->geo, p->stream));
+    HIPCHK(launch_copy_in(p->fmt, u, p->B.origin, p->geo, p->stream));
+    HIPCHK(load_rhs(p, f));
+    DField* cur = nullptr;
+    int64_t k = 0, cycles = 0;
+    double rr = 0;
+    srj_status result;
+    History hist;
+    hist.out = opts->history;
+    hist.cap = opts->history_cap;
+    srj_status st = solve_fields(p, opts->tol, opts->max_sweeps, &cur, &k, &cycles, &rr, &result,
+                                 opts->start_offset, opts->history ? &hist : nullptr);
+    if (st != SRJ_OK) return st;
+    opts->history_len = hist.len;
+    if (result != SRJ_EDIVERGED) HIPCHK(launch_copy_out(p->fmt, cur->origin, u, p->geo, p->stream));
+    return finish_info(p, info, k, cycles, rr, result);
 }
 
 srj_status srj_solve(srj_plan_t p, double* u, const double* f, double tol, int64_t max_sweeps,

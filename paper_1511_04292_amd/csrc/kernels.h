@@ -77,6 +77,10 @@ hipError_t launch_sweep_fused3d(Fmt f, const void* in, void* out, const void* b,
 // sum r^2 and max |r| of r = b64 - A u (binary64); zero_interior treats u's interior as 0.
 // partials must hold 2 * residual_blocks(g) doubles; result receives {sum, max}.
 int residual_blocks(const Geo& g);
+// One binary64 sweep u -> out with coefficient c fused with the residual norms of u: the
+// (sum r^2, max |r|) pair lands in result[0..1] as launch_residual would put it there.
+hipError_t launch_sweep_residual(const double* u, double* out, const double* b64, const Geo& g, double c,
+                                 double* partials, double* result, hipStream_t s);
 hipError_t launch_residual(Fmt f, const void* u, const double* b64, const Geo& g, int zero_interior,
                            double* partials, double* result, hipStream_t s);
 // IR: r = b64 - A u64 (binary64) written to rlo in format f, with its norms (as above).

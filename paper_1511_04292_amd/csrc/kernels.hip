@@ -304,6 +304,41 @@ __global__ __launch_bounds__(256) void k_residual_out(const double* __restrict__
     }
 }
 
+// One binary64 sweep that also yields the residual of the state it starts from: at every
+// interior point r = b - A u is formed as res_at forms it, which is the sweep's correction
+// term t bit for bit (same association, and the fused x - 4m of the blocked kernels is exact),
+// and the point is updated to u + c r (points under an operator's mask keep their value).  The
+// blocks cover the lines of k_residual in its order and its block reduction, so the partial
+// sums, and the norms k_reduce_final makes of them, equal those of a separate residual
+// evaluation: a cycle's check comes out of the cycle's first sweep (Sec. 2's stopping rule).
+__global__ __launch_bounds__(256) void k_sweep_residual(const double* __restrict__ u, double* __restrict__ o,
+                                                        const double* __restrict__ b64, Geo g, double c,
+                                                        double* __restrict__ partials)
+{
+    const int64_t lines = g.ny * (g.ndim == 3 ? g.nz : 1);
+    const int64_t pl = g.px * g.py;
+    double s = 0.0, m = 0.0;
+    const int64_t q0 = (int64_t)blockIdx.x * kResRows;
+    for (int64_t q = q0; q < min(q0 + kResRows, lines); ++q) {
+        const int i = (int)(q % g.ny) + 1;
+        const int k = (g.ndim == 3) ? (int)(q / g.ny) + 1 : 0;
+        const int64_t rowp = (int64_t)k * pl + (int64_t)i * g.px;
+        for (int j = threadIdx.x + 1; j <= g.nx; j += 256) {
+            const int64_t p = rowp + j;
+            const double r = res_at(u, b64, p, g.px, pl, g.ndim, i, j, k, g, false);
+            const double up = u[p];
+            o[p] = (g.op && g.mask && g.mask[p]) ? up : up + c * r;
+            s = s + r * r;
+            nanmax(m, fabs(r));
+        }
+    }
+    block_reduce(s, m);
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = s;
+        partials[2 * blockIdx.x + 1] = m;
+    }
+}
+
 // Deterministic final reduction: thread t folds partials t, t+256, ... in order.
 __global__ __launch_bounds__(256) void k_reduce_final(const double* __restrict__ partials, int n,
                                                       double* __restrict__ result)
@@ -474,6 +509,15 @@ hipError_t launch_residual(Fmt f, const void* u, const double* b64, const Geo& g
     int nb = residual_blocks(g);
     SRJ_DISPATCH(f, hipLaunchKernelGGL(k_residual<S>, dim3(nb), dim3(256), 0, s, (const S*)u, b64, g,
                                        zero_interior, partials));
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, s, partials, nb, result);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_residual(const double* u, double* out, const double* b64, const Geo& g, double c,
+                                 double* partials, double* result, hipStream_t s)
+{
+    const int nb = residual_blocks(g);
+    hipLaunchKernelGGL(k_sweep_residual, dim3(nb), dim3(256), 0, s, u, out, b64, g, c, partials);
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, s, partials, nb, result);
     return hipGetLastError();
 }

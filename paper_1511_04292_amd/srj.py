@@ -71,6 +71,12 @@ class _Info(ctypes.Structure):
                 ("seconds", ctypes.c_double), ("status", ctypes.c_int32)]
 
 
+class _SolveOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_sweeps", ctypes.c_int64), ("start_offset", ctypes.c_int64),
+                ("history", ctypes.POINTER(ctypes.c_double)), ("history_cap", ctypes.c_int64),
+                ("history_len", ctypes.c_int64)]
+
+
 class _Tune(ctypes.Structure):
     _fields_ = [("fused_sweeps", ctypes.c_int32), ("seg_rows", ctypes.c_int32), ("candidates", ctypes.c_int32),
                 ("us_per_sweep", ctypes.c_double), ("us_per_sweep_before", ctypes.c_double)]
@@ -82,7 +88,8 @@ EXPORTS = ["srj_plan", "srj_plan_destroy", "srj_plan_describe", "srj_plan_sequen
            "srj_plan_set_fusion", "srj_solve", "srj_sweeps", "srj_residual", "srj_solve_ir",
            "srj_schedule_optimal", "srj_schedule_order", "srj_status_string", "srj_last_error",
            "srj_adjoint", "srj_batch_plan", "srj_batch_solve", "srj_batch_destroy", "srj_plan_tune",
-           "srj_batch_tune", "srj_residual_static", "srj_schedule_counts", "srj_plan_operator"]
+           "srj_batch_tune", "srj_residual_static", "srj_schedule_counts", "srj_plan_operator", "srj_solve_ex",
+           "srj_plan_tune_cached", "srj_plan_poison"]
 
 
 def lib():
@@ -106,6 +113,7 @@ def lib():
     L.srj_plan_sequence.argtypes = [vp, ctypes.POINTER(i32), i64]
     L.srj_plan_set_fusion.argtypes = [vp, i32, i32]
     L.srj_solve.argtypes = [vp, vp, vp, dbl, i64, ctypes.POINTER(_Info)]
+    L.srj_solve_ex.argtypes = [vp, vp, vp, ctypes.POINTER(_SolveOpts), ctypes.POINTER(_Info)]
     L.srj_sweeps.argtypes = [vp, vp, vp, i64, i64, ctypes.POINTER(dbl)]
     L.srj_residual.argtypes = [vp, vp, vp, vp, ctypes.POINTER(dbl)]
     L.srj_solve_ir.argtypes = [vp, vp, vp, dbl, i32, i32, ctypes.POINTER(_Info)]
@@ -117,6 +125,8 @@ def lib():
     L.srj_batch_destroy.argtypes = [vp]
     L.srj_batch_destroy.restype = None
     L.srj_plan_tune.argtypes = [vp, ctypes.POINTER(_Tune)]
+    L.srj_plan_tune_cached.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(_Tune)]
+    L.srj_plan_poison.argtypes = [vp]
     L.srj_batch_tune.argtypes = [vp, ctypes.POINTER(_Tune)]
     L.srj_schedule_optimal.argtypes = [i32, dbl, dbl, ctypes.POINTER(dbl), ctypes.POINTER(dbl),
                                        ctypes.POINTER(i64), ctypes.POINTER(dbl)]
@@ -131,7 +141,8 @@ def lib():
     for name in ["srj_plan", "srj_plan_describe", "srj_plan_sequence", "srj_plan_set_fusion", "srj_solve",
                  "srj_sweeps", "srj_residual", "srj_solve_ir", "srj_schedule_optimal", "srj_schedule_order",
                  "srj_adjoint", "srj_batch_plan", "srj_batch_solve", "srj_plan_tune", "srj_batch_tune",
-                 "srj_residual_static", "srj_schedule_counts", "srj_plan_operator"]:
+                 "srj_residual_static", "srj_schedule_counts", "srj_plan_operator", "srj_solve_ex",
+                 "srj_plan_tune_cached", "srj_plan_poison"]:
         getattr(L, name).restype = i32
     _lib = L
     return L
@@ -288,6 +299,24 @@ def srj_solve(plan, u, f, tol, max_sweeps, raise_on_noconv=False):
                          int(max_sweeps), ctypes.byref(info))
     _check(st, (0, 5, 6) if not raise_on_noconv else (0,))
     return _info(info)
+
+
+def srj_solve_ex(plan, u, f, tol, max_sweeps, start_offset=0, history_cap=0):
+    """srj_solve resumed at step start_offset of a cycle and/or recording the relres of every
+    check (returned as info["history"], the first history_cap checks; info["checks"] counts
+    them all)."""
+    info = _Info()
+    hist = (ctypes.c_double * max(1, int(history_cap)))()
+    o = _SolveOpts(tol=float(tol), max_sweeps=int(max_sweeps), start_offset=int(start_offset),
+                   history=ctypes.cast(hist, ctypes.POINTER(ctypes.c_double)) if history_cap > 0 else None,
+                   history_cap=int(history_cap), history_len=0)
+    st = lib().srj_solve_ex(plan.handle, _dptr(u, plan.full_shape), _dptr(f, plan.full_shape), ctypes.byref(o),
+                            ctypes.byref(info))
+    _check(st, (0, 5, 6))
+    d = _info(info)
+    d["checks"] = int(o.history_len)
+    d["history"] = [hist[i] for i in range(min(int(o.history_len), int(history_cap)))]
+    return d
 
 
 def srj_sweeps(plan, u, f, k0, nsweeps):
@@ -451,6 +480,18 @@ def srj_plan_tune(plan):
     t = _Tune()
     _check(lib().srj_plan_tune(plan.handle, ctypes.byref(t)))
     return _tune_dict(t)
+
+
+def srj_plan_tune_cached(plan, path):
+    """srj_plan_tune through the on-disk cache at path (candidates = 0 on a cache hit)."""
+    t = _Tune()
+    _check(lib().srj_plan_tune_cached(plan.handle, os.fsencode(path), ctypes.byref(t)))
+    return _tune_dict(t)
+
+
+def srj_plan_poison(plan):
+    """Fill the plan's iterate, source and reduction buffers, padding included, with NaN bytes."""
+    _check(lib().srj_plan_poison(plan.handle))
 
 
 def srj_batch_tune(batch):

@@ -231,6 +231,43 @@ def test_solve_jacobi_matches_oracle():
         assert np.array_equal(host(ug), ref["u"])
 
 
+@pytest.mark.parametrize("case", ["srj2d_unfused", "jacobi2d_blocked", "jacobi3d_blocked", "srj3d_unfused"])
+def test_fused_cycle_check_matches_oracle(case):
+    """Binary64 plans that sweep one step per launch, and single-sweep cycles, take each
+    cycle's check from the cycle's first sweep: the stopping sweep, the relres and the
+    returned (checked, not advanced) state are the oracle's."""
+    rng = np.random.default_rng(23)
+    n = {"srj2d_unfused": (101, 70), "jacobi2d_blocked": (100, 70),
+         "jacobi3d_blocked": (12, 11, 10), "srj3d_unfused": (19, 13, 11)}[case]
+    h = 1.0 / (max(n) + 1)
+    full = tuple(x + 2 for x in reversed(n))
+    u0 = workloads.random_ring(full, rng)
+    f = rng.standard_normal(full)
+    if case.startswith("jacobi"):
+        w, q, seq, tol, fuse = [1.0], [1], [0], 1e-2, (10 if len(n) == 2 else 4)
+    else:
+        w, q, seq = oracle_schedule(3, n)
+        tol, fuse = 1e-10, 0
+    ref = sweeps.solve(u0, f, h, np.asarray(w)[seq], tol, 10 ** 6)
+    p = explicit_plan(n, h, w, q, seq, fuse=fuse)
+    assert srj.srj_plan_describe(p)["resident"] == 0
+    ug = dev(u0)
+    info = srj.srj_solve(p, ug, dev(f), tol, 10 ** 6)
+    assert info["status"] == ref["status"] == "ok"
+    assert info["sweeps"] == ref["sweeps"] > 0
+    assert abs(info["relres"] - ref["relres"]) <= 1e-12 * ref["relres"]
+    assert np.array_equal(host(ug), ref["u"])
+    # a sweep budget that ends inside the next cycle: the last checked state comes back
+    M = len(seq)
+    cap = max(ref["sweeps"] - M, 0) + (M - 1 if M > 1 else 0)
+    ref2 = sweeps.solve(u0, f, h, np.asarray(w)[seq], tol, cap)
+    ug2 = dev(u0)
+    info2 = srj.srj_solve(p, ug2, dev(f), tol, cap)
+    assert ref2["status"] == "noconv" and info2["status"] == "enoconv"
+    assert info2["sweeps"] == ref2["sweeps"]
+    assert np.array_equal(host(ug2), ref2["u"])
+
+
 @pytest.mark.parametrize("n,h", [((79, 79), None), ((1, 1), None), ((3, 200), None), ((61, 47), (1.0 / 62, 1.0 / 20))])
 def test_resident_small_solve_matches_oracle(n, h):
     """Grids up to 6656 points with the ring are solved in one workgroup with the grid in LDS:
