@@ -238,8 +238,9 @@ __global__ __launch_bounds__(256) void k_residual(const S* __restrict__ u, const
     const int64_t lines = g.ny * (g.ndim == 3 ? g.nz : 1);
     const int64_t pl = g.px * g.py;
     double s = 0.0, m = 0.0;
-    const int64_t q0 = (int64_t)blockIdx.x * kResRows;
-    for (int64_t q = q0; q < min(q0 + kResRows, lines); ++q) {
+    const int rpb = res_rows(lines);
+    const int64_t q0 = (int64_t)blockIdx.x * rpb;
+    for (int64_t q = q0; q < min(q0 + rpb, lines); ++q) {
         const int i = (int)(q % g.ny) + 1;
         const int k = (g.ndim == 3) ? (int)(q / g.ny) + 1 : 0;
         const int64_t rowp = (int64_t)k * pl + (int64_t)i * g.px;
@@ -265,8 +266,9 @@ __global__ __launch_bounds__(256) void k_residual_to_lo(const double* __restrict
     const int64_t lines = g.ny * (g.ndim == 3 ? g.nz : 1);
     const int64_t pl = g.px * g.py;
     double s = 0.0, m = 0.0;
-    const int64_t q0 = (int64_t)blockIdx.x * kResRows;
-    for (int64_t q = q0; q < min(q0 + kResRows, lines); ++q) {
+    const int rpb = res_rows(lines);
+    const int64_t q0 = (int64_t)blockIdx.x * rpb;
+    for (int64_t q = q0; q < min(q0 + rpb, lines); ++q) {
         const int i = (int)(q % g.ny) + 1;
         const int k = (g.ndim == 3) ? (int)(q / g.ny) + 1 : 0;
         const int64_t rowp = (int64_t)k * pl + (int64_t)i * g.px;
@@ -318,8 +320,9 @@ __global__ __launch_bounds__(256) void k_sweep_residual(const double* __restrict
     const int64_t lines = g.ny * (g.ndim == 3 ? g.nz : 1);
     const int64_t pl = g.px * g.py;
     double s = 0.0, m = 0.0;
-    const int64_t q0 = (int64_t)blockIdx.x * kResRows;
-    for (int64_t q = q0; q < min(q0 + kResRows, lines); ++q) {
+    const int rpb = res_rows(lines);
+    const int64_t q0 = (int64_t)blockIdx.x * rpb;
+    for (int64_t q = q0; q < min(q0 + rpb, lines); ++q) {
         const int i = (int)(q % g.ny) + 1;
         const int k = (g.ndim == 3) ? (int)(q / g.ny) + 1 : 0;
         const int64_t rowp = (int64_t)k * pl + (int64_t)i * g.px;
@@ -500,7 +503,8 @@ hipError_t launch_sweep_unfused(Fmt f, const void* in, void* out, const void* b,
 int residual_blocks(const Geo& g)
 {
     int64_t lines = g.ny * (g.ndim == 3 ? g.nz : 1);
-    return (int)((lines + kResRows - 1) / kResRows);
+    const int rpb = res_rows(lines);
+    return (int)((lines + rpb - 1) / rpb);
 }
 
 hipError_t launch_residual(Fmt f, const void* u, const double* b64, const Geo& g, int zero_interior,

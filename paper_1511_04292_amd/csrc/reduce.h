@@ -6,7 +6,17 @@
 
 namespace srj {
 
-constexpr int kResRows = 8;  // rows (2D) or (k, i) lines (3D) per residual block
+// Lines (rows in 2D, (k, i) lines in 3D) per residual block: as many blocks as fill the
+// device (about kResBlocks) while a block takes at most kResRowsMax lines, so that large
+// grids leave few partial sums.  Every kernel that reduces a residual uses this geometry,
+// which fixes the order of its sums.
+constexpr int kResRowsMax = 8;
+constexpr int64_t kResBlocks = 1024;
+__host__ __device__ inline int res_rows(int64_t lines)
+{
+    const int64_t r = lines / kResBlocks;
+    return (int)(r < 1 ? 1 : (r > kResRowsMax ? kResRowsMax : r));
+}
 
 // max that keeps a NaN once one is seen
 __device__ __forceinline__ void nanmax(double& m, double a)

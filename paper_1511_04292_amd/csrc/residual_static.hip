@@ -24,7 +24,7 @@ using namespace srj;
 
 namespace {
 
-// Residual blocks (kResRows lines each) the scratch holds: 2 (sum, max) pairs per block, one
+// Residual blocks (up to kResRowsMax lines each) the scratch holds: 2 (sum, max) pairs per block, one
 // for r and one for b~ (the residual of the zero interior).  65536 blocks = 524288 lines
 // (rows in 2D, (k, i) lines in 3D), 2 MiB.
 constexpr int kStaticBlocks = 65536;
@@ -76,7 +76,7 @@ __device__ __forceinline__ double res_dense(const double* u, const double* f, do
     return (s + hh * f[p]) - w.dg * ldz_d(u, p, zi);
 }
 
-// One block per kResRows lines: (sum r^2, max |r|) into part[0..2nb) and (sum b~^2, max |b~|)
+// One block per res_rows(lines) lines: (sum r^2, max |r|) into part[0..2nb) and (sum b~^2, max |b~|)
 // into part[2nb..4nb); r_out (may be null) receives r on the interior.
 __global__ __launch_bounds__(256) void k_residual_static(const double* __restrict__ u, const double* __restrict__ f,
                                                          double hh, Wts w, int ndim, int nx, int ny, int nz,
@@ -86,8 +86,9 @@ __global__ __launch_bounds__(256) void k_residual_static(const double* __restric
     const int64_t px = nx + 2, py = ny + 2, pl = px * py;
     const int64_t lines = (int64_t)ny * (ndim == 3 ? nz : 1);
     double s1 = 0.0, m1 = 0.0, s0 = 0.0, m0 = 0.0;
-    const int64_t q0 = (int64_t)blockIdx.x * kResRows;
-    for (int64_t q = q0; q < min(q0 + kResRows, lines); ++q) {
+    const int rpb = res_rows(lines);
+    const int64_t q0 = (int64_t)blockIdx.x * rpb;
+    for (int64_t q = q0; q < min(q0 + rpb, lines); ++q) {
         const int i = (int)(q % ny) + 1;
         const int k = (ndim == 3) ? (int)(q / ny) + 1 : 0;
         const int64_t rowp = (int64_t)k * pl + (int64_t)i * px;
@@ -162,10 +163,11 @@ extern "C" srj_status srj_residual_static(const srj_grid* grid, const double* u,
     }
     const int64_t nz = grid->ndim == 3 ? grid->n[2] : 1;
     const int64_t lines = grid->n[1] * nz;
-    const int64_t nb = (lines + kResRows - 1) / kResRows;
+    const int rpb = res_rows(lines);
+    const int64_t nb = (lines + rpb - 1) / rpb;
     if (nb > kStaticBlocks)
         return report(SRJ_EINVAL, "grid too large for the static scratch: at most " +
-                                      std::to_string((int64_t)kStaticBlocks * kResRows) +
+                                      std::to_string((int64_t)kStaticBlocks * kResRowsMax) +
                                       " lines (rows in 2D, n_y * n_z in 3D), got " + std::to_string(lines));
     double* part = nullptr;
     srj_status st = scratch_ptr(&part);
