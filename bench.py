@@ -32,6 +32,17 @@ B_PER_POINT_F64 = 24.0  # read u, read b, write u
 FUSED_SOURCES = ("sweep2d_tb.hip", "tb_core.h", "formats.h")
 
 
+OTHER_NAMES = ("small_2d_64", "case_study_585x280", "neumann_calibration_256", "grad_shafranov_300",
+               "smooth3d_512", "batch_1024", "adjoint_2048", "huge_2d_32768")
+
+
+def other_workloads():
+    """The other configurations measured in the same run, in the order they run."""
+    fns = (bench_small_2d, bench_case_study, bench_neumann_calibration, bench_grad_shafranov, bench_3d,
+           bench_batch, bench_adjoint, bench_huge_2d)
+    return list(zip(OTHER_NAMES, fns))
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
     for name in FUSED_SOURCES:
@@ -102,10 +113,12 @@ def summarize_trace(trace_dir):
     groups = {}
     for fn in glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True):
         for r in csv.DictReader(open(fn)):
-            key = (r["Kernel_Name"].split("(")[0].replace("void ", ""),
+            name = r["Kernel_Name"].replace("(anonymous namespace)::", "")
+            key = (name.split("(")[0].replace("void ", ""),
                    f'{r["Grid_Size_X"]}x{r["Grid_Size_Y"]}x{r["Grid_Size_Z"]}')
             groups.setdefault(key, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
     total = sum(sum(v) for v in groups.values())
+    timeline = batch_timeline(trace_dir)
     lines = ["| kernel | grid (threads) | calls | total ms | average us | min us | max us | % |",
              "|---|---|---|---|---|---|---|---|"]
     for (name, grid), v in sorted(groups.items(), key=lambda kv: -sum(kv[1])):
@@ -113,7 +126,46 @@ def summarize_trace(trace_dir):
             continue
         lines.append(f"| `{name}` | {grid} | {len(v)} | {sum(v) / 1e3:.2f} | {sum(v) / len(v):.2f} | "
                      f"{min(v):.1f} | {max(v):.1f} | {100 * sum(v) / total:.2f} |")
+    if timeline:
+        lines += ["", timeline]
     return "\n".join(lines)
+
+
+def batch_timeline(trace_dir):
+    """The batched solve's launches over time (the last run of k_batch_step launches without a
+    gap above 5 ms, i.e. the solve and not the tuner): how long launches take as problems
+    finish, and how much of the wall the gaps between launches are."""
+    import csv
+    import glob
+
+    ev = []
+    for fn in glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True):
+        for r in csv.DictReader(open(fn)):
+            if "k_batch_step" in r["Kernel_Name"]:
+                ev.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"])))
+    if not ev:
+        return ""
+    ev.sort()
+    i0 = 0
+    for i in range(1, len(ev)):
+        if ev[i][0] - ev[i - 1][1] > 5_000_000:
+            i0 = i
+    ev = ev[i0:]
+    t0 = ev[0][0]
+    span = (ev[-1][1] - t0) / 1e9
+    busy = sum(e - s for s, e in ev) / 1e9
+    out = [f"Batched solve: {len(ev)} launches in {span:.3f} s, {busy:.3f} s inside launches, "
+           f"{span - busy:.3f} s between them.", "",
+           "| from s | launches | mean launch us | share of the interval inside launches |", "|---|---|---|---|"]
+    step = 0.25
+    t = 0.0
+    while t < span:
+        sel = [(s, e) for s, e in ev if t <= (s - t0) / 1e9 < t + step]
+        if sel:
+            d = sum(e - s for s, e in sel) / len(sel) / 1e3
+            out.append(f"| {t:.2f} | {len(sel)} | {d:.1f} | {sum(e - s for s, e in sel) / 1e9 / step:.2f} |")
+        t += step
+    return "\n".join(out)
 
 
 def measured_traffic(kernel, workload):
@@ -210,6 +262,8 @@ def main():
                          "FETCH_SIZE / WRITE_SIZE, write profiles/traffic.json, print a table")
     ap.add_argument("--summarize-trace", metavar="TRACE_DIR",
                     help="print per-kernel, per-grid launch statistics of a rocprofv3 --kernel-trace run")
+    ap.add_argument("--only", choices=OTHER_NAMES, default=None,
+                    help="run one of the other workloads alone and print its JSON (profiling aid)")
     ap.add_argument("--kernel-only", action="store_true",
                     help="counter-collection run: one 1 GiB read / 1 GiB write calibration kernel, then "
                          "20 fused and 20 unfused sweep launches on the workload, 20 fused launches in "
@@ -231,6 +285,12 @@ def main():
     import torch
 
     from paper_1511_04292_amd import srj, workloads
+
+    if args.only:
+        fn = dict(other_workloads())[args.only]
+        print(f"bench: {args.only} ...", file=sys.stderr, flush=True)
+        print(json.dumps({"workload": args.only, "result": fn(torch, srj, workloads)}))
+        return
 
     n = args.n
     t0 = time.perf_counter()
@@ -377,11 +437,7 @@ def main():
         del plan, u, u0, f
         torch.cuda.empty_cache()
         other = {}
-        for name, fn in (("small_2d_64", bench_small_2d), ("case_study_585x280", bench_case_study),
-                         ("neumann_calibration_256", bench_neumann_calibration),
-                         ("grad_shafranov_300", bench_grad_shafranov),
-                         ("smooth3d_512", bench_3d), ("batch_1024", bench_batch),
-                         ("adjoint_2048", bench_adjoint), ("huge_2d_32768", bench_huge_2d)):
+        for name, fn in other_workloads():
             print(f"bench: {name} ...", file=sys.stderr, flush=True)
             other[name] = fn(torch, srj, workloads)
             torch.cuda.empty_cache()
