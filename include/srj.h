@@ -21,7 +21,8 @@
  * multiply-add, which is the same value since 4u is exact).  The residual r = b - A u
  * (A = dg I minus the weighted neighbour sum) is the t of that step;
  * relres = ||r||_2 / ||b~||_2, b~ being the residual of the state with a zero interior
- * (source plus boundary terms).  Plans with unequal spacings run one sweep per launch.
+ * (source plus boundary terms).  Plans with unequal spacings fuse sweeps only in 2D binary64
+ * (on tiles held in LDS, see srj_plan_set_fusion); otherwise they run one sweep per launch.
  *
  * Array layout at the ABI: dense, row-major, x fastest, ring included:
  *   2D: (n[1] + 2) rows of (n[0] + 2) doubles;  3D: (n[2]+2) x (n[1]+2) x (n[0]+2).
@@ -69,8 +70,9 @@ typedef struct {
                          Neumann on a cell-centred grid of n_i >= 2 cells per axis (Sec. 3.1,
                          Eq. Laplace; unit box: h_i = 1 / n_i): the ring is a row of ghost
                          cells mirroring their neighbours and is never read, a neighbour
-                         across the boundary being the cell itself.  Neumann plans are binary64
-                         and run one sweep per launch; the operator is singular (constants
+                         across the boundary being the cell itself.  Neumann plans are binary64;
+                         in 2D they fuse up to 8 sweeps per launch on tiles held in LDS, in
+                         3D they run one sweep per launch; the operator is singular (constants
                          solve A u = 0), so the source must have zero mean and srj_solve
                          measures relres against the initial residual ||r(u_0)|| (u_0
                          returned unchanged if that is 0).  The schedule's default
@@ -149,7 +151,9 @@ srj_status srj_plan_sequence(srj_plan_t plan, int32_t* seq, int64_t cap);
  * are solved by srj_solve in one launch of one workgroup holding the grid in LDS (resident = 1
  * in srj_plan_desc); srj_plan_set_fusion turns that off.
  * Override the number of sweeps fused per launch (0 = unfused reference kernel; at most
- * 10 in 2D, 5 in 3D; the default is the largest, except 4 for binary64 in 3D)
+ * 10 in 2D, 5 in 3D; the default is the largest, except 4 for binary64 in 3D; 2D binary64
+ * plans with unequal spacings, Neumann boundaries or an operator fuse at most 8, on tiles held
+ * in LDS, 8 by default; in 3D, and in binary32 / bfloat16, such plans sweep once per launch)
  * and the output rows each wave of the fused 2D kernel computes (seg_rows = 0, the
  * default: chosen per launch so that the grid of waves fills the device's resident wave
  * slots once, from the kernel's occupancy and the number of compute units).  The results
@@ -215,9 +219,10 @@ srj_status srj_residual(srj_plan_t plan, const double* u, const double* f, doubl
  * evaluated in that association; relres is the same Jacobi-scaled residual t measured against
  * t of the state whose free points are zero.  grid->h is ignored (the coefficients carry the
  * scaling), grid->dtype must be SRJ_F64 and grid->bc 0.  The schedule must be explicit or give
- * kappa_min or n_eff (the operator's spectrum is not known to the library).  Such plans run
- * one sweep per launch and serve srj_solve, srj_sweeps and srj_residual (norms of t); not
- * srj_solve_ir or srj_adjoint. */
+ * kappa_min or n_eff (the operator's spectrum is not known to the library).  In 2D such plans
+ * fuse up to 8 sweeps per launch on 32 x 32 tiles held in LDS with their weights and mask, in
+ * 3D they run one sweep per launch; they serve srj_solve, srj_sweeps and srj_residual (norms
+ * of t); not srj_solve_ir or srj_adjoint. */
 srj_status srj_plan_operator(const srj_grid* grid, const srj_schedule* schedule, const double* coef,
                              const uint8_t* mask, void* stream, srj_plan_t* out);
 
@@ -292,8 +297,9 @@ void srj_batch_destroy(srj_batch_t batch);
  * chosen; only their speed changes.  Synchronises the plan's stream; takes milliseconds
  * to about a second for the largest grids.
  *   srj_plan_tune: 2D plans time fusion depths {10, 8, 6, 4} x segment heights {automatic,
- *     24, 32, 48, 64, 96, 128}; 3D plans fusion depths {5, 4, 3, 2, 1, 0}.  Sets the plan's
- *     fusion (as srj_plan_set_fusion would).
+ *     24, 32, 48, 64, 96, 128}; 3D plans fusion depths {5, 4, 3, 2, 1, 0}; 2D binary64 plans
+ *     with unequal spacings, Neumann boundaries or an operator depths {8, 4, 2, 0}.  Sets the
+ *     plan's fusion (as srj_plan_set_fusion would).
  *   srj_batch_tune: times the batch's sweep launch with every problem sweeping, for
  *     largest tile heights {32, 64, 128, 256}, and keeps the fastest as the height the
  *     batch starts from (it still shortens tiles as problems finish). */

@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 SO = os.path.join(HERE, "libsrj.so")
-SOURCES = ["kernels.hip", "sweep2d_tb.hip", "sweep3d_tb.hip", "batch.hip", "residual_static.hip", "small_solve.hip",
+SOURCES = ["kernels.hip", "sweep2d_tb.hip", "sweep3d_tb.hip", "batch.hip", "residual_static.hip", "small_solve.hip", "sweep2d_lds.hip",
            "api.cpp",
            "batch_api.cpp", "planner.cpp"]
 ARCH = "gfx950"

@@ -156,6 +156,8 @@ struct srj_plan_s {
     int fuse = 8;
     int seg_rows = 0;  // output rows per wave in the fused 2D kernel (0: from the occupancy)
     bool resident = false;      // srj_solve runs in one workgroup with the grid in LDS
+    bool ldsfuse = false;       // fused sweeps run in the LDS-tiled kernel (2D binary64 plans
+                                // with unequal spacings, Neumann boundaries or an operator)
     double* cseq_d = nullptr;   // the cycle's coefficients on the device (resident solves)
     uint32_t fused_launches = 0;  // 2D launches so far: their parity alternates the stream direction
 
@@ -270,7 +272,9 @@ srj_status run_sweeps(srj_plan_t p, DField** cur, DField** nxt, const void* b, i
             int T = (int)std::min<int64_t>({(int64_t)p->fuse, end - k, to_cycle_end});
             Coefs co;
             for (int l = 0; l < T; ++l) co.c[l] = p->cseq[(k + l) % p->M];
-            if (p->geo.ndim == 2)
+            if (p->ldsfuse)
+                HIPCHK(launch_sweep_lds2d((*cur)->origin, (*nxt)->origin, b, p->geo, co, T, p->stream));
+            else if (p->geo.ndim == 2)
                 HIPCHK(launch_sweep_fused(p->fmt, (*cur)->origin, (*nxt)->origin, b, p->geo, co, T, p->seg_rows,
                                           (int)(p->fused_launches++ & 1u), p->stream));
             else
@@ -578,6 +582,11 @@ srj_status create_plan(const srj_grid* grid, const srj_schedule* schedule, void*
     p->fuse = (!p->iso || g.bc != 0) ? 0
                       : (g.ndim == 2) ? kMaxFuse
                                       : (fused3d_fits(g, p->fmt) ? (p->fmt == FMT_F64 ? kMaxFuse3d - 1 : kMaxFuse3d) : 0);
+    // 2D binary64 with unequal spacings, Neumann boundaries or an operator: up to 8 sweeps per
+    // launch on tiles held in LDS (the register-streamed kernels implement the equal-spacing
+    // Dirichlet operator only); in 3D these plans sweep once per launch
+    p->ldsfuse = (!p->iso || g.bc != 0 || g.op) && lds_fuse_fits(g, p->fmt);
+    if (p->ldsfuse) p->fuse = lds_fuse_max();
     // small binary64 2D grids: srj_solve keeps the grid in one compute unit's LDS
     if (p->fmt == FMT_F64 && small_solve_fits(g)) {
         if (hipMalloc(&p->cseq_d, sizeof(double) * (size_t)p->M) != hipSuccess ||
@@ -648,8 +657,13 @@ srj_status srj_plan_set_fusion(srj_plan_t p, int32_t fused, int32_t seg_rows)
     if (!p) return fail(SRJ_EINVAL, "null plan");
     if (fused < 0 || fused > kMaxFuse) return fail(SRJ_EINVAL, "fusion depth must be in [0, 10]");
     if (p->geo.ndim == 3 && fused > kMaxFuse3d) return fail(SRJ_EINVAL, "3D fusion depth must be in [0, 5]");
-    if (fused > 0 && !p->iso) return fail(SRJ_EINVAL, "fused sweeps need equal spacings on every axis");
-    if (fused > 0 && (p->geo.bc != 0 || p->geo.op)) return fail(SRJ_EINVAL, "fused sweeps need the Dirichlet Poisson operator");
+    if (fused > 0 && (!p->iso || p->geo.bc != 0 || p->geo.op)) {
+        if (!p->ldsfuse)
+            return fail(SRJ_EINVAL, "fused sweeps with unequal spacings, Neumann boundaries or an operator need a 2D "
+                                    "binary64 plan");
+        if (fused > lds_fuse_max())
+            return fail(SRJ_EINVAL, "at most 8 fused sweeps with unequal spacings, Neumann boundaries or an operator");
+    }
     if (p->geo.ndim == 3 && fused > 0 && !fused3d_fits(p->geo, p->fmt))
         return fail(SRJ_EINVAL, "z planes too large for the fused 3D kernel (1 GiB per plane at most)");
     if (seg_rows < 0 || seg_rows > (1 << 20)) return fail(SRJ_EINVAL, "segment rows must be in [0, 2^20]");
@@ -715,7 +729,10 @@ std::vector<Cand> tune_candidates(srj_plan_t p)
     std::vector<Cand> cands;
     cands.push_back({p->fuse, p->seg_rows});
     if (!p->iso || p->geo.bc != 0 || p->geo.op) {
-        // unequal spacings, Neumann boundaries, operators: the unfused kernel is the only one
+        // unequal spacings, Neumann boundaries, operators: the unfused kernel, and in 2D
+        // binary64 the LDS-tiled one
+        if (p->ldsfuse)
+            for (int T : {8, 4, 2, 0}) cands.push_back({T, 0});
     } else if (p->geo.ndim == 2) {
         for (int T : {10, 8, 6, 4})
             for (int H : {0, 24, 32, 48, 64, 96, 128}) cands.push_back({T, H});

@@ -65,6 +65,14 @@ hipError_t launch_sweep_unfused(Fmt f, const void* in, void* out, const void* b,
 // (The temporally blocked kernels implement the equal-spacing Dirichlet operator only.)
 hipError_t launch_sweep_fused(Fmt f, const void* in, void* out, const void* b, const Geo& g,
                               const Coefs& co, int T, int H, int flip, hipStream_t s);
+// T <= lds_fuse_max() (8) binary64 sweeps of a 2D grid with unequal spacings, Neumann
+// boundaries or a point-wise operator in one launch, on tiles held in LDS with T-wide halos
+// (sweep2d_lds.hip).  lds_fuse_fits: 2D binary64.
+int lds_fuse_max();
+bool lds_fuse_fits(const Geo& g, Fmt f);
+hipError_t launch_sweep_lds2d(const void* in, void* out, const void* b, const Geo& g, const Coefs& co, int T,
+                              hipStream_t s);
+
 // T <= kMaxFuse3d sweeps (coefficients co.c[0..T)) of a 3D grid in one launch: x-y tiles of
 // 64 x 32 with T-wide halos, streamed in z.  Needs fused3d_fits(g, f): a padded z plane
 // below 1 GiB (its stores are addressed within one plane).

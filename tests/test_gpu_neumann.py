@@ -46,15 +46,17 @@ def test_neumann_sweeps_bitwise(n, h):
     w, q, seq = sched(3, km)
     p = srj.srj_plan(n, hh, omega=w, q=q, sequence=seq, bc="neumann")
     d = srj.srj_plan_describe(p)
-    assert d["fused_sweeps"] == 0
+    assert d["fused_sweeps"] == (8 if nd == 2 else 0)  # 2D: tiles in LDS, 3D: unfused
     nsw = len(seq) + 5
-    ug = dev(u)
-    srj.srj_sweeps(p, ug, dev(f), 1, nsw)
     c = sweeps.coefficients(np.asarray(w)[seq], nd, wt)
     ref = NE.run(u, sweeps.rhs(f, hh), c, nsw, k0=1, wt=wt)
-    got = host(ug)
     inner = tuple(slice(1, -1) for _ in range(nd))
-    assert np.array_equal(got[inner], ref[inner])
+    for fuse in ((8, 5, 0) if nd == 2 else (0,)):
+        srj.srj_plan_set_fusion(p, fuse)
+        ug = dev(u)
+        srj.srj_sweeps(p, ug, dev(f), 1, nsw)
+        got = host(ug)
+        assert np.array_equal(got[inner], ref[inner]), fuse
     # residual norms and field
     r = torch.zeros_like(ug)
     nr = srj.srj_residual(p, dev(u), dev(f), r)
@@ -106,6 +108,6 @@ def test_neumann_jacobi_and_refusals():
     with pytest.raises(srj.SrjError):
         srj.srj_plan((N, N), 1.0 / N, omega=[1.0], q=[1], bc="neumann", dtype="f32")
     with pytest.raises(srj.SrjError):
-        srj.srj_plan_set_fusion(p, 4)
+        srj.srj_plan_set_fusion(p, 9)
     with pytest.raises(srj.SrjError):
         srj.srj_solve_ir(p, dev(u0), dev(f), 1e-8, 1, 10)

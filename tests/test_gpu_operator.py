@@ -48,20 +48,23 @@ def test_operator_sweeps_and_residual_bitwise(n, masked):
     w, q, seq = sched(3, 0.01)
     p = srj.srj_plan_operator(n, dev(coef), dev(mask, torch.uint8) if masked else None, omega=w, q=q,
                               sequence=seq, kappa_min=0.01)
-    assert srj.srj_plan_describe(p)["fused_sweeps"] == 0
-    ug = dev(u)
+    nd = len(n)
+    assert srj.srj_plan_describe(p)["fused_sweeps"] == (8 if nd == 2 else 0)  # 2D: tiles in LDS
     nsw = len(seq) + 4
-    srj.srj_sweeps(p, ug, dev(f), 2, nsw)
     wts, bs = OP.scale(coef, f)
     ref = OP.run(u, wts, bs, np.asarray(w)[seq], nsw, k0=2, mask=mask)
-    assert np.array_equal(ug.cpu().numpy(), ref)
+    for fuse in ((8, 3, 0) if nd == 2 else (0,)):
+        srj.srj_plan_set_fusion(p, fuse)
+        ug = dev(u)
+        srj.srj_sweeps(p, ug, dev(f), 2, nsw)
+        assert np.array_equal(ug.cpu().numpy(), ref), fuse
     r = torch.zeros_like(ug)
     nr = srj.srj_residual(p, dev(u), dev(f), r)
     t, t2, tmax = OP.residual(u, wts, bs, mask)
     assert np.array_equal(r.cpu().numpy(), t)
     assert math.isclose(nr["l2"], math.sqrt(t2), rel_tol=1e-12) and nr["linf"] == tmax
     with pytest.raises(srj.SrjError):
-        srj.srj_plan_set_fusion(p, 2)
+        srj.srj_plan_set_fusion(p, 9 if nd == 2 else 2)
     with pytest.raises(srj.SrjError):
         srj.srj_solve_ir(p, dev(u), dev(f), 1e-8, 1, 5)
 

@@ -52,9 +52,11 @@ def test_weighted_sweeps_bitwise(n, fmt):
     km = S.kappa_min_dirichlet(n, h)
     w, q, seq = sched(3, km)
     p = srj.srj_plan(n, h, omega=w, q=q, sequence=seq, dtype=fmt)
-    assert srj.srj_plan_describe(p)["fused_sweeps"] == 0
+    # 2D binary64: up to 8 sweeps per launch on tiles in LDS (the default); otherwise unfused
+    lds = nd == 2 and fmt == "f64"
+    assert srj.srj_plan_describe(p)["fused_sweeps"] == (8 if lds else 0)
     with pytest.raises(srj.SrjError):
-        srj.srj_plan_set_fusion(p, 2)
+        srj.srj_plan_set_fusion(p, 9 if lds else 2)
     nsw = len(seq) + 3
     ug = dev(u)
     srj.srj_sweeps(p, ug, dev(f), 2, nsw)
@@ -63,6 +65,11 @@ def test_weighted_sweeps_bitwise(n, fmt):
     if fmt == "f64":
         ref = sweeps.run(u, b, sweeps.coefficients(np.asarray(w)[seq], nd, wt), nsw, k0=2, wt=wt)
         assert np.array_equal(host(ug), ref)
+        for fuse in ((3, 0) if lds else ()):
+            srj.srj_plan_set_fusion(p, fuse)
+            ug = dev(u)
+            srj.srj_sweeps(p, ug, dev(f), 2, nsw)
+            assert np.array_equal(host(ug), ref), fuse
     else:
         c32 = sweeps.lo_coefficients(np.asarray(w)[seq], nd, fmt, wt)
         x = sweeps.lo_cast(u, fmt)
