@@ -7,7 +7,8 @@ compared bit for bit with the oracle run on the whole grid -- on the oracle's sc
 on the schedules the product planner builds for the benchmark.  The full 4096^2 and 512^3
 binary64 solves must stop at the cycle the exact DST-mode trajectory predicts, with the
 relres it predicts; the 512^3 results of all three precisions are compared with the exact
-discrete solution.
+discrete solution.  At 32768^2 (the throughput point) sampled regions of a window are
+compared with the oracle run on crops around them.
 """
 import numpy as np
 import pytest
@@ -221,3 +222,37 @@ def test_adjoint_2048_central_differences():
             fd = (float(loss(f + eps * vft, g + eps * vgt)) - float(loss(f - eps * vft, g - eps * vgt))) / (2 * eps)
         an = float((f.grad * vft).sum() + (g.grad * vgt).sum())
         assert abs(fd - an) <= 1e-5 * abs(an), (fd, an)
+
+
+def test_32768_window_sampled_bitwise():
+    """32768^2 binary64, the product-planned P = 10 schedule and the default launch shape that
+    bench.py times (10 sweeps per launch, automatic segment height): 14 sweeps from 4 before a
+    cycle end.  After s sweeps a point depends only on points within s of it, so the oracle run
+    on a crop with an s-point border (held fixed) gives the crop's inner points exactly; regions
+    at the corners, on strip and segment boundaries of the fused kernel and in the middle are
+    compared bit for bit."""
+    n = 32768
+    wl = workloads.blobs_2d_device(n, seed=0, device=DEV)
+    u0, f = wl["u0"], wl["f"]
+    plan = srj.srj_plan(wl["n"], wl["h"], P=10)
+    d = srj.srj_plan_describe(plan)
+    assert d["fused_sweeps"] == 10
+    seq = srj.srj_plan_sequence(plan)
+    M = int(d["M"])
+    k0, nsw = M - 4, 14
+    u = u0.clone()
+    srj.srj_sweeps(plan, u, f, k0, nsw)
+    torch.cuda.synchronize()
+    c = sweeps.coefficients(np.asarray(d["omega"])[seq], 2)
+    R, B = nsw, 48
+    # region origins (row, column) of the interior; strips are 108 columns wide at 10 levels
+    origins = [(1, 1), (n - B + 1, n - B + 1), (1, n - B + 1), (n // 2, 108 * 151 - 20),
+               (4096 - 20, 108 * 7 - 30), (12345, 23456)]
+    for (y, x) in origins:
+        ya, yb = max(y - R, 0), min(y + B + R, n + 2)
+        xa, xb = max(x - R, 0), min(x + B + R, n + 2)
+        cu = u0[ya:yb, xa:xb].cpu().numpy()
+        cf = f[ya:yb, xa:xb].cpu().numpy()
+        ref = sweeps.run(cu, sweeps.rhs(cf, wl["h"]), c, nsw, k0=k0)
+        got = u[y:y + B, x:x + B].cpu().numpy()
+        assert np.array_equal(got, ref[y - ya:y - ya + B, x - xa:x - xa + B]), (y, x)
