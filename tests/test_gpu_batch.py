@@ -100,3 +100,39 @@ def test_batch_with_planner_schedules_converges():
     info = srj.srj_solve_ir(p0, u, torch.from_numpy(wl["f"]).to(DEV), 1e-10, 1, 1000)
     assert info["cycles"] == infos[0]["cycles"]
     assert torch.equal(u, us[0])
+
+
+def test_batch_full_configuration():
+    """The benchmark's batch: 1024 problems, N log-uniform in [32, 1024], P in 3..8 planned by
+    the library, binary32 sweeps in binary64 refinement to 1e-10, one cycle per outer step.
+    Every returned state's binary64 residual, recomputed by the oracle on the host, meets the
+    tolerance and equals the reported relres; the first 40 problems with N <= 64 equal the
+    oracle's refinement on the same schedules bit for bit."""
+    import math
+
+    N, P = workloads.batch_sizes(count=1024)
+    wls = [workloads.batch_problem(int(nn), seed=10000 + j) for j, nn in enumerate(N)]
+    probs = [dict(n=wl["n"], h=wl["h"], P=int(pp)) for wl, pp in zip(wls, P)]
+    b = srj.srj_batch_plan(probs, dtype="f32")
+    us = [torch.from_numpy(wl["u0"]).to(DEV) for wl in wls]
+    fs = [torch.from_numpy(wl["f"]).to(DEV) for wl in wls]
+    infos, secs = srj.srj_batch_solve(b, us, fs, 1e-10, 1, 2000)
+    torch.cuda.synchronize()
+    assert all(i["status"] == "ok" for i in infos)
+    checked = 0
+    for j, wl in enumerate(wls):
+        u = us[j].cpu().numpy()
+        bb = sweeps.rhs(wl["f"], wl["h"])
+        r2, _ = sweeps.residual_norms(u, bb)
+        rr = math.sqrt(r2) / math.sqrt(sweeps.source_norm2(u, bb))
+        assert rr <= 1e-10 and abs(rr - infos[j]["relres"]) <= 1e-12 * rr, (j, int(N[j]), rr, infos[j])
+        if N[j] <= 64 and checked < 40:
+            # the schedule the batch built: a single-grid plan of the same request builds it too
+            p = srj.srj_plan(wl["n"], wl["h"], P=int(P[j]))
+            d = srj.srj_plan_describe(p)
+            seq = srj.srj_plan_sequence(p)
+            ref = sweeps.solve_ir(wl["u0"], wl["f"], wl["h"], np.asarray(d["omega"])[seq], 1e-10, 1, 2000, "f32")
+            assert ref["status"] == "ok" and infos[j]["cycles"] == ref["outer"], (j, infos[j], ref["outer"])
+            assert np.array_equal(u, ref["u"]), (j, int(N[j]))
+            checked += 1
+    assert checked == 40
