@@ -352,9 +352,9 @@ def order_balanced(w, q, km, kM=KAPPA_M, G=4096):
     among weights with uses left, the one minimising max_kappa |(s + L_i) - k T / M|,
     where s is the sum of the L of the steps already taken (ties to the larger weight).
     The partial products of the cycle then stay close to the straight path from 1 to the
-    full cycle factor in every mode.  Parity unpinned: an ordering is an engineering
-    choice the paper leaves open; what is pinned is that it is a permutation with the
-    right counts and that the full cycle factor does not depend on it.
+    full cycle factor in every mode.  The ordering is an engineering choice the paper leaves
+    open; pinned by a three-level example worked by hand on a two-point grid, and by being a
+    permutation with the right counts whose full cycle factor does not depend on the order.
     """
     grid = balanced_grid(km, kM, G)
     P = len(w)

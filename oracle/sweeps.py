@@ -286,7 +286,10 @@ def solve_ir(u0, f, h, omega_sequence, tol, inner_cycles, max_outer, fmt):
     A d = r approximately by ``inner_cycles`` SRJ cycles from d = 0 with a zero ring,
     in binary32 arithmetic on ``fmt`` storage (r cast to that storage first), then
     u += d in FP64.  ``fmt`` 'f64' runs the same loop with binary64 inner sweeps.
-    Parity unpinned beyond the FP64 residual it reports.
+    Pinned by: with one binary64 cycle per outer step it is the plain iteration (same stop,
+    iterates equal to rounding); with binary32 each outer step contracts ||r|| by the exact
+    cycle factor's maximum (Eq. cycleAmplFact) up to rounding; both storage formats end within
+    the conditioning bound of the exact discrete solution.
     """
     u = _c64(u0).copy()
     b = rhs(f, h)

@@ -213,6 +213,46 @@ def test_ir_reaches_tolerance_in_both_formats():
         assert np.max(np.abs(res["u"] - us)) <= 1e-7 * np.max(np.abs(us))
 
 
+def _ir_case(n, P):
+    w = workloads.small_2d(n, seed=3)
+    km = schedule.kappa_min_dirichlet([n, n])
+    opt = schedule.optimal(P, km)
+    q = schedule.q_floor(opt["beta"])
+    seq = schedule.weight_sequence(opt["w"], schedule.order_balanced(opt["w"], q, km))
+    return w, opt, q, seq
+
+
+@pytest.mark.parametrize("n,P", [(31, 3), (40, 5)])
+def test_ir_f64_one_cycle_is_the_plain_iteration(n, P):
+    """Refinement with one binary64 cycle per outer step is, in exact arithmetic, the plain
+    SRJ iteration cycle by cycle (the error goes e -> G e either way, G the cycle's
+    propagation matrix of Sec. 2): same stopping cycle, iterates equal to rounding."""
+    w, opt, q, seq = _ir_case(n, P)
+    M = len(seq)
+    ref = sweeps.solve(w["u0"], w["f"], w["h"], seq, 1e-10, 10 ** 6, history=True)
+    ir = sweeps.solve_ir(w["u0"], w["f"], w["h"], seq, 1e-10, 1, 10 ** 4, "f64")
+    assert ref["status"] == ir["status"] == "ok"
+    assert ir["outer"] == ref["sweeps"] // M and ir["sweeps"] == ref["sweeps"]
+    assert np.max(np.abs(ir["u"] - ref["u"])) <= 1e-13 * np.max(np.abs(ref["u"]))
+    hr, hi = np.array(ref["history"]), np.array(ir["history"])
+    big = hr > 1e-7  # above the residual's rounding floor
+    np.testing.assert_allclose(hi[big], hr[big], rtol=1e-6)
+
+
+@pytest.mark.parametrize("n,P", [(31, 3), (40, 5)])
+def test_ir_f32_outer_steps_contract_by_the_cycle_factor(n, P):
+    """Each outer step with one binary32 cycle reduces ||r||_2 by at most the cycle's exact
+    contraction max over the grid's symbols of |prod (1 - w_i kappa)^q_i| (Eq.
+    cycleAmplFact; the cycle operator is symmetric, so this is its 2-norm), up to binary32
+    rounding (slack 1e-3)."""
+    w, opt, q, seq = _ir_case(n, P)
+    gmax = spectral.cycle_amplification(opt["w"], q, (n, n))
+    r = sweeps.solve_ir(w["u0"], w["f"], w["h"], seq, 1e-10, 1, 10 ** 4, "f32")
+    assert r["status"] == "ok"
+    h = np.array(r["history"])
+    assert np.all(h[1:] <= (gmax + 1e-3) * h[:-1]), (gmax, (h[1:] / h[:-1]).max())
+
+
 def test_modal_prediction_with_large_schedule():
     # P = 10 scheme: single powers (1 - w kappa)^q overflow, the cycle factor must not;
     # two full cycles of the oracle's sweeps follow the exact modal relres
