@@ -768,11 +768,27 @@ def bench_adjoint(torch, srj, workloads, n=2048, levels=9, tol=1e-10):
     loss.backward()
     torch.cuda.synchronize()
     t2 = time.perf_counter()
+    fi, bi = u.grad_fn.info, u.grad_fn.backward_info
+    pts = n * n
+
+    fuse = int(tuned["fused_sweeps"])
+
+    def rates(info):
+        # effective per-sweep bytes: 24 B per point per sweep (above the HBM peak through the
+        # fusion of sweeps); per launch (fused sweeps sharing one pass) a rate above the HBM
+        # peak would mean the 101 MB working set is served from the 256 MB memory-side cache
+        gbs = B_PER_POINT_F64 * pts * info["sweeps"] / info["seconds"] / 1e9
+        per_launch = gbs / max(fuse, 1)
+        return {"sweeps": int(info["sweeps"]), "device_s": round(info["seconds"], 4),
+                "GLUP_s": round(pts * info["sweeps"] / info["seconds"] / 1e9, 1),
+                "effective_per_sweep_GBs": round(gbs, 1), "per_launch_GBs": round(per_launch, 1),
+                "per_launch_above_hbm_peak": per_launch > HBM_PEAK_GBS}
+
     return {"workload": f"2D {n}^2, f blobs and U(-1,1) ring as parameters, L = 1/2 ||u - u_target||^2, "
                         f"SRJ P={levels} forward to {tol:g}, adjoint to 1e-9 (binary64 floor of a smooth "
                         f"right-hand side is about 2e-10 here)",
             "forward_s": round(t1 - t0, 4), "backward_s": round(t2 - t1, 4), "launch_tuning": tuned,
-            "loss": float(loss.detach())}
+            "forward": rates(fi), "backward": rates(bi), "loss": float(loss.detach())}
 
 
 if __name__ == "__main__":

@@ -36,6 +36,7 @@ class SRJSolve(torch.autograd.Function):
         info = srj.srj_adjoint(ctx.plan, grad_u, ctx.tol, ctx.max_sweeps, df, dg)
         if info["status"] != "ok":
             raise srj.SrjError(5 if info["status"] == "enoconv" else 6, f"adjoint solve: {info}")
+        ctx.backward_info = info  # readable as u.grad_fn.backward_info after backward()
         return df, dg, None, None, None, None
 
 
