@@ -473,3 +473,45 @@ def test_errors():
     assert e.value.status == 1
     srj.srj_plan_set_fusion(p3, 0)
     assert srj.srj_plan_describe(p3)["fused_sweeps"] == 0
+
+
+def test_nan_source_diverges_on_every_path():
+    """A NaN in the source makes every solve path report SRJ_EDIVERGED at its first check:
+    the blocked 2D kernel, one sweep per launch (check fused into the cycle's first sweep),
+    the LDS-tiled kernels (unequal spacings, Neumann, operator), 3D, and the batch, where only
+    the problem holding the NaN fails."""
+    n = (90, 80)
+    rng = np.random.default_rng(5)
+    full = (n[1] + 2, n[0] + 2)
+    u0 = np.zeros(full)
+    f = rng.standard_normal(full)
+    f[40, 33] = np.nan
+    plans = []
+    p = srj.srj_plan(n, 1.0 / 91, P=3)
+    plans.append(("blocked", p))
+    p = srj.srj_plan(n, 1.0 / 91, P=3)
+    srj.srj_plan_set_fusion(p, 0)
+    plans.append(("one sweep per launch", p))
+    plans.append(("lds spacing", srj.srj_plan(n, (1.0 / 91, 0.5 / 81), P=3)))
+    plans.append(("lds neumann", srj.srj_plan(n, 1.0 / 90, P=3, bc="neumann")))
+    coef = np.zeros((5,) + full)
+    coef[1:] = 1.0
+    coef[0] = 4.5
+    plans.append(("lds operator", srj.srj_plan_operator(n, dev(coef), None, P=3, kappa_min=0.01)))
+    for name, p in plans:
+        info = srj.srj_solve(p, dev(u0), dev(f), 1e-10, 10 ** 5)
+        assert info["status"] == "ediverged", (name, info)
+    n3 = (20, 18, 16)
+    f3 = rng.standard_normal((18, 20, 22))
+    f3[5, 6, 7] = np.nan
+    p3 = srj.srj_plan(n3, 1.0 / 21, P=3)
+    info = srj.srj_solve(p3, dev(np.zeros_like(f3)), dev(f3), 1e-10, 10 ** 5)
+    assert info["status"] == "ediverged"
+    probs = [dict(n=(40, 40), h=1.0 / 41, P=3), dict(n=(50, 45), h=1.0 / 51, P=3)]
+    fa = rng.standard_normal((42, 42))
+    fb = rng.standard_normal((47, 52))
+    fb[10, 10] = np.nan
+    b = srj.srj_batch_plan(probs, dtype="f32")
+    infos, _ = srj.srj_batch_solve(b, [dev(np.zeros((42, 42))), dev(np.zeros((47, 52)))], [dev(fa), dev(fb)],
+                                   1e-10, 1, 200)
+    assert infos[0]["status"] == "ok" and infos[1]["status"] == "ediverged"
