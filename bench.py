@@ -32,14 +32,14 @@ B_PER_POINT_F64 = 24.0  # read u, read b, write u
 FUSED_SOURCES = ("sweep2d_tb.hip", "tb_core.h", "formats.h")
 
 
-OTHER_NAMES = ("small_2d_64", "case_study_585x280", "neumann_calibration_256", "grad_shafranov_300",
-               "smooth3d_512", "batch_1024", "adjoint_2048", "huge_2d_32768")
+OTHER_NAMES = ("small_2d_64", "case_study_585x280", "neumann_calibration_256", "planner_variants",
+               "grad_shafranov_300", "smooth3d_512", "batch_1024", "adjoint_2048", "huge_2d_32768")
 
 
 def other_workloads():
     """The other configurations measured in the same run, in the order they run."""
-    fns = (bench_small_2d, bench_case_study, bench_neumann_calibration, bench_grad_shafranov, bench_3d,
-           bench_batch, bench_adjoint, bench_huge_2d)
+    fns = (bench_small_2d, bench_case_study, bench_neumann_calibration, bench_planner_variants,
+           bench_grad_shafranov, bench_3d, bench_batch, bench_adjoint, bench_huge_2d)
     return list(zip(OTHER_NAMES, fns))
 
 
@@ -649,6 +649,58 @@ def bench_neumann_calibration(torch, srj, workloads, n=256, tol=1e-10):
         del plan
     for P in (2, 3, 4, 5):
         out[f"srj_P{P}"]["measured_acceleration"] = round(out["jacobi"]["sweeps"] / out[f"srj_P{P}"]["sweeps"], 3)
+    return out
+
+
+def bench_planner_variants(torch, srj, workloads, tol=1e-10):
+    """The planner variants of Sec. 4.3 measured on the device.
+    (1) Integer conversions of beta / beta_1 in Fig. 4's setting: P = 6 for N = 256 on the
+    Neumann model problem (Eq. Laplace, 256^2 cells, random start U(-1,1)), solved to relres
+    1e-10: sweeps, and the cycle factor's maximum over the grid's symbols, per conversion
+    (floor, nearest, ceiling, best per level); a conversion whose factor reaches 1 is refused.
+    (2) The two step orders' rounding floors: binary32 and bfloat16 storage (plain SRJ, no
+    refinement), 255^2 Dirichlet, zero ring, f ~ N(0,1), P = 8: the lowest relres of 40
+    cycles' checks for the balanced and the even order."""
+    import numpy as np
+
+    out = {"workload": "Sec. 4.3 variants: q conversions at P = 6, N = 256 (Neumann, 256^2 cells, "
+                       "relres 1e-10); balanced / even step orders' floors in binary32 / bfloat16 "
+                       "(255^2 Dirichlet, P = 8, 40 cycles)"}
+    n = 256
+    rng = np.random.default_rng(0)
+    u0 = torch.from_numpy(rng.uniform(-1.0, 1.0, (n + 2, n + 2))).to("cuda:0")
+    f = torch.zeros_like(u0)
+    conv = {}
+    for mode, name in ((0, "floor"), (1, "nearest"), (2, "ceiling"), (3, "best")):
+        try:
+            plan = srj.srj_plan((n, n), 1.0 / n, P=6, n_eff=float(n), bc="neumann", q_rounding=mode)
+        except srj.SrjError as e:
+            conv[name] = {"refused": str(e)}
+            continue
+        d = srj.srj_plan_describe(plan)
+        u = u0.clone()
+        info = srj.srj_solve(plan, u, f, tol, 10 ** 7)
+        conv[name] = {"q": [int(x) for x in d["q"]], "M": int(d["M"]), "sweeps": int(info["sweeps"]),
+                      "status": info["status"], "gamma_q_max": d["gamma_q_max"],
+                      "seconds": round(info["seconds"], 4)}
+        del plan
+    out["q_conversion_P6_N256"] = conv
+    m = 255
+    wl = workloads.batch_problem(m, seed=7)
+    u0 = torch.from_numpy(wl["u0"]).to("cuda:0")
+    f = torch.from_numpy(wl["f"]).to("cuda:0")
+    floors = {}
+    for fmt in ("f32", "bf16"):
+        for ordering, oname in ((0, "balanced"), (1, "even")):
+            plan = srj.srj_plan(wl["n"], wl["h"], P=8, dtype=fmt, ordering=ordering)
+            M = int(srj.srj_plan_describe(plan)["M"])
+            u = u0.clone()
+            info = srj.srj_solve_ex(plan, u, f, 0.0, 40 * M, history_cap=64)
+            h = [x for x in info["history"] if x == x]
+            floors[f"{fmt}_{oname}"] = {"floor_relres": min(h) if h else None, "final_relres": info["relres"],
+                                        "status": info["status"], "checks": info["checks"]}
+            del plan
+    out["order_floors_P8_255"] = floors
     return out
 
 
