@@ -33,13 +33,14 @@ FUSED_SOURCES = ("sweep2d_tb.hip", "tb_core.h", "formats.h")
 
 
 OTHER_NAMES = ("small_2d_64", "case_study_585x280", "neumann_calibration_256", "planner_variants",
-               "grad_shafranov_300", "smooth3d_512", "batch_1024", "adjoint_2048", "huge_2d_32768")
+               "grad_shafranov_300", "spherical_poisson_512", "smooth3d_512", "batch_1024", "adjoint_2048",
+               "huge_2d_32768")
 
 
 def other_workloads():
     """The other configurations measured in the same run, in the order they run."""
     fns = (bench_small_2d, bench_case_study, bench_neumann_calibration, bench_planner_variants,
-           bench_grad_shafranov, bench_3d, bench_batch, bench_adjoint, bench_huge_2d)
+           bench_grad_shafranov, bench_spherical_poisson, bench_3d, bench_batch, bench_adjoint, bench_huge_2d)
     return list(zip(OTHER_NAMES, fns))
 
 
@@ -701,6 +702,38 @@ def bench_planner_variants(torch, srj, workloads, tol=1e-10):
                                         "status": info["status"], "checks": info["checks"]}
             del plan
     out["order_floors_P8_255"] = floors
+    return out
+
+
+def bench_spherical_poisson(torch, srj, workloads, N=512, tol=1e-10):
+    """Sec. 5.2: the Poisson equation in spherical coordinates, axisymmetric, multiplied by r^2
+    (a variable-coefficient operator given point by point), N x N cells, solved with the
+    Neumann-row schemes for N at P = 6 and P = 15 (the paper's smallest and largest) to relres
+    1e-10, from a zero start (ab initio) and from the exact solution with 1/N relative noise
+    (the paper's realistic calculation); error against the series solution."""
+    import numpy as np
+
+    out = {"workload": f"Sec. 5.2 spherical Poisson, axisymmetric, {N} x {N} cells, r^2-scaled operator, "
+                       f"Neumann-row schemes for N = {N}, relres {tol:g}"}
+    inner = (slice(1, -1), slice(1, -1))
+    for start in ("zero", "realistic"):
+        wl = workloads.spherical_poisson_2d(N, start=start, seed=0)
+        coef = torch.from_numpy(wl["coef"]).to("cuda:0")
+        f = torch.from_numpy(wl["f"]).to("cuda:0")
+        for P in (6, 15):
+            plan = srj.srj_plan_operator(wl["n"], coef, None, P=P, n_eff=float(N))
+            d = srj.srj_plan_describe(plan)
+            u = torch.from_numpy(wl["u0"]).to("cuda:0")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = srj.srj_solve(plan, u, f, tol, 10 ** 7)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            err = float(np.max(np.abs(u.cpu().numpy() - wl["u_exact"])[inner]))
+            out[f"{start}_P{P}"] = {"sweeps": int(info["sweeps"]), "seconds": round(dt, 4), "M": int(d["M"]),
+                                    "relres": info["relres"], "status": info["status"],
+                                    "fused_sweeps": int(d["fused_sweeps"]), "max_err_vs_series": err}
+            del plan
     return out
 
 

@@ -5,7 +5,7 @@ The operator is given per point: (A u)_P = a_P u_P - sum over the 2d neighbours 
 with coef = [a_P, a_W, a_E, a_S, a_N (, a_D, a_U)] arrays of the full-grid shape (W/E along x,
 the last array axis; S/N along y; D/U along z).  The equation is A u = f at every interior
 point whose mask is 0; masked points and the ring hold fixed (Dirichlet) values, which lets the
-iteration run "only inside the region using a mask" (Sec. 5.3, test B).
+iteration run inside a region of any shape (Sec. 5.3, test B).
 
 Jacobi scaling, one IEEE division per coefficient: w_nb = a_nb / a_P, bs = f / a_P.  One step
 with weight omega (Eq. 2nd-order_CD for this operator):

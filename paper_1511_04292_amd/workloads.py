@@ -250,3 +250,100 @@ def grad_shafranov(n=298, C=0.0, test="A"):
         out["mask"] = mask
     out["u0"] = u0
     return out
+
+
+def _sph_first_zero(l):
+    """First positive zero of the spherical Bessel function j_l (bracketed scan, then brentq)."""
+    from scipy.optimize import brentq
+    from scipy.special import spherical_jn
+
+    x = max(1.0, float(l))
+    step = 0.05
+    f0 = spherical_jn(l, x)
+    while True:
+        x1 = x + step
+        f1 = spherical_jn(l, x1)
+        if f0 == 0.0:
+            return x
+        if f0 * f1 < 0.0:
+            return brentq(lambda t: spherical_jn(l, t), x, x1, xtol=1e-15, rtol=1e-15, maxiter=200)
+        x, f0 = x1, f1
+
+
+def spherical_series(r, theta, terms=30):
+    """Sec. 5.2's axisymmetric test (m_max = 0, n_max -> infinity): the source
+    s = -sum_n a_2n k_2n^2 j_2n(k_2n r) Y_2n^0(theta) for r <= 1 (0 outside) and the solution
+    u = sum_n (a_2n j_2n(k_2n r) + b_2n r^2n) Y_2n^0 for r <= 1, sum_n b_2n r^-(2n+1) Y_2n^0 for
+    r > 1, with a_l = 2^-l, k_l the first zero of j_l, b_l = -a_l/(2l+1) (l j_l(k_l) - k_l
+    j_(l+1)(k_l)) and Y_l^0 = sqrt((2l+1)/(4 pi)) P_l(cos theta).  The terms fall as 4^-n: the
+    sum stops at 30 terms, far below binary64 resolution.  Returns (s, u) on the broadcast of
+    r and theta."""
+    from scipy.special import eval_legendre, spherical_jn
+
+    r = np.asarray(r, dtype=np.float64)
+    theta = np.asarray(theta, dtype=np.float64)
+    s = np.zeros(np.broadcast(r, theta).shape)
+    u = np.zeros_like(s)
+    inside = r <= 1.0
+    for nn in range(terms):
+        l = 2 * nn
+        a = 2.0 ** (-l)
+        k = _sph_first_zero(l)
+        b = -a / (2 * l + 1) * (l * spherical_jn(l, k) - k * spherical_jn(l + 1, k))
+        Y = math.sqrt((2 * l + 1) / (4.0 * math.pi)) * eval_legendre(l, np.cos(theta))
+        jr = spherical_jn(l, k * np.where(inside, r, 1.0))
+        s = s + np.where(inside, -a * k * k * jr, 0.0) * Y
+        u = u + np.where(inside, a * jr + b * r ** l, b * np.where(inside, 1.0, r) ** (-(l + 1))) * Y
+    return s, u
+
+
+def spherical_poisson_2d(N, start="zero", seed=0):
+    """Sec. 5.2's Poisson equation in spherical coordinates, axisymmetric (r, theta) on
+    [0, 1] x [0, pi] with N x N cells, multiplied by r^2 and discretised by second-order central
+    differences on the staggered grid r_i = (i - 1/2)/N, theta_j = (j - 1/2) pi / N
+    (x, the fastest axis, is r; y is theta):
+        r^2 (u_E - 2u + u_W)/dr^2 + r (u_E - u_W)/dr + (u_N - 2u + u_S)/dth^2
+        + cot(theta) (u_N - u_S)/(2 dth) = r^2 s,
+    written as A u = f with A = -(that operator), f = -r^2 s: a_W = r (r - dr)/dr^2,
+    a_E = r (r + dr)/dr^2, a_S = 1/dth^2 - cot/(2 dth), a_N = 1/dth^2 + cot/(2 dth),
+    a_P = 2 r^2/dr^2 + 2/dth^2.  Boundaries: at the centre u_0 = u_1 = u_2, so the unknowns in
+    r are i = 2..N and the first one's diagonal takes a_W in (a_P - a_W, a_W = 0); at theta = 0
+    and pi a ghost cell mirrors its neighbour (a_P - a_S resp. a_P - a_N); at r_(N+1) =
+    1 + dr/2 the ring holds the exact exterior solution.  Interior: (N - 1) x N points.
+    start: "zero" (the paper's ab initio calculation) or "realistic": the exact solution times
+    (1 + U(-1/2, 1/2)/N) per point, seeded.  Returns n, coef (5, N+2, N+1), u0, f, r, theta,
+    u_exact (on the full grid) and h (dr, dth)."""
+    dr, dth = 1.0 / N, math.pi / N
+    ri = (np.arange(1, N + 2) - 0.5) * dr          # x = 0 .. N  <->  i = 1 .. N+1
+    tj = (np.arange(0, N + 2) - 0.5) * dth         # y = 0 .. N+1 <->  j = 0 .. N+1
+    R, TH = np.meshgrid(ri, tj, indexing="xy")
+    my, mx = N + 2, N + 1
+    with np.errstate(divide="ignore", invalid="ignore"):
+        cot = np.cos(TH) / np.sin(TH)
+    coef = np.zeros((5, my, mx))
+    coef[1] = R * (R - dr) / (dr * dr)
+    coef[2] = R * (R + dr) / (dr * dr)
+    coef[3] = 1.0 / (dth * dth) - cot / (2.0 * dth)
+    coef[4] = 1.0 / (dth * dth) + cot / (2.0 * dth)
+    coef[0] = 2.0 * R * R / (dr * dr) + 2.0 / (dth * dth)
+    # folds: centre (x = 1 is i = 2: u_1 = u_2), axis ghosts at theta = 0 (y = 1) and pi (y = N)
+    coef[0, :, 1] -= coef[1, :, 1]
+    coef[1, :, 1] = 0.0
+    coef[0, 1, :] -= coef[3, 1, :]
+    coef[3, 1, :] = 0.0
+    coef[0, N, :] -= coef[4, N, :]
+    coef[4, N, :] = 0.0
+    ring = np.ones((my, mx), bool)
+    ring[1:-1, 1:-1] = False
+    coef[:, ring] = 0.0
+    coef[0, ring] = 1.0
+    s_src, u_ex = spherical_series(R, TH)
+    f = np.where(ring, 0.0, -(R * R) * s_src)
+    u0 = np.zeros((my, mx))
+    u0[1:-1, -1] = u_ex[1:-1, -1]  # r_(N+1) = 1 + dr/2: the exterior solution
+    if start == "realistic":
+        rng = np.random.default_rng(seed)
+        u0[1:-1, 1:-1] = u_ex[1:-1, 1:-1] * (1.0 + rng.uniform(-0.5, 0.5, (N, N - 1)) / N)
+    elif start != "zero":
+        raise ValueError("start is 'zero' or 'realistic'")
+    return dict(n=(N - 1, N), coef=coef, u0=u0, f=f, r=ri, theta=tj, u_exact=u_ex, h=(dr, dth))

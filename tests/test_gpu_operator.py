@@ -104,3 +104,29 @@ def test_operator_plan_refusals():
         srj.srj_plan_operator(n, dev(coef), None, P=3)
     with pytest.raises(TypeError):
         srj.srj_plan_operator(n, dev(coef[:4]), None, P=3, kappa_min=0.01)
+
+
+@pytest.mark.parametrize("start", ["zero", "realistic"])
+def test_spherical_poisson_solves_bitwise(start):
+    """Sec. 5.2's Poisson equation in spherical coordinates (axisymmetric, r^2-scaled, 48 x 48
+    cells) from a zero start and from the paper's warm start (the exact solution with 1/N
+    relative noise): the GPU stops where the oracle does with the same iterate, within the
+    discretisation error of the series solution; the warm start needs fewer sweeps."""
+    N = 48
+    wl = workloads.spherical_poisson_2d(N, start=start, seed=4)
+    km = S.kappa_min_neumann(N)
+    w, q, seq = sched(6, km)
+    ref = OP.solve(wl["u0"], wl["f"], wl["coef"], np.asarray(w)[seq], 1e-10, 10 ** 6)
+    p = srj.srj_plan_operator(wl["n"], dev(wl["coef"]), None, omega=w, q=q, sequence=seq, n_eff=N)
+    ug = dev(wl["u0"])
+    info = srj.srj_solve(p, ug, dev(wl["f"]), 1e-10, 10 ** 6)
+    assert ref["status"] == "ok" and info["status"] == "ok"
+    assert info["sweeps"] == ref["sweeps"]
+    got = ug.cpu().numpy()
+    assert np.array_equal(got, ref["u"])
+    inner = (slice(1, -1), slice(1, -1))
+    assert np.max(np.abs(got - wl["u_exact"])[inner]) < 1.5 * 0.00252 * (16 / N) ** 2
+    if start == "realistic":
+        cold = OP.solve(workloads.spherical_poisson_2d(N)["u0"], wl["f"], wl["coef"], np.asarray(w)[seq], 1e-10,
+                        10 ** 6)
+        assert info["sweeps"] < cold["sweeps"]

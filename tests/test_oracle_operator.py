@@ -101,3 +101,27 @@ def test_grad_shafranov_test_a_dipole():
     x = scipy.sparse.linalg.spsolve(A.tocsc(), rhs)
     err = float(np.max(np.abs(x - wl["u_exact"][free])))
     assert 5e-5 < err < 9.0 / 300 ** 2, err
+
+
+def test_spherical_poisson_discretisation_is_second_order():
+    """Sec. 5.2's axisymmetric Poisson test: the discrete system (centre folded, axis ghosts,
+    exact exterior data at r = 1 + dr/2), solved directly, approaches the series solution at
+    second order, and its Jacobi-scaled operator is diagonally dominant (Jacobi symbols in
+    [0, 2])."""
+    import scipy.sparse.linalg as spla
+
+    errs = []
+    for N in (16, 32, 64):
+        wl = workloads.spherical_poisson_2d(N)
+        c = wl["coef"]
+        inner = (slice(1, -1), slice(1, -1))
+        assert np.all(c[0][inner] + 1e-12 * c[0][inner] >= c[1][inner] + c[2][inner] + c[3][inner] + c[4][inner])
+        assert np.all(c[1:][(slice(None),) + inner] >= 0)
+        A, rhs, free = OP.dense_system_sparse(c, wl["f"], wl["u0"])
+        u = wl["u0"].copy()
+        u[free] = spla.spsolve(A.tocsr(), rhs)
+        errs.append(np.max(np.abs(u - wl["u_exact"])[inner]))
+    assert 3.8 < errs[0] / errs[1] < 4.2 and 3.8 < errs[1] / errs[2] < 4.2, errs
+    # the series solution is continuous at r = 1 and its source vanishes there
+    s, u = workloads.spherical_series(np.array([1.0 - 1e-9, 1.0 + 1e-9]), np.array([0.4, 0.4]))
+    assert abs(u[0] - u[1]) < 1e-8 and abs(s[0]) < 1e-7
