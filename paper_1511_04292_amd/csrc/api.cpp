@@ -576,9 +576,10 @@ srj_status create_plan(const srj_grid* grid, const srj_schedule* schedule, void*
         destroy(p);
         return fail(SRJ_EHIP, "initial fill failed");
     }
-    // 3D: 5 sweeps per launch for the 4- and 2-byte formats, 4 for binary64 (at 5 its
-    // registers spill and the launch is slower per sweep); unequal spacings: one sweep per
-    // launch (the temporally blocked kernels implement the equal-spacing operator only)
+    // 2D: 10 sweeps per launch; 3D: 5 for the 4- and 2-byte formats, 4 for binary64 (at 5 its
+    // registers spill and the launch is slower per sweep); unequal spacings and Neumann
+    // boundaries: the register-streamed kernels implement the equal-spacing Dirichlet
+    // operator only
     p->fuse = (!p->iso || g.bc != 0) ? 0
                       : (g.ndim == 2) ? kMaxFuse
                                       : (fused3d_fits(g, p->fmt) ? (p->fmt == FMT_F64 ? kMaxFuse3d - 1 : kMaxFuse3d) : 0);

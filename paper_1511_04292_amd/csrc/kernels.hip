@@ -8,13 +8,17 @@
 // -ffp-contract=off), so every kernel below -- unfused or temporally blocked -- produces
 // bit-identical iterates for the same sweep sequence.  wy, wz and dg are the weights of a
 // box whose axes have different spacings (Geo); with equal spacings they are 1, 1 and 2d,
-// every product by them is exact, and the temporally blocked kernels, which implement that
-// case only, give the same bits.  Storage formats: binary64,
+// every product by them is exact, and the register-streamed temporally blocked kernels,
+// which implement that case only, give the same bits.  Storage formats: binary64,
 // binary32, and bfloat16 (binary32 arithmetic, round-to-nearest-even on every store).
 //
 // The sweep is bound by HBM bandwidth (0.3 flop per byte unfused), so no kernel uses the
-// matrix cores.  This file holds the unfused sweeps, data movement, residual reductions
-// and refinement helpers; the temporally blocked 2D sweep is in sweep2d_tb.hip.
+// matrix cores.  This file holds the one-sweep kernels (with the sweep that also forms the
+// residual of its input), data movement, residual reductions, operator set-up and refinement
+// helpers.  Elsewhere: the temporally blocked sweeps (sweep2d_tb.hip, sweep3d_tb.hip, and
+// sweep2d_lds.hip for unequal spacings, Neumann boundaries and operators), the whole small
+// solve in LDS (small_solve.hip), the batch (batch.hip) and the allocation-free residual
+// (residual_static.hip).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
