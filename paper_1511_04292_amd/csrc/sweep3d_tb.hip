@@ -38,21 +38,18 @@ template <int T> struct Coefs3T {
     double c[T];
 };
 
-constexpr int k3Waves = 16;                 // waves per block
-constexpr int k3Rows = 2;                   // rows per wave
-constexpr int k3TileY = k3Waves * k3Rows;   // tile rows
-constexpr int k3Threads = 64 * k3Waves;
+constexpr int k3Rows = 2;  // rows per wave; a block of NW waves covers NW * k3Rows tile rows
 
-template <class S, int T, int D>
-__global__ __launch_bounds__(k3Threads) void k_sweep3d_tb(const S* __restrict__ uin, S* __restrict__ uout,
+template <class S, int T, int D, int NW>
+__global__ __launch_bounds__(64 * NW) void k_sweep3d_tb(const S* __restrict__ uin, S* __restrict__ uout,
                                                     const S* __restrict__ bb, int64_t px, int64_t py, int nx,
                                                     int ny, int nz, Coefs3T<T> co, int Tact, int ntx, int nty,
                                                     int ntz, int zs)
 {
     using Cm = typename Tr<S>::C;
     constexpr int SX = 64 - 2 * T;        // output columns per tile
-    constexpr int SY = k3TileY - 2 * T;   // output rows per tile
-    __shared__ Cm xch[2][T][k3Waves][2][64];
+    constexpr int SY = (NW * k3Rows) - 2 * T;   // output rows per tile
+    __shared__ Cm xch[2][T][NW][2][64];
 
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -76,7 +73,7 @@ __global__ __launch_bounds__(k3Threads) void k_sweep3d_tb(const S* __restrict__ 
         const int trow = w * k3Rows + r;
         yr[r] = 1 + ty * SY - T + trow;
         updy[r] = yr[r] >= 1 && yr[r] <= ny;
-        outy[r] = updy[r] && trow >= T && trow < k3TileY - T;
+        outy[r] = updy[r] && trow >= T && trow < (NW * k3Rows) - T;
         const int64_t yc = yr[r] < 0 ? 0 : (yr[r] > ny + 1 ? ny + 1 : yr[r]);
         colp[r] = yc * px + xcl;
     }
@@ -114,7 +111,7 @@ __global__ __launch_bounds__(k3Threads) void k_sweep3d_tb(const S* __restrict__ 
 #pragma unroll
     for (int s = 0; s < D; ++s) load_plane(kb + s, U[s], B[s]);
 
-    const int wu = max(w - 1, 0), wd = min(w + 1, k3Waves - 1);
+    const int wu = max(w - 1, 0), wd = min(w + 1, NW - 1);
     // K steps per loop iteration, K a multiple of D (the load slots), 2 (the two older planes
     // per level) and T (the delay line of b): every register then plays the same role at both
     // ends of the loop body and the back edge needs no copies.  The last iteration may run up
@@ -191,12 +188,13 @@ __global__ __launch_bounds__(k3Threads) void k_sweep3d_tb(const S* __restrict__ 
     }
 }
 
-template <class S, int T, int D>
+template <class S, int T, int D, int NW>
 static int tb3_resident_blocks()
 {
     static const int blocks = [] {
         int nb = 0, dev = 0, ncu = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep3d_tb<S, T, D>, k3Threads, 0) != hipSuccess) nb = 1;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep3d_tb<S, T, D, NW>, 64 * NW, 0) != hipSuccess)
+            nb = 1;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
             ncu = 1;
@@ -205,23 +203,41 @@ static int tb3_resident_blocks()
     return blocks;
 }
 
-template <class S, int T, int D>
-static void tb3d(const S* in, S* out, const S* b, const Geo& g, const Coefs& co, int Tact, hipStream_t s)
+template <class S, int T, int D, int NW>
+static void tb3d_launch(const S* in, S* out, const S* b, const Geo& g, const Coefs3T<T>& ct, int Tact, hipStream_t s)
 {
-    constexpr int SX = 64 - 2 * T, SY = k3TileY - 2 * T;
-    Coefs3T<T> ct;
-    for (int l = 0; l < T; ++l) ct.c[l] = l < Tact ? co.c[l] : 0.0;
+    constexpr int SX = 64 - 2 * T, SY = NW * k3Rows - 2 * T;
     const int ntx = (int)((g.nx + SX - 1) / SX);
     const int nty = (int)((g.ny + SY - 1) / SY);
     // z runs: as many as fill the resident block slots once (at least one), balanced
-    int ntz = std::max(1, tb3_resident_blocks<S, T, D>() / (ntx * nty));
+    int ntz = std::max(1, tb3_resident_blocks<S, T, D, NW>() / (ntx * nty));
     int zs = (int)((g.nz + ntz - 1) / ntz);
     zs = std::max(1, std::min(zs, (int)g.nz));
     ntz = (int)((g.nz + zs - 1) / zs);
     zs = (int)((g.nz + ntz - 1) / ntz);
     const int nblk = (ntx * nty * ntz + 7) / 8 * 8;
-    hipLaunchKernelGGL((k_sweep3d_tb<S, T, D>), dim3(nblk), dim3(k3Threads), 0, s, in, out, b, g.px, g.py, (int)g.nx,
+    hipLaunchKernelGGL((k_sweep3d_tb<S, T, D, NW>), dim3(nblk), dim3(64 * NW), 0, s, in, out, b, g.px, g.py, (int)g.nx,
                        (int)g.ny, (int)g.nz, ct, Tact, ntx, nty, ntz, zs);
+}
+
+// Tiles of 16 waves (32 rows) by default; 15 waves (30 rows) when that fills more of the
+// resident block slots in one round without needing a second (512^2 planes at T = 4: 240
+// tiles instead of 220 for 256 compute units), each tile then doing 6% less work.
+template <class S, int T, int D>
+static void tb3d(const S* in, S* out, const S* b, const Geo& g, const Coefs& co, int Tact, hipStream_t s)
+{
+    Coefs3T<T> ct;
+    for (int l = 0; l < T; ++l) ct.c[l] = l < Tact ? co.c[l] : 0.0;
+    auto tiles = [&](int nw) {
+        const int64_t SX = 64 - 2 * T, SY = nw * k3Rows - 2 * T;
+        return ((g.nx + SX - 1) / SX) * ((g.ny + SY - 1) / SY);
+    };
+    const int64_t t16 = tiles(16), t15 = tiles(15);
+    const int64_t slots = tb3_resident_blocks<S, T, D, 16>();
+    if (t16 < slots && t15 > t16 && t15 <= slots && 15 * k3Rows > 2 * T + 8)
+        tb3d_launch<S, T, D, 15>(in, out, b, g, ct, Tact, s);
+    else
+        tb3d_launch<S, T, D, 16>(in, out, b, g, ct, Tact, s);
 }
 
 template <class S, int D>
