@@ -314,18 +314,21 @@ srj_status srj_plan_tune(srj_plan_t plan, srj_tune_info* info);
 srj_status srj_batch_tune(srj_batch_t batch, srj_tune_info* info);
 /* srj_plan_tune through an on-disk cache (a text file at path, created if missing, one line
  * per tuned configuration).  The key is the device (architecture name and compute-unit
- * count), ndim, n, the storage format, the boundary kind, equal or unequal spacings and
- * operator plans.  On a hit the stored launch shape is applied without timing anything
+ * count), ndim, n, the storage format, the boundary kind, equal or unequal spacings,
+ * operator plans and the cycle length M (launches end at cycle ends).  On a hit the stored launch shape is applied without timing anything
  * (info->candidates = 0, both times = the stored time); on a miss the plan is tuned and a
  * line is appended.  Entries that the plan could not run are ignored.  SRJ_EINVAL for a
  * null path, SRJ_EHIP if the file cannot be written after tuning (the plan is tuned
  * anyway). */
 srj_status srj_plan_tune_cached(srj_plan_t plan, const char* path, srj_tune_info* info);
 
-/* Debugging aid: fill every device buffer the plan owns, padding and alignment slack
- * included, with all-one bytes (a NaN in binary64, binary32 and bfloat16).  Later calls
- * write the points they use before reading them, so a kernel that read outside its
- * stencil's points would turn results into NaN; results must stay bit-identical. */
+/* Debugging aid: fill the plan's working buffers (the iterate pair, the right-hand sides in
+ * the sweep format and in binary64, the refinement iterate and the reduction partials),
+ * padding and alignment slack included, with all-one bytes (a NaN in binary64, binary32 and
+ * bfloat16).  Later calls write the points they use before reading them, so a kernel that
+ * read outside its stencil's points would turn results into NaN; results must stay
+ * bit-identical.  What the plan was built from stays: the schedule's coefficients and an
+ * operator plan's weights and mask.  Not for graph capture (it clears with memset). */
 srj_status srj_plan_poison(srj_plan_t plan);
 
 /* Host-only schedule computations (no device needed). */

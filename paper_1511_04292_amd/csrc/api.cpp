@@ -310,8 +310,6 @@ void fill_info(srj_solve_info* info, int64_t sweeps, int64_t cycles, double relr
     info->status = (int32_t)st;
 }
 
-// Solve on the plan's fields: A and B hold the initial state (ring included), blo/b64 the
-// scaled source.  On return *cur points at the field with the returned state.
 // Where a solve records the relres of its checks (host memory, first cap entries kept).
 struct History {
     double* out = nullptr;
@@ -324,6 +322,8 @@ struct History {
     }
 };
 
+// Solve on the plan's fields: A and B hold the initial state (ring included), blo/b64 the
+// scaled source.  On return *cur points at the field with the returned state.
 // k0 (0 <= k0 < M): the state in A/B is the iterate after k0 sweeps of a cycle; the solve
 // completes that cycle before its first check.  hist (may be null) receives every check.
 srj_status solve_fields(srj_plan_t p, double tol, int64_t max_sweeps, DField** cur, int64_t* k_out,
@@ -745,7 +745,8 @@ std::vector<Cand> tune_candidates(srj_plan_t p)
     return cands;
 }
 
-// Cache key of a plan's tuning: device, grid, format, boundary kind, spacing kind, operator.
+// Cache key of a plan's tuning: device, grid, format, boundary kind, spacing kind, operator,
+// and the cycle length M (launches end at cycle ends, so M shapes the launches timed).
 srj_status tune_key(srj_plan_t p, std::string* key)
 {
     int dev = 0;
@@ -759,11 +760,11 @@ srj_status tune_key(srj_plan_t p, std::string* key)
     *key = arch + " " + std::to_string(prop.multiProcessorCount) + " " + std::to_string(p->geo.ndim) + " " +
            std::to_string(p->geo.nx) + " " + std::to_string(p->geo.ny) + " " + std::to_string(p->geo.nz) + " " +
            std::to_string((int)p->fmt) + " " + std::to_string(p->geo.bc) + " " + std::to_string(p->iso ? 1 : 0) +
-           " " + std::to_string(p->geo.op ? 1 : 0);
+           " " + std::to_string(p->geo.op ? 1 : 0) + " " + std::to_string(p->M);
     return SRJ_OK;
 }
 
-constexpr const char* kTuneTag = "srj-tune-v1";
+constexpr const char* kTuneTag = "srj-tune-v2";
 
 }  // namespace
 

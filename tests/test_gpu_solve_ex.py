@@ -118,7 +118,7 @@ def test_tune_cache_roundtrip(tmp_path):
     t1 = srj.srj_plan_tune_cached(a, path)
     assert t1["candidates"] > 0
     lines = open(path).read().splitlines()
-    assert len(lines) == 1 and lines[0].startswith("srj-tune-v1 ")
+    assert len(lines) == 1 and lines[0].startswith("srj-tune-v2 ")
     b = srj.srj_plan(n, 1.0 / 701, P=6)
     t2 = srj.srj_plan_tune_cached(b, path)
     assert t2["candidates"] == 0
@@ -128,9 +128,10 @@ def test_tune_cache_roundtrip(tmp_path):
     # another grid misses and appends; a line naming a shape the plan cannot run is skipped
     c = srj.srj_plan((300, 200), 1.0 / 301, P=5)
     with open(path, "a") as fp:
-        key = lines[0].split()[1:11]
+        key = lines[0].split()[1:12]
         key[3:5] = ["300", "200"]
-        fp.write("srj-tune-v1 " + " ".join(key) + " 7 5 1.0\n")
+        key[10] = str(srj.srj_plan_describe(c)["M"])
+        fp.write("srj-tune-v2 " + " ".join(key) + " 7 5 1.0\n")
         fp.write("garbage line\n")
     t3 = srj.srj_plan_tune_cached(c, path)
     assert t3["candidates"] > 0 and t3["fused_sweeps"] != 7
