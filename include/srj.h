@@ -177,7 +177,7 @@ typedef struct {
                                sweeps and checks at that cycle end */
     double* history;        /* host array or NULL: relres of every check, in order */
     int64_t history_cap;    /* entries history holds (the first history_cap checks are kept) */
-    int64_t history_len;    /* out: checks made (can exceed history_cap) */
+    int64_t history_len;    /* out: checks made (can exceed history_cap); 0 if history is NULL */
 } srj_solve_opts;
 
 /* srj_solve with a start offset and a record of the residual at every check (the history

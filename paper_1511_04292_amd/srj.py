@@ -304,7 +304,7 @@ def srj_solve(plan, u, f, tol, max_sweeps, raise_on_noconv=False):
 def srj_solve_ex(plan, u, f, tol, max_sweeps, start_offset=0, history_cap=0):
     """srj_solve resumed at step start_offset of a cycle and/or recording the relres of every
     check (returned as info["history"], the first history_cap checks; info["checks"] counts
-    them all)."""
+    them all when history_cap > 0, and is 0 otherwise)."""
     info = _Info()
     hist = (ctypes.c_double * max(1, int(history_cap)))()
     o = _SolveOpts(tol=float(tol), max_sweeps=int(max_sweeps), start_offset=int(start_offset),
