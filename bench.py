@@ -838,6 +838,17 @@ def bench_adjoint(torch, srj, workloads, n=2048, levels=9, tol=1e-10):
     """Differentiable solve on 2048^2: forward SRJ and the adjoint SRJ backward."""
     from paper_1511_04292_amd.autograd import srj_solve_diff
 
+    # untimed warm-up of the same forward and backward on a 64^2 copy of the workload: the
+    # first backward of a process starts torch's autograd device thread and loads the kernels
+    # of the loss and its gradient, tens of milliseconds that are no part of the solve
+    ws = workloads.adjoint_2d(64)
+    fs = torch.from_numpy(ws["f"]).to("cuda:0").requires_grad_(True)
+    gs = torch.from_numpy(ws["g"]).to("cuda:0").requires_grad_(True)
+    us = srj_solve_diff(fs, gs, srj.srj_plan((64, 64), ws["h"], P=3), tol=tol, tol_backward=1e-9)
+    (0.5 * ((us - torch.from_numpy(ws["u_target"]).to("cuda:0"))[1:-1, 1:-1] ** 2).sum()).backward()
+    torch.cuda.synchronize()
+    del ws, fs, gs, us
+
     wl = workloads.adjoint_2d(n)
     f = torch.from_numpy(wl["f"]).to("cuda:0").requires_grad_(True)
     g = torch.from_numpy(wl["g"]).to("cuda:0").requires_grad_(True)
