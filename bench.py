@@ -279,8 +279,8 @@ def main():
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: the SRJ solver here runs on a single MI355X; "
-              "multi-GPU runs are not part of this build.", file=sys.stderr)
+        print("bench.py measures one GPU only: the SRJ solver runs on a single MI355X and has no "
+              "multi-GPU path.", file=sys.stderr)
         sys.exit(2)
 
     import torch
