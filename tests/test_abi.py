@@ -45,6 +45,28 @@ def test_library_shares_torchs_hip_runtime():
     assert out.stdout.strip().splitlines()[-1] == "1", out.stdout
 
 
+def test_missing_library_fails_loudly(monkeypatch):
+    """Without the built library every entry point raises: there is no fallback path."""
+    monkeypatch.setattr(srj, "_lib", None)
+    monkeypatch.setattr(srj, "SO", os.path.join(ROOT, "no_such_dir", "libsrj.so"))
+    with pytest.raises(ImportError, match="not built"):
+        srj.lib()
+    with pytest.raises(ImportError, match="not built"):
+        srj.srj_plan((8, 8), 1.0 / 9, P=2)
+
+
+def test_package_never_reaches_the_oracle():
+    """The product package imports nothing from the oracle (test infrastructure only)."""
+    pkg = os.path.dirname(os.path.abspath(srj.__file__))
+    for dirpath, _, files in os.walk(pkg):
+        for name in files:
+            if not name.endswith((".py", ".cpp", ".hip", ".h")):
+                continue
+            text = open(os.path.join(dirpath, name)).read()
+            assert not re.search(r"^\s*(from|import)\s+oracle\b", text, flags=re.M), name
+            assert "srj_oracle" not in text, name
+
+
 def test_status_strings():
     L = srj.lib()
     assert L.srj_status_string(0) == b"ok"
