@@ -50,9 +50,16 @@ __device__ __forceinline__ int vcopy(int x)
 typedef unsigned int tb_u32x2 __attribute__((ext_vector_type(2)));
 constexpr int kTbMasked = 0x40000000;  // offset added for a masked row; the record count stays below it
 
+// Binary64 stores carry the non-temporal hint (cache-policy bit nt): the fused binary64
+// launches write a field that the next launch reads only after the rest of the grid has
+// streamed through, and measured faster with it (4096^2 at 10 sweeps 87.7 against 89.0 us,
+// 512^3 at 4 sweeps 921 against 944 us).  The 4- and 2-byte formats, whose 2D working sets
+// stay in the memory-side cache, measured 3-6% slower with it and store plainly.
+constexpr int kTbStoreNt = 2;
+
 __device__ __forceinline__ void tb_store(double v, __amdgpu_buffer_rsrc_t r, int off)
 {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(tb_u32x2, v), r, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(tb_u32x2, v), r, off, 0, kTbStoreNt);
 }
 __device__ __forceinline__ void tb_store(float v, __amdgpu_buffer_rsrc_t r, int off)
 {
