@@ -378,7 +378,8 @@ def main():
     avg_launch = sec / launches
     bytes_launch = B_PER_POINT_F64 * pts
     achieved = bytes_launch / avg_launch / 1e9
-    kname = f"k_sweep2d_tb<double,{fuse},2,3>" if fuse > 0 else "k_sweep2d<double>"
+    hint = 2 if int(desc.get("store_nt", 0)) else 0  # the kernel's store-hint template argument
+    kname = f"k_sweep2d_tb<double,{fuse},2,3,{hint}>" if fuse > 0 else "k_sweep2d<double>"
     wname = f"blobs2d_{n}x{n}_f64"
     # counters were taken on the default launch shape (the default depth, segment height
     # from the occupancy); the record is keyed by kernel (and so depth), another segment

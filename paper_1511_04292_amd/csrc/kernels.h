@@ -61,10 +61,11 @@ hipError_t launch_sweep_unfused(Fmt f, const void* in, void* out, const void* b,
                                 double c, hipStream_t s);
 // T consecutive 2D sweeps in -> out in one launch with coefficients co.c[0..T), row
 // segments of H output rows per wave.  flip (0 or 1) reverses the direction every segment
-// streams in; callers alternate it from launch to launch (it changes no result).
+// streams in; callers alternate it from launch to launch (it changes no result).  nt: binary64
+// stores carry the non-temporal hint (ignored for the other formats; it changes no result).
 // (The temporally blocked kernels implement the equal-spacing Dirichlet operator only.)
 hipError_t launch_sweep_fused(Fmt f, const void* in, void* out, const void* b, const Geo& g,
-                              const Coefs& co, int T, int H, int flip, hipStream_t s);
+                              const Coefs& co, int T, int H, int flip, bool nt, hipStream_t s);
 // T <= lds_fuse_max() (8) binary64 sweeps of a 2D grid with unequal spacings, Neumann
 // boundaries or a point-wise operator in one launch, on tiles held in LDS with T-wide halos
 // (sweep2d_lds.hip).  lds_fuse_fits: 2D binary64.

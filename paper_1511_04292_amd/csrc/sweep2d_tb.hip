@@ -29,7 +29,7 @@ template <int T> struct CoefsT {
 // keeping the overlapping halo reads of neighbouring waves in one L2.
 // The 4- and 2-byte formats are held to 3 waves per SIMD (168 VGPRs): at 10 levels the
 // compiler would otherwise take 185 and leave 2; binary64 is left to the compiler.
-template <class S, int T, int C, int D>
+template <class S, int T, int C, int D, int HINT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(S) == 8 ? 1 : 3)))
 void k_sweep2d_tb(const S* __restrict__ uin, S* __restrict__ uout, const S* __restrict__ bb, int64_t px, int nx,
                   int ny, CoefsT<T> co, int nstrip, int nwaves, int H, int flip)
@@ -43,17 +43,18 @@ void k_sweep2d_tb(const S* __restrict__ uin, S* __restrict__ uout, const S* __re
     Cm cf[T];
 #pragma unroll
     for (int l = 0; l < T; ++l) cf[l] = (Cm)co.c[l];
-    tb_tile<S, T, C, D>(uin, uout, bb, px, nx, ny, cf, T, wid % nstrip, wid / nstrip, H, flip);
+    tb_tile<S, T, C, D, true, true, HINT>(uin, uout, bb, px, nx, ny, cf, T, wid % nstrip, wid / nstrip, H, flip);
 }
 
 // Waves of one kernel instance that the device holds at once: blocks per CU (from the
 // kernel's register and LDS use) x 4 waves x CUs.
-template <class S, int T, int C, int D>
+template <class S, int T, int C, int D, int HINT>
 static int tb_resident_waves()
 {
     static const int waves = [] {
         int nb = 0, dev = 0, ncu = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep2d_tb<S, T, C, D>, 256, 0) != hipSuccess) nb = 1;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep2d_tb<S, T, C, D, HINT>, 256, 0) != hipSuccess)
+            nb = 1;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
             ncu = 1;
@@ -62,7 +63,7 @@ static int tb_resident_waves()
     return waves;
 }
 
-template <class S, int T, int C, int D>
+template <class S, int T, int C, int D, int HINT>
 static void tb2d(const S* in, S* out, const S* b, const Geo& g, const Coefs& co, int H, int flip,
                  hipStream_t s)
 {
@@ -74,32 +75,46 @@ static void tb2d(const S* in, S* out, const S* b, const Geo& g, const Coefs& co,
         // One round: as many row segments as leave every resident wave slot one tile, so
         // that all waves start together and the device stays full until they end.  Below
         // 2T rows a tile would spend most of its steps filling the pipeline.
-        const int per_strip = std::max(1, tb_resident_waves<S, T, C, D>() / nstrip);
+        const int per_strip = std::max(1, tb_resident_waves<S, T, C, D, HINT>() / nstrip);
         H = std::max((int)((g.ny + per_strip - 1) / per_strip), std::max(2 * T, 8));
     }
     H = std::min(H, tb_max_rows(g.px, (int)sizeof(S)));
     const int nseg = (int)((g.ny + H - 1) / H);
     const int nwaves = nstrip * nseg;
     const int nblk = ((nwaves + 3) / 4 + 7) / 8 * 8;
-    hipLaunchKernelGGL((k_sweep2d_tb<S, T, C, D>), dim3(nblk), dim3(256), 0, s, in, out, b, g.px,
+    hipLaunchKernelGGL((k_sweep2d_tb<S, T, C, D, HINT>), dim3(nblk), dim3(256), 0, s, in, out, b, g.px,
                        (int)g.nx, (int)g.ny, ct, nstrip, nwaves, H, flip);
 }
 
+// The non-temporal store hint applies to binary64 only (see kTbStoreNt).
+template <class S, int T, int C, int D>
+static void tb2d_h(const S* in, S* out, const S* b, const Geo& g, const Coefs& co, int H, int flip, bool nt,
+                   hipStream_t s)
+{
+    if constexpr (sizeof(S) == 8) {
+        if (nt) {
+            tb2d<S, T, C, D, kTbStoreNt>(in, out, b, g, co, H, flip, s);
+            return;
+        }
+    }
+    tb2d<S, T, C, D, 0>(in, out, b, g, co, H, flip, s);
+}
+
 template <class S, int C, int D>
-static void tb2d_T(const S* in, S* out, const S* b, const Geo& g, const Coefs& co, int T, int H, int flip,
+static void tb2d_T(const S* in, S* out, const S* b, const Geo& g, const Coefs& co, int T, int H, int flip, bool nt,
                    hipStream_t s)
 {
     switch (T) {
-    case 1: tb2d<S, 1, C, D>(in, out, b, g, co, H, flip, s); break;
-    case 2: tb2d<S, 2, C, D>(in, out, b, g, co, H, flip, s); break;
-    case 3: tb2d<S, 3, C, D>(in, out, b, g, co, H, flip, s); break;
-    case 4: tb2d<S, 4, C, D>(in, out, b, g, co, H, flip, s); break;
-    case 5: tb2d<S, 5, C, D>(in, out, b, g, co, H, flip, s); break;
-    case 6: tb2d<S, 6, C, D>(in, out, b, g, co, H, flip, s); break;
-    case 7: tb2d<S, 7, C, D>(in, out, b, g, co, H, flip, s); break;
-    case 8: tb2d<S, 8, C, D>(in, out, b, g, co, H, flip, s); break;
-    case 9: tb2d<S, 9, C, D>(in, out, b, g, co, H, flip, s); break;
-    default: tb2d<S, 10, C, D>(in, out, b, g, co, H, flip, s); break;
+    case 1: tb2d_h<S, 1, C, D>(in, out, b, g, co, H, flip, nt, s); break;
+    case 2: tb2d_h<S, 2, C, D>(in, out, b, g, co, H, flip, nt, s); break;
+    case 3: tb2d_h<S, 3, C, D>(in, out, b, g, co, H, flip, nt, s); break;
+    case 4: tb2d_h<S, 4, C, D>(in, out, b, g, co, H, flip, nt, s); break;
+    case 5: tb2d_h<S, 5, C, D>(in, out, b, g, co, H, flip, nt, s); break;
+    case 6: tb2d_h<S, 6, C, D>(in, out, b, g, co, H, flip, nt, s); break;
+    case 7: tb2d_h<S, 7, C, D>(in, out, b, g, co, H, flip, nt, s); break;
+    case 8: tb2d_h<S, 8, C, D>(in, out, b, g, co, H, flip, nt, s); break;
+    case 9: tb2d_h<S, 9, C, D>(in, out, b, g, co, H, flip, nt, s); break;
+    default: tb2d_h<S, 10, C, D>(in, out, b, g, co, H, flip, nt, s); break;
     }
 }
 
@@ -107,21 +122,21 @@ static void tb2d_T(const S* in, S* out, const S* b, const Geo& g, const Coefs& c
 // and the kernel keeps 3 waves per SIMD at 8 sweeps), 4 for the 4-byte and 2-byte formats.
 template <class S>
 static void tb2d_dispatch(const S* in, S* out, const S* b, const Geo& g, const Coefs& co, int T,
-                          int H, int flip, hipStream_t s)
+                          int H, int flip, bool nt, hipStream_t s)
 {
     constexpr int C = 2;
     if constexpr (sizeof(S) == 8)
-        tb2d_T<S, C, 3>(in, out, b, g, co, T, H, flip, s);
+        tb2d_T<S, C, 3>(in, out, b, g, co, T, H, flip, nt, s);
     else
-        tb2d_T<S, C, 4>(in, out, b, g, co, T, H, flip, s);
+        tb2d_T<S, C, 4>(in, out, b, g, co, T, H, flip, false, s);
 }
 
 hipError_t launch_sweep_fused(Fmt f, const void* in, void* out, const void* b, const Geo& g,
-                              const Coefs& co, int T, int H, int flip, hipStream_t s)
+                              const Coefs& co, int T, int H, int flip, bool nt, hipStream_t s)
 {
     if (g.ndim != 2 || T < 1 || T > kMaxFuse || H < 0) return hipErrorInvalidValue;  // H = 0: automatic
     flip &= 1;
-    SRJ_DISPATCH(f, tb2d_dispatch<S>((const S*)in, (S*)out, (const S*)b, g, co, T, H, flip, s));
+    SRJ_DISPATCH(f, tb2d_dispatch<S>((const S*)in, (S*)out, (const S*)b, g, co, T, H, flip, nt, s));
     return hipGetLastError();
 }
 

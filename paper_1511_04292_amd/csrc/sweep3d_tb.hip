@@ -174,7 +174,7 @@ __global__ __launch_bounds__(64 * NW) void k_sweep3d_tb(const S* __restrict__ ui
 #pragma unroll
             for (int r = 0; r < k3Rows; ++r) {
                 const int rowpart = outy[r] ? (int)((int64_t)yr[r] * px * (int64_t)sizeof(S)) : kTbMasked;
-                tb_store(Tr<S>::st(in[r]), rs, rowpart + lanebase);
+                tb_store<sizeof(S) == 8 ? kTbStoreNt : 0>(Tr<S>::st(in[r]), rs, rowpart + lanebase);
             }
 #pragma unroll
             for (int l = T - 1; l > 0; --l)

@@ -50,24 +50,28 @@ __device__ __forceinline__ int vcopy(int x)
 typedef unsigned int tb_u32x2 __attribute__((ext_vector_type(2)));
 constexpr int kTbMasked = 0x40000000;  // offset added for a masked row; the record count stays below it
 
-// Binary64 stores carry the non-temporal hint (cache-policy bit nt): the fused binary64
-// launches write a field that the next launch reads only after the rest of the grid has
-// streamed through, and measured faster with it (4096^2 at 10 sweeps 87.7 against 89.0 us,
-// 512^3 at 4 sweeps 921 against 944 us).  The 4- and 2-byte formats, whose 2D working sets
-// stay in the memory-side cache, measured 3-6% slower with it and store plainly.
+// HINT is the stores' cache-policy operand: 0 (plain) or kTbStoreNt (the non-temporal bit).
+// Which launches take the hint was measured, alternating builds on one machine: the fused
+// binary64 3D sweep always (512^3 at 4 sweeps: 921 against 944 us), the fused binary64 2D
+// sweep while its three fields fit in about twice the memory-side cache (4096^2 at 10 sweeps:
+// 87.3 against 89.2 us; 8192^2 to 32768^2 were 2-3% slower with it, one sweep per launch
+// 18-37% slower); the 4- and 2-byte formats never (3-6% slower).
 constexpr int kTbStoreNt = 2;
 
+template <int HINT = 0>
 __device__ __forceinline__ void tb_store(double v, __amdgpu_buffer_rsrc_t r, int off)
 {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(tb_u32x2, v), r, off, 0, kTbStoreNt);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(tb_u32x2, v), r, off, 0, HINT);
 }
+template <int HINT = 0>
 __device__ __forceinline__ void tb_store(float v, __amdgpu_buffer_rsrc_t r, int off)
 {
-    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, off, 0, HINT);
 }
+template <int HINT = 0>
 __device__ __forceinline__ void tb_store(bf16_t v, __amdgpu_buffer_rsrc_t r, int off)
 {
-    __builtin_amdgcn_raw_buffer_store_b16(v.v, r, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b16(v.v, r, off, 0, HINT);
 }
 
 // Two neighbouring elements x, x+1 of a row in one load (x odd: the pair is aligned to its
@@ -160,7 +164,7 @@ struct TbRegs {
 //             the grid (the ring and beyond, fixed per lane) keep their values;
 //   TB_FULL:  rows, columns and levels above Tact are all checked.
 enum { TB_CLEAN = 0, TB_COLS = 1, TB_FULL = 2 };
-template <class S, int T, int C, int D, int MODE>
+template <class S, int T, int C, int D, int MODE, int HINT>
 __device__ __forceinline__ void tb_step(TbRegs<typename Tr<S>::C, T, C, D>& R, int s, int lmax, int r,
                                         const typename Tr<S>::C (&cf)[T], const bool (&upd)[C], int ny,
                                         int Tact, int y0, int y1, int rowbytes, const int (&lanebase)[C],
@@ -220,7 +224,7 @@ __device__ __forceinline__ void tb_step(TbRegs<typename Tr<S>::C, T, C, D>& R, i
         const int j = r - dir * T;
         const int rowpart = (j >= y0 && j < y1) ? (j - y0) * rowbytes : kTbMasked;
 #pragma unroll
-        for (int c = 0; c < C; ++c) tb_store(Tr<S>::st(in[c]), rs, rowpart + lanebase[c]);
+        for (int c = 0; c < C; ++c) tb_store<HINT>(Tr<S>::st(in[c]), rs, rowpart + lanebase[c]);
     }
 #pragma unroll
     for (int l = T - 1; l > 0; --l)
@@ -243,7 +247,7 @@ __device__ __forceinline__ void tb_step(TbRegs<typename Tr<S>::C, T, C, D>& R, i
 // are needed; the rest of the step loop is free of branches so that the D row loads in
 // flight (register slots named statically by unrolling the loop D times) overlap D steps
 // of arithmetic.  H * px * sizeof(S) must not exceed what tb_max_rows allows.
-template <class S, int T, int C, int D, int FILL, int STEADY, bool WIDE>
+template <class S, int T, int C, int D, int FILL, int STEADY, bool WIDE, int HINT>
 __device__ __forceinline__ void tb_tile_body(const S* __restrict__ uin, S* __restrict__ uout,
                                              const S* __restrict__ bb, int64_t px, int nx, int ny,
                                              const typename Tr<S>::C (&cf)[T], int Tact, int st, int sg, int H,
@@ -320,7 +324,7 @@ __device__ __forceinline__ void tb_tile_body(const S* __restrict__ uin, S* __res
     for (int i = 0; i < F; ++i) {
         const int s = i % D;
         const int lmax = min(T, i / 2);
-        tb_step<S, T, C, D, FILL>(R, s, lmax, r_first + dir * i, cf, upd, ny, Tact, y0, y1, rowbytes, lanebase, rs,
+        tb_step<S, T, C, D, FILL, HINT>(R, s, lmax, r_first + dir * i, cf, upd, ny, Tact, y0, y1, rowbytes, lanebase, rs,
                                   dir);
         load_row(r_first + dir * (i + D), R.U[s], R.B[s]);
         // keep each row load in its step: bunched at the end of the loop body they would be
@@ -339,7 +343,7 @@ __device__ __forceinline__ void tb_tile_body(const S* __restrict__ uin, S* __res
 #pragma unroll
             for (int q = 0; q < K; ++q) {
                 const int r = r_first + dir * (i0 + q);
-                tb_step<S, T, C, D, STEADY>(R, q % D, T, r, cf, upd, ny, Tact, y0, y1, rowbytes, lanebase, rs,
+                tb_step<S, T, C, D, STEADY, HINT>(R, q % D, T, r, cf, upd, ny, Tact, y0, y1, rowbytes, lanebase, rs,
                                             dir);
                 load_row(r + dir * D, R.U[q % D], R.B[q % D]);
                 __builtin_amdgcn_sched_barrier(0);
@@ -350,7 +354,7 @@ __device__ __forceinline__ void tb_tile_body(const S* __restrict__ uin, S* __res
 #pragma unroll
         for (int s = 0; s < D; ++s) {
             const int r = r_first + dir * (i0 + s);
-            tb_step<S, T, C, D, STEADY>(R, s, T, r, cf, upd, ny, Tact, y0, y1, rowbytes, lanebase, rs, dir);
+            tb_step<S, T, C, D, STEADY, HINT>(R, s, T, r, cf, upd, ny, Tact, y0, y1, rowbytes, lanebase, rs, dir);
             load_row(r + dir * D, R.U[s], R.B[s]);
             __builtin_amdgcn_sched_barrier(0);
         }
@@ -363,7 +367,7 @@ __device__ __forceinline__ void tb_tile_body(const S* __restrict__ uin, S* __res
 // use two variants only.  WIDE: whether binary64 at 10 levels may unroll its steady loop
 // over lcm(D, 2) steps (the batch kernel, which also holds the residual path, may not: it
 // would fall to one wave per SIMD).
-template <class S, int T, int C, int D, bool EDGES = true, bool WIDE = true>
+template <class S, int T, int C, int D, bool EDGES = true, bool WIDE = true, int HINT = 0>
 __device__ __forceinline__ void tb_tile(const S* __restrict__ uin, S* __restrict__ uout,
                                         const S* __restrict__ bb, int64_t px, int nx, int ny,
                                         const typename Tr<S>::C (&cf)[T], int Tact, int st, int sg, int H,
@@ -392,22 +396,22 @@ __device__ __forceinline__ void tb_tile(const S* __restrict__ uin, S* __restrict
         // binary64 below 10 levels keeps two variants: more would raise the kernel's register
         // count past three waves per SIMD at 8 levels (at 10 it holds two waves either way)
         if (Tact < T || top || bottom || cols)
-            tb_tile_body<S, T, C, D, TB_FULL, TB_FULL, WIDE>(uin, uout, bb, px, nx, ny, cf, Tact, st, sg, H, dir);
+            tb_tile_body<S, T, C, D, TB_FULL, TB_FULL, WIDE, HINT>(uin, uout, bb, px, nx, ny, cf, Tact, st, sg, H, dir);
         else
-            tb_tile_body<S, T, C, D, TB_CLEAN, TB_CLEAN, WIDE>(uin, uout, bb, px, nx, ny, cf, Tact, st, sg, H, dir);
+            tb_tile_body<S, T, C, D, TB_CLEAN, TB_CLEAN, WIDE, HINT>(uin, uout, bb, px, nx, ny, cf, Tact, st, sg, H, dir);
         return;
     }
     if (Tact < T || (top && bottom)) {
-        tb_tile_body<S, T, C, D, TB_FULL, TB_FULL, WIDE>(uin, uout, bb, px, nx, ny, cf, Tact, st, sg, H, dir);
+        tb_tile_body<S, T, C, D, TB_FULL, TB_FULL, WIDE, HINT>(uin, uout, bb, px, nx, ny, cf, Tact, st, sg, H, dir);
     } else if (top || bottom) {
         if (cols)
-            tb_tile_body<S, T, C, D, TB_FULL, TB_COLS, WIDE>(uin, uout, bb, px, nx, ny, cf, Tact, st, sg, H, dir);
+            tb_tile_body<S, T, C, D, TB_FULL, TB_COLS, WIDE, HINT>(uin, uout, bb, px, nx, ny, cf, Tact, st, sg, H, dir);
         else
-            tb_tile_body<S, T, C, D, TB_FULL, TB_CLEAN, WIDE>(uin, uout, bb, px, nx, ny, cf, Tact, st, sg, H, dir);
+            tb_tile_body<S, T, C, D, TB_FULL, TB_CLEAN, WIDE, HINT>(uin, uout, bb, px, nx, ny, cf, Tact, st, sg, H, dir);
     } else if (cols) {
-        tb_tile_body<S, T, C, D, TB_COLS, TB_COLS, WIDE>(uin, uout, bb, px, nx, ny, cf, Tact, st, sg, H, dir);
+        tb_tile_body<S, T, C, D, TB_COLS, TB_COLS, WIDE, HINT>(uin, uout, bb, px, nx, ny, cf, Tact, st, sg, H, dir);
     } else {
-        tb_tile_body<S, T, C, D, TB_CLEAN, TB_CLEAN, WIDE>(uin, uout, bb, px, nx, ny, cf, Tact, st, sg, H, dir);
+        tb_tile_body<S, T, C, D, TB_CLEAN, TB_CLEAN, WIDE, HINT>(uin, uout, bb, px, nx, ny, cf, Tact, st, sg, H, dir);
     }
 }
 

@@ -63,7 +63,7 @@ class _Desc(ctypes.Structure):
                 ("kappa_max", ctypes.c_double), ("rho", ctypes.c_double),
                 ("gamma_q_max", ctypes.c_double), ("prefix_peak_log10", ctypes.c_double),
                 ("suffix_peak_log10", ctypes.c_double), ("fused_sweeps", ctypes.c_int32),
-                ("resident", ctypes.c_int32)]
+                ("resident", ctypes.c_int32), ("store_nt", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -273,7 +273,8 @@ def srj_plan_describe(plan):
     return dict(P=P, M=d.M, omega=np.array(d.omega[:P]), beta=np.array(d.beta[:P]),
                 q=np.array(d.q[:P], dtype=np.int64), kappa_min=d.kappa_min, kappa_max=d.kappa_max,
                 rho=d.rho, gamma_q_max=d.gamma_q_max, prefix_peak_log10=d.prefix_peak_log10,
-                suffix_peak_log10=d.suffix_peak_log10, fused_sweeps=d.fused_sweeps, resident=d.resident)
+                suffix_peak_log10=d.suffix_peak_log10, fused_sweeps=d.fused_sweeps, resident=d.resident,
+                store_nt=d.store_nt)
 
 
 def srj_plan_sequence(plan):

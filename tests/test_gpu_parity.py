@@ -475,6 +475,18 @@ def test_errors():
     assert srj.srj_plan_describe(p3)["fused_sweeps"] == 0
 
 
+def test_store_hint_follows_the_working_set():
+    """Fused 2D binary64 plans store with the non-temporal hint while input, output and b fit
+    in twice the 256 MiB memory-side cache (4096^2 yes, 8192^2 no); the flag is reported for
+    2D binary64 plans only (3D binary64 always takes the hint, the other formats never)."""
+    assert srj.srj_plan_describe(srj.srj_plan((4096, 4096), 1.0 / 4097, omega=[1.0], q=[1]))["store_nt"] == 1
+    assert srj.srj_plan_describe(srj.srj_plan((8192, 8192), 1.0 / 8193, omega=[1.0], q=[1]))["store_nt"] == 0
+    assert srj.srj_plan_describe(srj.srj_plan((64, 48), 1.0 / 65, omega=[1.0], q=[1]))["store_nt"] == 1
+    assert srj.srj_plan_describe(srj.srj_plan((4096, 4096), 1.0 / 4097, omega=[1.0], q=[1],
+                                              dtype="f32"))["store_nt"] == 0
+    assert srj.srj_plan_describe(srj.srj_plan((64, 64, 64), 1.0 / 65, omega=[1.0], q=[1]))["store_nt"] == 0
+
+
 def test_nan_source_diverges_on_every_path():
     """A NaN in the source makes every solve path report SRJ_EDIVERGED at its first check:
     the blocked 2D kernel, one sweep per launch (check fused into the cycle's first sweep),
