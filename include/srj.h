@@ -123,9 +123,10 @@ typedef struct {
     double suffix_peak_log10;
     int32_t fused_sweeps;          /* sweeps fused per launch by the 2D/3D kernels */
     int32_t resident;              /* 1: srj_solve runs in one workgroup with the grid in LDS */
-    int32_t store_nt;              /* 1: the fused 2D binary64 launches store with the
-                                      non-temporal cache hint (grids whose input, output and b
-                                      fields fit in twice the 256 MiB memory-side cache) */
+    int32_t store_nt;              /* 1: the register-streamed fused 2D binary64 launches
+                                      (equal spacings, Dirichlet) store with the non-temporal
+                                      cache hint: grids whose input, output and b fields fit in
+                                      twice the 256 MiB memory-side cache */
 } srj_plan_desc;
 
 typedef struct {

@@ -592,7 +592,7 @@ srj_status create_plan(const srj_grid* grid, const srj_schedule* schedule, void*
     // Fused 2D binary64 launches store with the non-temporal hint while the three fields they
     // touch (input, output, b) fit in twice the 256 MiB memory-side cache: measured faster up
     // to 4096^2, slower from 8192^2 on (the 3D kernel always takes it, the other formats never)
-    p->store_nt = p->fmt == FMT_F64 && g.ndim == 2 &&
+    p->store_nt = p->fmt == FMT_F64 && g.ndim == 2 && p->iso && g.bc == 0 && !g.op &&
                   3.0 * (double)p->field_elems * sizeof(double) <= 2.0 * 256.0 * 1024.0 * 1024.0;
     // small binary64 2D grids: srj_solve keeps the grid in one compute unit's LDS
     if (p->fmt == FMT_F64 && small_solve_fits(g)) {

@@ -485,6 +485,9 @@ def test_store_hint_follows_the_working_set():
     assert srj.srj_plan_describe(srj.srj_plan((4096, 4096), 1.0 / 4097, omega=[1.0], q=[1],
                                               dtype="f32"))["store_nt"] == 0
     assert srj.srj_plan_describe(srj.srj_plan((64, 64, 64), 1.0 / 65, omega=[1.0], q=[1]))["store_nt"] == 0
+    # plans that run the LDS-tiled kernel instead report 0
+    assert srj.srj_plan_describe(srj.srj_plan((64, 48), (1.0 / 65, 0.5 / 49), omega=[1.0], q=[1]))["store_nt"] == 0
+    assert srj.srj_plan_describe(srj.srj_plan((64, 48), 1.0 / 64, omega=[1.0], q=[1], bc="neumann"))["store_nt"] == 0
 
 
 def test_nan_source_diverges_on_every_path():
