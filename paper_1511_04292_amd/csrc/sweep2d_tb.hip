@@ -3,11 +3,13 @@
 // T consecutive scheduled sweeps (Sec. 2; each step as in Sec. 3.1, Eq. 2nd-order_CD,
 // evaluated with the association and rounding of the unfused kernel, so the result is
 // bit-identical to T unfused sweeps) are applied in one launch.  Each wavefront owns a
-// strip of 64*C columns (C per lane) and a segment of rows, streams the rows from top to
-// bottom and keeps T time levels of a 3-row window in registers: one HBM read of u and b
-// and one write of u serve T sweeps.  Horizontal neighbours cross lanes by DPP lane
-// shifts; no LDS and no barriers are needed because every wave is independent (strips
-// overlap by T columns on each side, segments by T rows, the overlap being recomputed).
+// strip of 64*C columns (C per lane) and a segment of rows, streams the rows (downwards or
+// upwards: neighbouring segments alternate, and every launch flips them) and keeps T time
+// levels of a 3-row window in registers: one HBM read of u and b and one write of u serve T
+// sweeps.  Horizontal neighbours cross lanes by DPP lane shifts; no LDS and no barriers are
+// needed because every wave is independent (strips overlap by T columns on each side,
+// segments by T rows, the overlap being recomputed).  The last template argument is the
+// stores' cache hint (kTbStoreNt or 0), chosen per plan for binary64.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

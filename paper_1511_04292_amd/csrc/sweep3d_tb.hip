@@ -2,15 +2,16 @@
 //
 // T consecutive scheduled sweeps (Sec. 2; each step the 7-point form of Sec. 3.1's update
 // with d = 3, evaluated with the association and rounding of the unfused kernel, so the
-// result is bit-identical to T unfused sweeps) are applied in one launch.  A block of 16 waves
-// owns an x-y tile of 64 columns (one per lane) by 32 rows (2 per wave) and streams a run of
-// z planes through it.  At step k the block takes plane k (level 0) and computes level l for
+// result is bit-identical to T unfused sweeps) are applied in one launch.  A block of NW waves
+// (16, or 15 where that fills more compute units) owns an x-y tile of 64 columns (one per
+// lane) by 2 NW rows (2 per wave) and streams a run of z planes through it.  At step k the block takes plane k (level 0) and computes level l for
 // plane k - l, l = 1..T, from level l-1 planes k-l-1, k-l and k-l+1: each lane keeps, per
 // level, the two older planes of its 2 points in registers; x neighbours cross lanes by DPP
 // shifts, y neighbours are the lane's own rows except across wave boundaries, where the
 // boundary rows of each level are exchanged through LDS (double-buffered by step parity, one
 // barrier per step).  One HBM read of u and b and one write of u serve T sweeps; tiles overlap
 // by T columns and rows on each side and z runs by T planes, the overlap being recomputed.
+// Binary64 stores carry the non-temporal hint (kTbStoreNt).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
