@@ -44,3 +44,25 @@ def test_summarize_trace_groups_by_kernel_and_grid():
     # two launches of 100 and 96 us on the 194560-thread grid come first (largest total)
     assert first[0] == "`srj::k_sweep2d_tb<double, 8, 2, 3>`" and first[1] == "194560x1x1"
     assert first[2] == "2" and first[4] == "98.00"
+
+
+def test_kernel_source_hash_skips_comments_only(tmp_path, monkeypatch):
+    csrc = tmp_path / "paper_1511_04292_amd" / "csrc"
+    csrc.mkdir(parents=True)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    code = {"sweep2d_tb.hip": "int f(int x)\n{\n    return x + 1;\n}\n", "tb_core.h": "#pragma once\n",
+            "formats.h": "struct A { int v; };\n"}
+
+    def write(files):
+        for name, text in files.items():
+            (csrc / name).write_text(text)
+        return bench.kernel_source_hash()
+
+    h0 = write(code)
+    commented = dict(code)
+    commented["sweep2d_tb.hip"] = ("// header\n/* block\n   comment */\nint f(int x)  // trailing\n{\n\n"
+                                   "        return x + 1;\n}\n")
+    assert write(commented) == h0
+    changed = dict(code)
+    changed["sweep2d_tb.hip"] = "int f(int x)\n{\n    return x + 2;\n}\n"
+    assert write(changed) != h0
