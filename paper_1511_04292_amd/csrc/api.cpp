@@ -159,7 +159,7 @@ struct srj_plan_s {
     bool ldsfuse = false;       // fused sweeps run in the LDS-tiled kernel (2D binary64 plans
                                 // with unequal spacings, Neumann boundaries or an operator)
     double* cseq_d = nullptr;   // the cycle's coefficients on the device (resident solves)
-    uint32_t fused_launches = 0;  // 2D launches so far: their parity alternates the stream direction
+    uint32_t fused_launches = 0;  // fused launches so far: their parity alternates the stream direction
     bool store_nt = false;        // fused 2D binary64 stores carry the non-temporal hint
 
     // device buffers
@@ -279,7 +279,8 @@ srj_status run_sweeps(srj_plan_t p, DField** cur, DField** nxt, const void* b, i
                 HIPCHK(launch_sweep_fused(p->fmt, (*cur)->origin, (*nxt)->origin, b, p->geo, co, T, p->seg_rows,
                                           (int)(p->fused_launches++ & 1u), p->store_nt, p->stream));
             else
-                HIPCHK(launch_sweep_fused3d(p->fmt, (*cur)->origin, (*nxt)->origin, b, p->geo, co, T, p->stream));
+                HIPCHK(launch_sweep_fused3d(p->fmt, (*cur)->origin, (*nxt)->origin, b, p->geo, co, T,
+                                            (int)(p->fused_launches++ & 1u), p->stream));
             k += T;
         }
         if (launches) *launches += 1;

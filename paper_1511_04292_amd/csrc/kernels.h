@@ -75,14 +75,15 @@ hipError_t launch_sweep_lds2d(const void* in, void* out, const void* b, const Ge
                               hipStream_t s);
 
 // T <= kMaxFuse3d sweeps (coefficients co.c[0..T)) of a 3D grid in one launch: x-y tiles of
-// 64 x 32 with T-wide halos, streamed in z.  Needs fused3d_fits(g, f): a padded z plane
-// below 1 GiB (its stores are addressed within one plane).
+// 64 x 30 or 64 x 32 with T-wide halos, streamed in z, upwards or (flip = 1) downwards;
+// callers alternate flip from launch to launch (it changes no result).  Needs
+// fused3d_fits(g, f): a padded z plane below 1 GiB (its stores are addressed within one plane).
 inline bool fused3d_fits(const Geo& g, Fmt f)
 {
     return g.px * g.py * (int64_t)fmt_size(f) < ((int64_t)1 << 30) - 4096;
 }
 hipError_t launch_sweep_fused3d(Fmt f, const void* in, void* out, const void* b, const Geo& g,
-                                const Coefs& co, int T, hipStream_t s);
+                                const Coefs& co, int T, int flip, hipStream_t s);
 // sum r^2 and max |r| of r = b64 - A u (binary64); zero_interior treats u's interior as 0.
 // partials must hold 2 * residual_blocks(g) doubles; result receives {sum, max}.
 int residual_blocks(const Geo& g);

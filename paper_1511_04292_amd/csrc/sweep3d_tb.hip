@@ -45,7 +45,7 @@ template <class S, int T, int D, int NW>
 __global__ __launch_bounds__(64 * NW) void k_sweep3d_tb(const S* __restrict__ uin, S* __restrict__ uout,
                                                     const S* __restrict__ bb, int64_t px, int64_t py, int nx,
                                                     int ny, int nz, Coefs3T<T> co, int Tact, int ntx, int nty,
-                                                    int ntz, int zs)
+                                                    int ntz, int zs, int dir)
 {
     using Cm = typename Tr<S>::C;
     constexpr int SX = 64 - 2 * T;        // output columns per tile
@@ -82,6 +82,12 @@ __global__ __launch_bounds__(64 * NW) void k_sweep3d_tb(const S* __restrict__ ui
     const int z1 = min(z0 + zs, nz + 1);
     const int kb = z0 - T;
     const int ke = z1 - 1 + T;
+    // dir = +1 streams the run's planes upwards (level l works on plane k - l), -1 downwards
+    // (plane k + l); the z pair of the sum is then formed as (U + D), the same IEEE sum as
+    // (D + U).  Launches alternate it, so that each starts on the planes the previous one
+    // touched last.
+    const int kfirst = dir > 0 ? kb : ke;
+    const int nsteps = ke - kb + 1;
 
     Cm cf[T];
 #pragma unroll
@@ -110,19 +116,19 @@ __global__ __launch_bounds__(64 * NW) void k_sweep3d_tb(const S* __restrict__ ui
 
     Cm U[D][k3Rows], B[D][k3Rows];
 #pragma unroll
-    for (int s = 0; s < D; ++s) load_plane(kb + s, U[s], B[s]);
+    for (int s = 0; s < D; ++s) load_plane(kfirst + dir * s, U[s], B[s]);
 
     const int wu = max(w - 1, 0), wd = min(w + 1, NW - 1);
     // K steps per loop iteration, K a multiple of D (the load slots), 2 (the two older planes
     // per level) and T (the delay line of b): every register then plays the same role at both
     // ends of the loop body and the back edge needs no copies.  The last iteration may run up
-    // to K - 1 planes past ke: they are loaded clamped and never stored.
+    // to K - 1 planes past the run's last step: they are loaded clamped and never stored.
     constexpr int K = k3_lcm(k3_lcm(D, 2), T);
-    for (int k0 = kb; k0 <= ke; k0 += K) {
+    for (int i0 = 0; i0 < nsteps; i0 += K) {
 #pragma unroll
         for (int q = 0; q < K; ++q) {
             const int s = q % D;
-            const int k = k0 + q;
+            const int k = kfirst + dir * (i0 + q);
             const int cur = k & 1, prev = cur ^ 1;
             Cm in[k3Rows];
 #pragma unroll
@@ -131,11 +137,12 @@ __global__ __launch_bounds__(64 * NW) void k_sweep3d_tb(const S* __restrict__ ui
             xch[cur][0][w][1][lane] = in[k3Rows - 1];
 #pragma unroll
             for (int l = 1; l <= T; ++l) {
-                // level l on plane p = k - l; its y neighbours across wave boundaries are the
-                // neighbouring waves' rows of plane p at level l-1, published in step k-1
+                // level l on plane p = k - dir l; its y neighbours across wave boundaries are
+                // the neighbouring waves' rows of plane p at level l-1, published in the
+                // previous step
                 const Cm up = xch[prev][l - 1][wu][1][lane];
                 const Cm dn = xch[prev][l - 1][wd][0][lane];
-                const int p = k - l;
+                const int p = k - dir * l;
                 const bool pok = (p >= 1) & (p <= nz) & (l <= Tact);
                 Cm out[k3Rows], vs[k3Rows];
 #pragma unroll
@@ -167,8 +174,8 @@ __global__ __launch_bounds__(64 * NW) void k_sweep3d_tb(const S* __restrict__ ui
                     xch[cur][l][w][1][lane] = in[k3Rows - 1];
                 }
             }
-            // level T of plane k - T
-            const int pT = k - T;
+            // level T of plane k - dir T
+            const int pT = k - dir * T;
             const bool zout = (pT >= z0) & (pT < z1);
             const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
                 (void*)(uout + (int64_t)min(max(pT, 0), nz + 1) * pl), (short)0, zout ? plbytes : 0, 0x00020000);
@@ -184,7 +191,7 @@ __global__ __launch_bounds__(64 * NW) void k_sweep3d_tb(const S* __restrict__ ui
 #pragma unroll
             for (int r = 0; r < k3Rows; ++r) bq[0][r] = B[s][r];
             __syncthreads();
-            load_plane(k + D, U[s], B[s]);
+            load_plane(k + dir * D, U[s], B[s]);
         }
     }
 }
@@ -205,7 +212,8 @@ static int tb3_resident_blocks()
 }
 
 template <class S, int T, int D, int NW>
-static void tb3d_launch(const S* in, S* out, const S* b, const Geo& g, const Coefs3T<T>& ct, int Tact, hipStream_t s)
+static void tb3d_launch(const S* in, S* out, const S* b, const Geo& g, const Coefs3T<T>& ct, int Tact, int dir,
+                        hipStream_t s)
 {
     constexpr int SX = 64 - 2 * T, SY = NW * k3Rows - 2 * T;
     const int ntx = (int)((g.nx + SX - 1) / SX);
@@ -218,14 +226,14 @@ static void tb3d_launch(const S* in, S* out, const S* b, const Geo& g, const Coe
     zs = (int)((g.nz + ntz - 1) / ntz);
     const int nblk = (ntx * nty * ntz + 7) / 8 * 8;
     hipLaunchKernelGGL((k_sweep3d_tb<S, T, D, NW>), dim3(nblk), dim3(64 * NW), 0, s, in, out, b, g.px, g.py, (int)g.nx,
-                       (int)g.ny, (int)g.nz, ct, Tact, ntx, nty, ntz, zs);
+                       (int)g.ny, (int)g.nz, ct, Tact, ntx, nty, ntz, zs, dir);
 }
 
 // Tiles of 16 waves (32 rows) by default; 15 waves (30 rows) when that fills more of the
 // resident block slots in one round without needing a second (512^2 planes at T = 4: 240
 // tiles instead of 220 for 256 compute units), each tile then doing 6% less work.
 template <class S, int T, int D>
-static void tb3d(const S* in, S* out, const S* b, const Geo& g, const Coefs& co, int Tact, hipStream_t s)
+static void tb3d(const S* in, S* out, const S* b, const Geo& g, const Coefs& co, int Tact, int dir, hipStream_t s)
 {
     Coefs3T<T> ct;
     for (int l = 0; l < T; ++l) ct.c[l] = l < Tact ? co.c[l] : 0.0;
@@ -236,35 +244,36 @@ static void tb3d(const S* in, S* out, const S* b, const Geo& g, const Coefs& co,
     const int64_t t16 = tiles(16), t15 = tiles(15);
     const int64_t slots = tb3_resident_blocks<S, T, D, 16>();
     if (t16 < slots && t15 > t16 && t15 <= slots && 15 * k3Rows > 2 * T + 8)
-        tb3d_launch<S, T, D, 15>(in, out, b, g, ct, Tact, s);
+        tb3d_launch<S, T, D, 15>(in, out, b, g, ct, Tact, dir, s);
     else
-        tb3d_launch<S, T, D, 16>(in, out, b, g, ct, Tact, s);
+        tb3d_launch<S, T, D, 16>(in, out, b, g, ct, Tact, dir, s);
 }
 
 template <class S, int D>
-static void tb3d_TD(const S* in, S* out, const S* b, const Geo& g, const Coefs& co, int T, hipStream_t s)
+static void tb3d_TD(const S* in, S* out, const S* b, const Geo& g, const Coefs& co, int T, int dir, hipStream_t s)
 {
     switch (T) {
-    case 1: tb3d<S, 1, D>(in, out, b, g, co, 1, s); break;
-    case 2: tb3d<S, 2, D>(in, out, b, g, co, 2, s); break;
-    case 3: tb3d<S, 3, D>(in, out, b, g, co, 3, s); break;
-    case 4: tb3d<S, 4, D>(in, out, b, g, co, 4, s); break;
-    default: tb3d<S, 5, D>(in, out, b, g, co, 5, s); break;
+    case 1: tb3d<S, 1, D>(in, out, b, g, co, 1, dir, s); break;
+    case 2: tb3d<S, 2, D>(in, out, b, g, co, 2, dir, s); break;
+    case 3: tb3d<S, 3, D>(in, out, b, g, co, 3, dir, s); break;
+    case 4: tb3d<S, 4, D>(in, out, b, g, co, 4, dir, s); break;
+    default: tb3d<S, 5, D>(in, out, b, g, co, 5, dir, s); break;
     }
 }
 
 // Two planes in flight per wave.
 template <class S>
-static void tb3d_T(const S* in, S* out, const S* b, const Geo& g, const Coefs& co, int T, hipStream_t s)
+static void tb3d_T(const S* in, S* out, const S* b, const Geo& g, const Coefs& co, int T, int dir, hipStream_t s)
 {
-    tb3d_TD<S, 2>(in, out, b, g, co, T, s);
+    tb3d_TD<S, 2>(in, out, b, g, co, T, dir, s);
 }
 
 hipError_t launch_sweep_fused3d(Fmt f, const void* in, void* out, const void* b, const Geo& g,
-                                const Coefs& co, int T, hipStream_t s)
+                                const Coefs& co, int T, int flip, hipStream_t s)
 {
     if (g.ndim != 3 || T < 1 || T > kMaxFuse3d) return hipErrorInvalidValue;
-    SRJ_DISPATCH(f, tb3d_T<S>((const S*)in, (S*)out, (const S*)b, g, co, T, s));
+    const int dir = (flip & 1) ? -1 : 1;
+    SRJ_DISPATCH(f, tb3d_T<S>((const S*)in, (S*)out, (const S*)b, g, co, T, dir, s));
     return hipGetLastError();
 }
 
