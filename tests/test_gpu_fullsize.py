@@ -104,19 +104,20 @@ def smooth():
 
 
 def test_smooth_512cube_window_bitwise(smooth):
-    """Depth-4 binary64 launches (the benchmark's) and the short launches at a cycle end:
-    from step M - 5, 12 sweeps run as launches of 4, 1, 4 and 3."""
+    """Depth-5 binary64 launches (the default) with a short launch at a cycle end and a ragged
+    last one: from step M - 3, 12 sweeps run as launches of 3, 5 and 4 (the z direction
+    alternating between them)."""
     wl = smooth
     w, q, seq = oracle_schedule(8, wl["n"])
     M = int(np.sum(q))
     plan = srj.srj_plan(wl["n"], wl["h"], omega=w, q=q, sequence=seq)
-    assert srj.srj_plan_describe(plan)["fused_sweeps"] == 4
+    assert srj.srj_plan_describe(plan)["fused_sweeps"] == 5
     c = sweeps.coefficients(np.asarray(w)[seq], 3)
     b = sweeps.rhs(wl["f"], wl["h"])
-    k0, n = M - 5, 12
+    k0, n = M - 3, 12
     u = torch.from_numpy(wl["u0"]).to(DEV)
     _, launches = srj.srj_sweeps(plan, u, torch.from_numpy(wl["f"]).to(DEV), k0, n)
-    assert launches == 4
+    assert launches == 3
     ref = sweeps.run(wl["u0"], b, c, n, k0=k0)
     assert np.array_equal(u.cpu().numpy(), ref)
 
