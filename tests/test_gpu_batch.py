@@ -1,5 +1,6 @@
 """Batched solves: every problem's result is bit-identical to the oracle's FP64 refinement
-around binary32 sweeps with the same schedule, with the same number of outer steps."""
+around binary32, bfloat16-storage or binary64 sweeps with the same schedule, with the same
+number of outer steps."""
 import numpy as np
 import pytest
 import torch
@@ -32,7 +33,7 @@ def make_problem(n, seed):
     return u0, f
 
 
-@pytest.mark.parametrize("fmt", ["f32", "bf16"])
+@pytest.mark.parametrize("fmt", ["f32", "bf16", "f64"])
 def test_batch_matches_oracle_per_problem(fmt):
     probs, data, refs = [], [], []
     for i, n in enumerate(SIZES):
