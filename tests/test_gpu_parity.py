@@ -325,7 +325,7 @@ def test_product_planner_plan_solves_cfg_small():
 # ----------------------------------------------------------- reduced precision
 
 @pytest.mark.parametrize("fmt", ["f32", "bf16"])
-@pytest.mark.parametrize("fuse", [0, 5, 8, 10])
+@pytest.mark.parametrize("fuse", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10])
 def test_lowprec_sweeps_bitwise(fmt, fuse):
     n = (200, 131)
     h = 1.0 / 201
@@ -391,7 +391,7 @@ def test_ir_f64_matches_oracle(ndim):
 
 
 @pytest.mark.parametrize("fmt", ["f32", "bf16"])
-@pytest.mark.parametrize("fuse", [0, 2, 4, 5])
+@pytest.mark.parametrize("fuse", [0, 1, 2, 3, 4, 5])
 def test_lowprec_sweeps_3d_bitwise(fmt, fuse):
     n = (70, 37, 29)
     h = 1.0 / 71
