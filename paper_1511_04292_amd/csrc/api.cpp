@@ -578,11 +578,13 @@ srj_status create_plan(const srj_grid* grid, const srj_schedule* schedule, void*
         destroy(p);
         return fail(SRJ_EHIP, "initial fill failed");
     }
-    // 2D: 10 sweeps per launch; 3D: 5 (binary64 spills a few registers at 5, but with launches
-    // alternating their z direction and non-temporal stores 5 sweeps per launch measured 7-10%
-    // faster per sweep than 4); unequal spacings and Neumann boundaries: the register-streamed
-    // kernels implement the equal-spacing Dirichlet operator only
-    p->fuse = (!p->iso || g.bc != 0) ? 0 : (g.ndim == 2) ? kMaxFuse : (fused3d_fits(g, p->fmt) ? kMaxFuse3d : 0);
+    // 2D: 10 sweeps per launch; 3D: 5, 4 or 3 from a cost model of the launch shape (5 at 512^3,
+    // where it measured 7-10% faster per sweep than 4; 4 where 5 would leave compute units
+    // idle or waste much of a short z run); unequal spacings and Neumann boundaries: the
+    // register-streamed kernels implement the equal-spacing Dirichlet operator only
+    p->fuse = (!p->iso || g.bc != 0) ? 0
+              : (g.ndim == 2)        ? kMaxFuse
+                                     : (fused3d_fits(g, p->fmt) ? fused3d_default_depth(g, p->fmt) : 0);
     // 2D binary64 with unequal spacings, Neumann boundaries or an operator: up to 8 sweeps per
     // launch on tiles held in LDS (the register-streamed kernels implement the equal-spacing
     // Dirichlet operator only); in 3D these plans sweep once per launch

@@ -84,6 +84,9 @@ inline bool fused3d_fits(const Geo& g, Fmt f)
 }
 hipError_t launch_sweep_fused3d(Fmt f, const void* in, void* out, const void* b, const Geo& g,
                                 const Coefs& co, int T, int flip, hipStream_t s);
+// Default sweeps per fused 3D launch for a grid (5, 4 or 3): the depth whose launch shape a
+// cost model of the tiling (rounds of blocks, steps per block) gives the lowest time per sweep.
+int fused3d_default_depth(const Geo& g, Fmt f);
 // sum r^2 and max |r| of r = b64 - A u (binary64); zero_interior treats u's interior as 0.
 // partials must hold 2 * residual_blocks(g) doubles; result receives {sum, max}.
 int residual_blocks(const Geo& g);

@@ -211,42 +211,100 @@ static int tb3_resident_blocks()
     return blocks;
 }
 
+// Launch shape of depth T with NW-wave blocks: tiles per axis and z runs of zs planes, as
+// many runs as fill the resident block slots once (at least one), balanced.
+struct Tb3Shape {
+    int ntx, nty, ntz, zs;
+};
+template <class S, int T, int D, int NW>
+static Tb3Shape tb3_shape(const Geo& g)
+{
+    constexpr int SX = 64 - 2 * T, SY = NW * k3Rows - 2 * T;
+    Tb3Shape sh;
+    sh.ntx = (int)((g.nx + SX - 1) / SX);
+    sh.nty = (int)((g.ny + SY - 1) / SY);
+    int ntz = std::max(1, tb3_resident_blocks<S, T, D, NW>() / (sh.ntx * sh.nty));
+    int zs = (int)((g.nz + ntz - 1) / ntz);
+    zs = std::max(1, std::min(zs, (int)g.nz));
+    ntz = (int)((g.nz + zs - 1) / zs);
+    sh.ntz = ntz;
+    sh.zs = (int)((g.nz + ntz - 1) / ntz);
+    return sh;
+}
+
 template <class S, int T, int D, int NW>
 static void tb3d_launch(const S* in, S* out, const S* b, const Geo& g, const Coefs3T<T>& ct, int Tact, int dir,
                         hipStream_t s)
 {
-    constexpr int SX = 64 - 2 * T, SY = NW * k3Rows - 2 * T;
-    const int ntx = (int)((g.nx + SX - 1) / SX);
-    const int nty = (int)((g.ny + SY - 1) / SY);
-    // z runs: as many as fill the resident block slots once (at least one), balanced
-    int ntz = std::max(1, tb3_resident_blocks<S, T, D, NW>() / (ntx * nty));
-    int zs = (int)((g.nz + ntz - 1) / ntz);
-    zs = std::max(1, std::min(zs, (int)g.nz));
-    ntz = (int)((g.nz + zs - 1) / zs);
-    zs = (int)((g.nz + ntz - 1) / ntz);
-    const int nblk = (ntx * nty * ntz + 7) / 8 * 8;
+    const Tb3Shape sh = tb3_shape<S, T, D, NW>(g);
+    const int nblk = (sh.ntx * sh.nty * sh.ntz + 7) / 8 * 8;
     hipLaunchKernelGGL((k_sweep3d_tb<S, T, D, NW>), dim3(nblk), dim3(64 * NW), 0, s, in, out, b, g.px, g.py, (int)g.nx,
-                       (int)g.ny, (int)g.nz, ct, Tact, ntx, nty, ntz, zs, dir);
+                       (int)g.ny, (int)g.nz, ct, Tact, sh.ntx, sh.nty, sh.ntz, sh.zs, dir);
 }
 
 // Tiles of 16 waves (32 rows) by default; 15 waves (30 rows) when that fills more of the
 // resident block slots in one round without needing a second (512^2 planes at T = 4: 240
 // tiles instead of 220 for 256 compute units), each tile then doing 6% less work.
 template <class S, int T, int D>
-static void tb3d(const S* in, S* out, const S* b, const Geo& g, const Coefs& co, int Tact, int dir, hipStream_t s)
+static bool tb3_use15(const Geo& g)
 {
-    Coefs3T<T> ct;
-    for (int l = 0; l < T; ++l) ct.c[l] = l < Tact ? co.c[l] : 0.0;
     auto tiles = [&](int nw) {
         const int64_t SX = 64 - 2 * T, SY = nw * k3Rows - 2 * T;
         return ((g.nx + SX - 1) / SX) * ((g.ny + SY - 1) / SY);
     };
     const int64_t t16 = tiles(16), t15 = tiles(15);
     const int64_t slots = tb3_resident_blocks<S, T, D, 16>();
-    if (t16 < slots && t15 > t16 && t15 <= slots && 15 * k3Rows > 2 * T + 8)
+    return t16 < slots && t15 > t16 && t15 <= slots && 15 * k3Rows > 2 * T + 8;
+}
+
+template <class S, int T, int D>
+static void tb3d(const S* in, S* out, const S* b, const Geo& g, const Coefs& co, int Tact, int dir, hipStream_t s)
+{
+    Coefs3T<T> ct;
+    for (int l = 0; l < T; ++l) ct.c[l] = l < Tact ? co.c[l] : 0.0;
+    if (tb3_use15<S, T, D>(g))
         tb3d_launch<S, T, D, 15>(in, out, b, g, ct, Tact, dir, s);
     else
         tb3d_launch<S, T, D, 16>(in, out, b, g, ct, Tact, dir, s);
+}
+
+// Modelled time per sweep of depth T, in units of the per-step cost: rounds of blocks x the
+// steps one block streams (its z run plus 2T, rounded up to the unrolled loop's K steps) x a
+// per-step cost a + b T, over the T sweeps a launch advances.  a = 1.04 and b = 0.154 (us)
+// were fitted to the binary64 launches at 512^3 (4 and 5 sweeps); the model then picks the
+// measured fastest depth at 256^3, 384^3 (where 5 leaves 112 compute units idle), 512^3 and
+// 640^3.
+template <class S, int T, int D, int NW>
+static double tb3_cost_nw(const Geo& g)
+{
+    const Tb3Shape sh = tb3_shape<S, T, D, NW>(g);
+    const int64_t slots = std::max(1, tb3_resident_blocks<S, T, D, NW>());
+    const int64_t blocks = (int64_t)sh.ntx * sh.nty * sh.ntz;
+    const int64_t rounds = (blocks + slots - 1) / slots;
+    constexpr int K = k3_lcm(k3_lcm(D, 2), T);
+    const int64_t steps = (sh.zs + 2 * T + K - 1) / K * K;
+    return (double)rounds * (double)steps * (1.04 + 0.154 * T) / T;
+}
+
+template <class S, int T, int D>
+static double tb3_cost(const Geo& g)
+{
+    return tb3_use15<S, T, D>(g) ? tb3_cost_nw<S, T, D, 15>(g) : tb3_cost_nw<S, T, D, 16>(g);
+}
+
+// Depth 5, 4 or 3, whichever the model gives the lowest time per sweep (ties to the deeper).
+template <class S, int D>
+static int tb3_pick(const Geo& g)
+{
+    int best = 5;
+    double c = tb3_cost<S, 5, D>(g);
+    const double c4 = tb3_cost<S, 4, D>(g), c3 = tb3_cost<S, 3, D>(g);
+    if (c4 < c) {
+        best = 4;
+        c = c4;
+    }
+    if (c3 < c) best = 3;
+    return best;
 }
 
 template <class S, int D>
@@ -270,6 +328,16 @@ static void tb3d_T(const S* in, S* out, const S* b, const Geo& g, const Coefs& c
         tb3d_TD<S, 3>(in, out, b, g, co, T, dir, s);
     else
         tb3d_TD<S, 2>(in, out, b, g, co, T, dir, s);
+}
+
+int fused3d_default_depth(const Geo& g, Fmt f)
+{
+    if (g.ndim != 3) return 0;
+    switch (f) {
+    case FMT_F64: return tb3_pick<double, 3>(g);
+    case FMT_F32: return tb3_pick<float, 2>(g);
+    default: return tb3_pick<bf16_t, 2>(g);
+    }
 }
 
 hipError_t launch_sweep_fused3d(Fmt f, const void* in, void* out, const void* b, const Geo& g,
