@@ -272,8 +272,8 @@ static void tb3d(const S* in, S* out, const S* b, const Geo& g, const Coefs& co,
 // steps one block streams (its z run plus 2T, rounded up to the unrolled loop's K steps) x a
 // per-step cost a + b T, over the T sweeps a launch advances.  a = 1.04 and b = 0.154 (us)
 // were fitted to the binary64 launches at 512^3 (4 and 5 sweeps); the model then picks the
-// measured fastest depth at 256^3, 384^3 (where 5 leaves 112 compute units idle), 512^3 and
-// 640^3.
+// measured fastest depth at 256^3, 384^3 (where 5 gives 160 blocks for 256 compute units),
+// 512^3 and 640^3.
 template <class S, int T, int D, int NW>
 static double tb3_cost_nw(const Geo& g)
 {
