@@ -125,8 +125,8 @@ typedef struct {
     int32_t resident;              /* 1: srj_solve runs in one workgroup with the grid in LDS */
     int32_t store_nt;              /* 1: the register-streamed fused 2D binary64 launches
                                       (equal spacings, Dirichlet) store with the non-temporal
-                                      cache hint: grids whose input, output and b fields fit in
-                                      twice the 256 MiB memory-side cache */
+                                      cache hint: grids whose input, output and b fields
+                                      exceed the 256 MiB memory-side cache but fit in twice it */
 } srj_plan_desc;
 
 typedef struct {

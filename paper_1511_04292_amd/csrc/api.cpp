@@ -590,11 +590,16 @@ srj_status create_plan(const srj_grid* grid, const srj_schedule* schedule, void*
     // Dirichlet operator only); in 3D these plans sweep once per launch
     p->ldsfuse = (!p->iso || g.bc != 0 || g.op) && lds_fuse_fits(g, p->fmt);
     if (p->ldsfuse) p->fuse = lds_fuse_max();
-    // Fused 2D binary64 launches store with the non-temporal hint while the three fields they
-    // touch (input, output, b) fit in twice the 256 MiB memory-side cache: measured faster up
-    // to 4096^2, slower from 8192^2 on (the 3D kernel always takes it, the other formats never)
-    p->store_nt = p->fmt == FMT_F64 && g.ndim == 2 && p->iso && g.bc == 0 && !g.op &&
-                  3.0 * (double)p->field_elems * sizeof(double) <= 2.0 * 256.0 * 1024.0 * 1024.0;
+    // Fused 2D binary64 launches store with the non-temporal hint when the three fields they
+    // touch (input, output, b) exceed the 256 MiB memory-side cache but fit in twice it: at
+    // 4096^2 faster at every depth (2% at 10 sweeps per launch, 5% at one); at 2048^2, inside
+    // the cache, as fast at 10 and 37% slower at one; from 8192^2 on slower (2-3% at 10).  The
+    // 3D kernel always takes the hint, the other formats never.
+    {
+        const double ws = 3.0 * (double)p->field_elems * sizeof(double), mall = 256.0 * 1024.0 * 1024.0;
+        p->store_nt = p->fmt == FMT_F64 && g.ndim == 2 && p->iso && g.bc == 0 && !g.op && ws > mall &&
+                      ws <= 2.0 * mall;
+    }
     // small binary64 2D grids: srj_solve keeps the grid in one compute unit's LDS
     if (p->fmt == FMT_F64 && small_solve_fits(g)) {
         if (hipMalloc(&p->cseq_d, sizeof(double) * (size_t)p->M) != hipSuccess ||

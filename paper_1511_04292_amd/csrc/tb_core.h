@@ -53,9 +53,9 @@ constexpr int kTbMasked = 0x40000000;  // offset added for a masked row; the rec
 // HINT is the stores' cache-policy operand: 0 (plain) or kTbStoreNt (the non-temporal bit).
 // Which launches take the hint was measured, alternating builds on one machine: the fused
 // binary64 3D sweep always (512^3 at 4 sweeps: 921 against 944 us), the fused binary64 2D
-// sweep while its three fields fit in about twice the memory-side cache (4096^2 at 10 sweeps:
-// 87.3 against 89.2 us; 8192^2 to 32768^2 were 2-3% slower with it, one sweep per launch
-// 18-37% slower); the 4- and 2-byte formats never (3-6% slower).
+// sweep when its three fields exceed the memory-side cache but fit in twice it (4096^2 at 10
+// sweeps: 87.3 against 89.2 us; 2048^2, inside the cache, was 37% slower at one sweep per
+// launch, 8192^2 to 32768^2 2-3% slower at ten); the 4- and 2-byte formats never (3-6% slower).
 constexpr int kTbStoreNt = 2;
 
 template <int HINT = 0>

@@ -8,8 +8,8 @@ on the schedules the product planner builds for the benchmark.  The full 4096^2 
 binary64 solves must stop at the cycle the exact DST-mode trajectory predicts, with the
 relres it predicts; the 512^3 results of all three precisions are compared with the exact
 discrete solution.  At 32768^2 (the throughput point) sampled regions of a window are
-compared with the oracle run on crops around them.  A 4800 x 4700 window covers the fused 2D
-binary64 kernel in the form that large grids run (plain stores) at every depth.
+compared with the oracle run on crops around them.  Windows at 4800 x 4700 and 3500 x 3400
+cover the fused 2D binary64 kernel in both store forms at every depth.
 """
 import numpy as np
 import pytest
@@ -55,12 +55,13 @@ def test_blobs_4096_window_bitwise(blobs):
         assert np.array_equal(u.cpu().numpy(), ref), (k0, n)
 
 
-def test_plain_store_variant_every_depth_bitwise():
-    """The fused binary64 2D kernel in its plain-store form (grids whose input, output and b
-    fields exceed twice the memory-side cache take no non-temporal hint), at every depth 1..10,
-    against the oracle on a 4800 x 4700 grid: 23 sweeps from 7 before a cycle end."""
-    n = (4800, 4700)
-    h = 1.0 / 4801
+@pytest.mark.parametrize("n,hint", [((4800, 4700), 0), ((3500, 3400), 1)])
+def test_store_variants_every_depth_bitwise(n, hint):
+    """The fused binary64 2D kernel in both store forms, at every depth 1..10, against the
+    oracle: 23 sweeps from 7 before a cycle end.  4800 x 4700 (input, output and b beyond twice
+    the memory-side cache) stores plainly, 3500 x 3400 (between once and twice) with the
+    non-temporal hint."""
+    h = 1.0 / (n[0] + 1)
     rng = np.random.default_rng(21)
     full = (n[1] + 2, n[0] + 2)
     u0 = rng.uniform(-1.0, 1.0, full)
@@ -68,7 +69,7 @@ def test_plain_store_variant_every_depth_bitwise():
     w, q, seq = oracle_schedule(4, n)
     M = int(np.sum(q))
     plan = srj.srj_plan(n, h, omega=w, q=q, sequence=seq)
-    assert srj.srj_plan_describe(plan)["store_nt"] == 0
+    assert srj.srj_plan_describe(plan)["store_nt"] == hint
     k0, nsw = M - 7, 23
     ref = sweeps.run(u0, sweeps.rhs(f, h), sweeps.coefficients(np.asarray(w)[seq], 2), nsw, k0=k0)
     fd = torch.from_numpy(f).to(DEV)

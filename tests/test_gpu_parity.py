@@ -477,12 +477,14 @@ def test_errors():
 
 
 def test_store_hint_follows_the_working_set():
-    """Fused 2D binary64 plans store with the non-temporal hint while input, output and b fit
-    in twice the 256 MiB memory-side cache (4096^2 yes, 8192^2 no); the flag is reported for
-    2D binary64 plans only (3D binary64 always takes the hint, the other formats never)."""
+    """Fused 2D binary64 plans store with the non-temporal hint when input, output and b exceed
+    the 256 MiB memory-side cache but fit in twice it (4096^2 yes; 2048^2 and 8192^2 no); the
+    flag is reported for 2D binary64 plans only (3D binary64 always takes the hint, the other
+    formats never)."""
     assert srj.srj_plan_describe(srj.srj_plan((4096, 4096), 1.0 / 4097, omega=[1.0], q=[1]))["store_nt"] == 1
     assert srj.srj_plan_describe(srj.srj_plan((8192, 8192), 1.0 / 8193, omega=[1.0], q=[1]))["store_nt"] == 0
-    assert srj.srj_plan_describe(srj.srj_plan((64, 48), 1.0 / 65, omega=[1.0], q=[1]))["store_nt"] == 1
+    assert srj.srj_plan_describe(srj.srj_plan((2048, 2048), 1.0 / 2049, omega=[1.0], q=[1]))["store_nt"] == 0
+    assert srj.srj_plan_describe(srj.srj_plan((64, 48), 1.0 / 65, omega=[1.0], q=[1]))["store_nt"] == 0
     assert srj.srj_plan_describe(srj.srj_plan((4096, 4096), 1.0 / 4097, omega=[1.0], q=[1],
                                               dtype="f32"))["store_nt"] == 0
     assert srj.srj_plan_describe(srj.srj_plan((64, 64, 64), 1.0 / 65, omega=[1.0], q=[1]))["store_nt"] == 0
