@@ -155,7 +155,9 @@ srj_status srj_plan_sequence(srj_plan_t plan, int32_t* seq, int64_t cap);
  * are solved by srj_solve in one launch of one workgroup holding the grid in LDS (resident = 1
  * in srj_plan_desc); srj_plan_set_fusion turns that off.
  * Override the number of sweeps fused per launch (0 = unfused reference kernel; at most
- * 10 in 2D, 5 in 3D; the default is the largest, except 4 for binary64 in 3D; 2D binary64
+ * 10 in 2D, 5 in 3D; the default is 10 in 2D and, in 3D, 5, 4 or 3, whichever a model of the
+ * launch shape (blocks against compute units, steps per block) gives the lowest time per
+ * sweep; 2D binary64
  * plans with unequal spacings, Neumann boundaries or an operator fuse at most 8, on tiles held
  * in LDS, 8 by default; in 3D, and in binary32 / bfloat16, such plans sweep once per launch)
  * and the output rows each wave of the fused 2D kernel computes (seg_rows = 0, the
